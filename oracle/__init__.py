@@ -1,0 +1,36 @@
+"""Plain FP64 CPU oracle for the Q^k spectral-element fast-diagonalisation solver.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  It shares no code with
+the GPU library and never imports it.
+
+Every function follows the paper (Liu, Shen & Zhang, "A simple GPU
+implementation of spectral-element methods for solving 3D Poisson type
+equations on rectangular domains and its applications", arXiv 2310.00226) and
+cites the section / equation it restates.  All arithmetic is float64; numpy's
+matmul and symmetric eigensolver serve as library primitives.
+
+Parity status of each function (what pins it is in tests/test_oracle_*.py):
+  gll, diff_matrix, element_matrices, axis_operators, axis_eigen   pinned
+  fd_solve, apply_h3, residual, residual_at, dense_system          pinned
+  ch_step                                                          pinned
+"""
+from .sem_oracle import (  # noqa: F401
+    gll,
+    legendre,
+    diff_matrix,
+    element_matrices,
+    axis_operators,
+    axis_eigen,
+    Problem,
+    fd_solve,
+    mode_product,
+    apply_h3,
+    residual,
+    residual_at,
+    dense_system,
+    dense_solve,
+    ch_step,
+    ch_operator_residual,
+    rel_max_err,
+)

@@ -1,0 +1,330 @@
+"""Plain FP64 oracle: test infrastructure only (see oracle/__init__.py).
+
+Paper: Liu, Shen & Zhang, arXiv 2310.00226.  Section numbers below refer to it.
+
+Conventions.  A 3D nodal array is a C-ordered numpy array of shape
+(nx, ny, nz); entry [i, j, l] is the value at node (x_i, y_j, z_l).  The paper
+stores the same array column-major (x fastest); only the storage order differs,
+the mathematics is unchanged.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# 1D reference element: Gauss-Lobatto-Legendre points, weights, derivative
+# ---------------------------------------------------------------------------
+
+
+def legendre(k: int, x):
+    """(P_k(x), P_{k-1}(x)) by the three-term Legendre recurrence."""
+    x = np.asarray(x, dtype=np.float64)
+    p_prev = np.ones_like(x)
+    if k == 0:
+        return p_prev, np.zeros_like(x)
+    p = x.copy()
+    for n in range(1, k):
+        p_prev, p = p, ((2 * n + 1) * x * p - n * p_prev) / (n + 1)
+    return p, p_prev
+
+
+def gll(k: int):
+    """(k+1)-point Gauss-Lobatto-Legendre nodes (ascending) and weights on [-1, 1].
+
+    Sec. 2.1: the Q^k basis is the Lagrange basis at these points and all
+    integrals use this quadrature.  Interior nodes are the roots of P_k'; they
+    are found by Newton's method from the Chebyshev-Lobatto points, using
+    P_k'' from Legendre's differential equation.  Weights: 2 / (k(k+1) P_k(x)^2).
+    """
+    if k < 1:
+        raise ValueError("k >= 1")
+    x = -np.cos(np.pi * np.arange(k + 1) / k)
+    x[0], x[-1] = -1.0, 1.0
+    xi = x[1:-1].copy()
+    for _ in range(100):
+        p, pm1 = legendre(k, xi)
+        dp = k * (xi * p - pm1) / (xi * xi - 1.0)
+        d2p = (2.0 * xi * dp - k * (k + 1) * p) / (1.0 - xi * xi)
+        step = dp / d2p
+        xi -= step
+        if np.all(np.abs(step) <= 1e-16 * np.maximum(1.0, np.abs(xi))):
+            break
+    x[1:-1] = xi
+    # symmetry of the rule: average the two halves to remove rounding asymmetry
+    x = 0.5 * (x - x[::-1])
+    p, _ = legendre(k, x)
+    w = 2.0 / (k * (k + 1) * p * p)
+    return x, w
+
+
+def diff_matrix(x):
+    """D[i, j] = l_j'(x_i) for the Lagrange basis at nodes x (Appendix LegendreD).
+
+    Off-diagonal: (w_i / w_j) / (x_i - x_j) with w_i = prod_{m != i}(x_i - x_m);
+    diagonal: sum_{m != i} 1 / (x_i - x_m)  (the derivative of l_i at x_i).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    n = x.size
+    diff = x[:, None] - x[None, :]
+    np.fill_diagonal(diff, 1.0)
+    omega = np.prod(diff, axis=1)
+    d = (omega[:, None] / omega[None, :]) / diff
+    inv = 1.0 / diff
+    np.fill_diagonal(inv, 0.0)
+    d[np.arange(n), np.arange(n)] = inv.sum(axis=1)
+    return d
+
+
+def element_matrices(k: int):
+    """Reference-element stiffness K_ref = D^T W D and lumped mass diag(w).
+
+    Sec. 2.1: stiffness entries are <phi_i', phi_j'> and mass entries
+    <phi_i, phi_j> under GLL quadrature; the mass is diagonal because the basis
+    interpolates at the quadrature points (Appendix SEGenerator1D).
+    """
+    x, w = gll(k)
+    d = diff_matrix(x)
+    k_ref = d.T @ (w[:, None] * d)
+    return x, w, k_ref
+
+
+# ---------------------------------------------------------------------------
+# 1D global operators on one axis
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class AxisOps:
+    k: int
+    ne: int
+    a: float
+    b: float
+    bc: str          # "dirichlet" | "neumann" (homogeneous)
+    x: np.ndarray    # node coordinates of the unknowns
+    K: np.ndarray    # dense stiffness, n x n
+    M: np.ndarray    # lumped mass (diagonal), length n
+    h: float         # half element width
+
+
+def axis_operators(k: int, ne: int, a: float, b: float, bc: str) -> AxisOps:
+    """Assemble the 1D stiffness K and lumped mass M on [a, b] with ne elements.
+
+    Appendix SEGenerator1D: ne uniform elements of width 2h, h = (b - a)/(2 ne);
+    neighbouring elements share their end node, giving ne*k + 1 nodes; element
+    matrices are K_ref / h and h * diag(w).  Homogeneous Neumann keeps every
+    node (natural condition).  Homogeneous Dirichlet removes the two boundary
+    nodes, leaving ne*k - 1 unknowns (the DoF counts of Table 1).
+    """
+    if bc not in ("dirichlet", "neumann"):
+        raise ValueError(bc)
+    xr, w, k_ref = element_matrices(k)
+    h = (b - a) / (2.0 * ne)
+    nfull = ne * k + 1
+    kfull = np.zeros((nfull, nfull))
+    mfull = np.zeros(nfull)
+    xfull = np.zeros(nfull)
+    for e in range(ne):
+        s = e * k
+        kfull[s:s + k + 1, s:s + k + 1] += k_ref / h
+        mfull[s:s + k + 1] += h * w
+        xfull[s:s + k + 1] = a + h * (2 * e + 1 + xr)
+    xfull[0], xfull[-1] = a, b
+    if bc == "dirichlet":
+        sl = slice(1, nfull - 1)
+        return AxisOps(k, ne, a, b, bc, xfull[sl].copy(), kfull[sl, sl].copy(), mfull[sl].copy(), h)
+    return AxisOps(k, ne, a, b, bc, xfull, kfull, mfull, h)
+
+
+def axis_eigen(ops: AxisOps):
+    """Generalised eigenpairs K s = lambda M s, ascending, M-orthonormal.
+
+    Sec. 2.3: with M diagonal, form the symmetric S1 = M^{-1/2} K M^{-1/2},
+    symmetrise it, take S1 = Q Lambda Q^T, and set T = M^{-1/2} Q (here S);
+    its inverse is Q^T M^{1/2} = S^T M (here the forward factor F).
+    Returns (lam, S, F).
+    """
+    mh = np.sqrt(ops.M)
+    s1 = ops.K / (mh[:, None] * mh[None, :])
+    s1 = 0.5 * (s1 + s1.T)
+    lam, q = np.linalg.eigh(s1)
+    order = np.argsort(lam, kind="stable")
+    lam, q = lam[order], q[:, order]
+    s = q / mh[:, None]
+    f = (q * mh[:, None]).T
+    return lam, s, f
+
+
+# ---------------------------------------------------------------------------
+# 3D problem
+# ---------------------------------------------------------------------------
+
+
+class Problem:
+    """-Lap u + alpha u = f on a box with homogeneous Dirichlet or Neumann BCs,
+    Q^k SEM with ne[a] elements on axis a (Sec. 2, eq. pde / matvec3D)."""
+
+    def __init__(self, k: int, ne, box, alpha: float, bc: str):
+        self.k = int(k)
+        self.ne = tuple(int(v) for v in ne)
+        self.box = tuple(float(v) for v in box)
+        self.alpha = float(alpha)
+        self.bc = bc
+        self.axes = [axis_operators(self.k, self.ne[a], self.box[2 * a], self.box[2 * a + 1], bc)
+                     for a in range(3)]
+        self.eig = [axis_eigen(o) for o in self.axes]
+
+    @property
+    def shape(self):
+        return tuple(o.x.size for o in self.axes)
+
+    def lam3(self):
+        lx, ly, lz = (e[0] for e in self.eig)
+        return lx[:, None, None] + ly[None, :, None] + lz[None, None, :]
+
+    def mass3(self):
+        mx, my, mz = (o.M for o in self.axes)
+        return mx[:, None, None] * my[None, :, None] * mz[None, None, :]
+
+    def h_dense(self, a: int):
+        o = self.axes[a]
+        return o.K / o.M[:, None]
+
+
+def mode_product(x, mat, axis: int, out=None):
+    """Y = x contracted with mat along `axis`: Y[.., l, ..] = sum_m mat[l, m] x[.., m, ..].
+
+    Sec. 2.4 (eq. tensorprod and its three-statement listing): one mode product
+    per axis, each a plain matrix product.
+    """
+    nx, ny, nz = x.shape
+    if axis == 2:
+        return np.matmul(x, mat.T, out=out)
+    if axis == 1:
+        return np.matmul(mat, x, out=out)
+    if axis == 0:
+        res = np.matmul(mat, x.reshape(nx, ny * nz),
+                        out=None if out is None else out.reshape(nx, ny * nz))
+        return res.reshape(nx, ny, nz)
+    raise ValueError(axis)
+
+
+def fd_solve(prob: Problem, f: np.ndarray) -> np.ndarray:
+    """Fast-diagonalisation solve of eq. (3D-Poisson) with the alpha shift.
+
+    u = (S_x (x) S_y (x) S_z) [ (F_x (x) F_y (x) F_z) f ] ./ (Lambda3D + alpha),
+    F = S^T M.  Mode products in the paper's order: z, y, x forward, then the
+    entrywise divide (Appendix Poisson3D adds alpha), then z, y, x backward.
+    """
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    (lx, sx, fx), (ly, sy, fy), (lz, sz, fz) = prob.eig
+    buf1 = np.empty_like(f)
+    buf2 = np.empty_like(f)
+    mode_product(f, fz, 2, out=buf1)
+    mode_product(buf1, fy, 1, out=buf2)
+    mode_product(buf2, fx, 0, out=buf1)
+    buf1 /= (lx[:, None, None] + ly[None, :, None] + lz[None, None, :] + prob.alpha)
+    mode_product(buf1, sz, 2, out=buf2)
+    mode_product(buf2, sy, 1, out=buf1)
+    mode_product(buf1, sx, 0, out=buf2)
+    return buf2
+
+
+def apply_h3(prob: Problem, u: np.ndarray) -> np.ndarray:
+    """(H_x (+) H_y (+) H_z) u with H = M^{-1} K per axis (eq. matvec3D, H-form)."""
+    out = mode_product(u, prob.h_dense(2), 2)
+    out += mode_product(u, prob.h_dense(1), 1)
+    out += mode_product(u, prob.h_dense(0), 0)
+    return out
+
+
+def residual(prob: Problem, u: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """Nodal residual r = f - (alpha I + H_3) u, i.e. M_3^{-1}(M_3 f - A u)."""
+    return f - prob.alpha * u - apply_h3(prob, u)
+
+
+def residual_at(prob: Problem, u: np.ndarray, f: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """The nodal residual at the points idx (an (m, 3) integer array), each
+    evaluated from the rows of H_x, H_y, H_z through that point."""
+    idx = np.asarray(idx, dtype=np.int64)
+    hx, hy, hz = (prob.h_dense(a) for a in range(3))
+    out = np.empty(idx.shape[0])
+    for t, (i, j, l) in enumerate(idx):
+        s = prob.alpha * u[i, j, l]
+        s += hx[i, :] @ u[:, j, l]
+        s += hy[j, :] @ u[i, :, l]
+        s += hz[l, :] @ u[i, j, :]
+        out[t] = f[i, j, l] - s
+    return out
+
+
+def dense_system(prob: Problem):
+    """Assembled dense A = K(x)M(x)M + M(x)K(x)M + M(x)M(x)K + alpha M(x)M(x)M and
+    the diagonal of M(x)M(x)M, in the C (x-slowest) ordering (eq. matvec3D)."""
+    kx, ky, kz = (o.K for o in prob.axes)
+    mx, my, mz = (np.diag(o.M) for o in prob.axes)
+    a = (np.kron(np.kron(kx, my), mz) + np.kron(np.kron(mx, ky), mz)
+         + np.kron(np.kron(mx, my), kz) + prob.alpha * np.kron(np.kron(mx, my), mz))
+    m3 = np.kron(np.kron(prob.axes[0].M, prob.axes[1].M), prob.axes[2].M)
+    return a, m3
+
+
+def dense_solve(prob: Problem, f: np.ndarray) -> np.ndarray:
+    """Brute force: solve A u = M_3 f by LU with partial pivoting."""
+    a, m3 = dense_system(prob)
+    u = np.linalg.solve(a, m3 * f.reshape(-1))
+    return u.reshape(prob.shape)
+
+
+# ---------------------------------------------------------------------------
+# Cahn-Hilliard BDF2 / IMEX step (Sec. 3.5)
+# ---------------------------------------------------------------------------
+
+
+def ch_step(prob: Problem, phi_n, phi_nm1, eps: float, mob: float, dt: float):
+    """One step of eq. (chscheme-2): phi_{n+1} = D phi_hat + (m dt/eps) D Lap F'(phi_bar).
+
+    a = 3/2, phi_hat = 2 phi_n - phi_{n-1}/2, phi_bar = 2 phi_n - phi_{n-1},
+    F'(phi) = phi^3 - phi (F = (phi^2 - 1)^2 / 4), D = (a I + m dt eps Lap^2)^{-1}.
+    The discrete Laplacian is -H_3, so in the eigenbasis Lap -> -Lambda3D:
+    phi_{n+1} = S_3 [ (F_3 phi_hat - (m dt/eps) Lambda3D F_3 g) / (a + m dt eps Lambda3D^2) ].
+    (prob.alpha is not used.)
+    """
+    a = 1.5
+    phi_hat = 2.0 * phi_n - 0.5 * phi_nm1
+    phi_bar = 2.0 * phi_n - phi_nm1
+    g = phi_bar ** 3 - phi_bar
+    (lx, sx, fx), (ly, sy, fy), (lz, sz, fz) = prob.eig
+    lam = prob.lam3()
+
+    def fwd(v):
+        return mode_product(mode_product(mode_product(v, fz, 2), fy, 1), fx, 0)
+
+    def bwd(v):
+        return mode_product(mode_product(mode_product(v, sz, 2), sy, 1), sx, 0)
+
+    c = (fwd(phi_hat) - (mob * dt / eps) * lam * fwd(g)) / (a + mob * dt * eps * lam * lam)
+    return bwd(c)
+
+
+def ch_operator_residual(prob: Problem, phi_np1, phi_n, phi_nm1, eps, mob, dt):
+    """Residual of (a I + m dt eps H_3^2) phi_{n+1} = phi_hat - (m dt/eps) H_3 g,
+    evaluated with the assembled H (independent of the eigen path)."""
+    a = 1.5
+    phi_hat = 2.0 * phi_n - 0.5 * phi_nm1
+    phi_bar = 2.0 * phi_n - phi_nm1
+    g = phi_bar ** 3 - phi_bar
+    lhs = a * phi_np1 + mob * dt * eps * apply_h3(prob, apply_h3(prob, phi_np1))
+    rhs = phi_hat - (mob * dt / eps) * apply_h3(prob, g)
+    return lhs - rhs
+
+
+def rel_max_err(a, b) -> float:
+    """||a - b||_inf / ||b||_inf."""
+    b = np.asarray(b)
+    return float(np.max(np.abs(np.asarray(a) - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+__all__ = [n for n in dir() if not n.startswith("_") and n not in ("math", "np", "dataclass", "annotations")]
