@@ -1,0 +1,121 @@
+/*
+ * sem.h -- C ABI of the MI355X (gfx950) fast-diagonalisation solver for Q^k
+ * spectral-element discretisations of  -Lap u + alpha u = f  on a 3D box.
+ *
+ * Method: Liu, Shen & Zhang, "A simple GPU implementation of spectral-element
+ * methods for solving 3D Poisson type equations on rectangular domains and its
+ * applications", arXiv 2310.00226.
+ *   - discretisation: Sec. 2.1 (eq. fem): continuous Q^k Lagrange basis on the
+ *     (k+1)-point Gauss-Lobatto nodes of each element, all integrals by that
+ *     quadrature, hence a diagonal (lumped) mass matrix;
+ *   - linear system: Sec. 2.4, eq. matvec3D,
+ *       (K(x)M(x)M + M(x)K(x)M + M(x)M(x)K + alpha M(x)M(x)M) u = (M(x)M(x)M) f;
+ *   - solver: Sec. 2.2-2.4, eq. 3D-Poisson with the robust eigen-solve of
+ *     Sec. 2.3:  u = (S_x(x)S_y(x)S_z) diag(1/(lx_i+ly_j+lz_l+alpha)) (S_x(x)S_y(x)S_z)^T M_3 f,
+ *     K S = M S Lambda, S^T M S = I per axis.
+ *
+ * Layout of every 3D array: row-major (n_x, n_y, n_z), z fastest, i.e. entry
+ * u[(i*n_y + j)*n_z + l] is the value at node (x_i, y_j, z_l).  (The paper stores
+ * the same array column-major; only the storage order differs.)  Values are
+ * nodal; with Dirichlet conditions only interior nodes are unknowns
+ * (n_a = ne_a*k - 1), with Neumann all nodes are (n_a = ne_a*k + 1).
+ *
+ * Memory: array arguments named f, u, r, phi are DEVICE pointers owned by the
+ * caller, float64, at least 8-byte aligned, on the device the plan was created
+ * on.  Calls are asynchronous on the plan's stream (default: the null stream)
+ * unless stated otherwise; a plan is not thread-safe (use one plan per stream).
+ *
+ * Errors: every call returns a sem_status and never aborts.  sem_last_error()
+ * returns a description of the last failure on the calling thread.  A device
+ * fault raised by earlier asynchronous work is reported as SEM_EDEVICE by the
+ * next call that synchronises.
+ */
+#ifndef SEM_H_
+#define SEM_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_plan sem_plan;
+
+typedef enum { SEM_BC_DIRICHLET = 0, SEM_BC_NEUMANN = 1 } sem_bc; /* homogeneous (Sec. 2.1 remark) */
+
+/* Arithmetic of the mode products.  The residual, the solution update and the
+ * 1D eigen-decompositions are always FP64. */
+typedef enum {
+  SEM_F64 = 0,   /* FP64 MFMA, FP64 intermediates */
+  SEM_F32 = 1,   /* FP32 MFMA, FP32 intermediates */
+  SEM_BF16 = 2,  /* BF16 MFMA with FP32 accumulation, BF16 intermediates */
+  SEM_BF16X3 = 3 /* split BF16 (hi + lo) operands, three BF16 MFMAs, FP32 accumulation */
+} sem_prec;
+
+typedef enum {
+  SEM_OK = 0,
+  SEM_EINVAL = 1,      /* invalid argument */
+  SEM_ENOMEM = 2,      /* device or host allocation failed */
+  SEM_EDEVICE = 3,     /* HIP runtime error or device fault */
+  SEM_ESINGULAR = 4,   /* the operator has a zero eigenvalue (Neumann with alpha = 0) */
+  SEM_ENOCONV = 5,     /* iterative refinement stopped without meeting the tolerance */
+  SEM_ENONFINITE = 6   /* a residual or update became NaN / Inf */
+} sem_status;
+
+/* ---- plan ----------------------------------------------------------------- */
+
+/* Build the 1D operators of each axis (Appendix SEGenerator1D: ne[a] uniform
+ * elements on [box[2a], box[2a+1]], GLL rule of degree k), their generalised
+ * eigen-decompositions in FP64 on the host (Sec. 2.3), and upload the factors to
+ * the current HIP device.  k >= 1, ne[a] >= 1, box[2a] < box[2a+1], alpha >= 0.
+ * Returns SEM_ESINGULAR when alpha + min eigenvalue sum is 0 (Neumann, alpha = 0).
+ * Synchronous.  The plan owns its factor storage (a few MB) until destroyed. */
+sem_status sem_plan_create(int k, const int ne[3], const double box[6], double alpha, sem_bc bc, sem_plan **out);
+void sem_plan_destroy(sem_plan *p);
+
+/* n[a] = number of unknowns per axis. */
+sem_status sem_plan_dims(const sem_plan *p, int n[3]);
+/* Host copy of the n[axis] node coordinates / eigenvalues (ascending) of one axis. */
+sem_status sem_plan_nodes(const sem_plan *p, int axis, double *x_host);
+sem_status sem_plan_eigenvalues(const sem_plan *p, int axis, double *lam_host);
+/* Run subsequent calls on this hipStream_t (NULL = the null stream). */
+sem_status sem_plan_set_stream(sem_plan *p, void *hip_stream);
+
+/* Scratch memory needed by sem_solve / sem_solve_refined at precision prec.
+ * The caller may provide it (sem_plan_set_workspace, device memory that stays
+ * valid while the plan uses it); otherwise the plan allocates it on first use. */
+sem_status sem_plan_workspace_bytes(const sem_plan *p, sem_prec prec, size_t *bytes);
+sem_status sem_plan_set_workspace(sem_plan *p, void *dev_ptr, size_t bytes);
+
+/* ---- solve ---------------------------------------------------------------- */
+
+/* FP64 fast-diagonalisation solve (eq. 3D-Poisson): u = A^{-1} M_3 f.
+ * Forward mode products along z, y, x with F_a = S_a^T M_a, the divide by
+ * lx_i + ly_j + lz_l + alpha fused into the x-axis product, backward products
+ * with S_a.  f and u are device arrays of n_x n_y n_z doubles; u may alias f. */
+sem_status sem_solve(sem_plan *p, const double *f, double *u);
+
+/* One FP64 mode product along `axis` (0 = x, 1 = y, 2 = z) with the forward
+ * factor F_a (inverse = 0) or the backward factor S_a (inverse = 1):
+ * out[.., l, ..] = sum_m A[l][m] in[.., m, ..].  in and out must not alias. */
+sem_status sem_mode_product(sem_plan *p, int axis, int inverse, const double *in, double *out);
+
+/* Nodal residual r = f - M_3^{-1} A u = f - alpha u - (H_x + H_y + H_z) u with
+ * H = M^{-1} K (eq. matvec3D in H-form), FP64, matrix-free.  r must not alias u. */
+sem_status sem_residual(sem_plan *p, const double *u, const double *f, double *r);
+
+/* Host-only helper (no device needed): the 1D operators of one axis as built by
+ * sem_plan_create.  Call with all output pointers NULL to get n; then pass
+ * buffers of n (x, mass, lam) and n*n (S, F, row-major) doubles; any output may
+ * be NULL.  S: backward factor (K S = M S Lambda, S^T M S = I); F = S^T M. */
+sem_status sem_axis_host(int k, int ne, double a, double b, sem_bc bc, int *n, double *x, double *mass, double *lam,
+                         double *S, double *F);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *sem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEM_H_ */

@@ -132,19 +132,32 @@ def axis_operators(k: int, ne: int, a: float, b: float, bc: str) -> AxisOps:
         mfull[s:s + k + 1] += h * w
         xfull[s:s + k + 1] = a + h * (2 * e + 1 + xr)
     xfull[0], xfull[-1] = a, b
+    # <grad 1, grad v> = 0: make every row of the (Neumann) stiffness sum to zero up to one
+    # rounding, as LegendreD does for D, before the Dirichlet restriction
+    offd = kfull - np.diag(np.diag(kfull))
+    np.fill_diagonal(kfull, -offd.sum(axis=1))
     if bc == "dirichlet":
         sl = slice(1, nfull - 1)
         return AxisOps(k, ne, a, b, bc, xfull[sl].copy(), kfull[sl, sl].copy(), mfull[sl].copy(), h)
     return AxisOps(k, ne, a, b, bc, xfull, kfull, mfull, h)
 
 
-def axis_eigen(ops: AxisOps):
+def axis_eigen(ops: AxisOps, refine: bool = True):
     """Generalised eigenpairs K s = lambda M s, ascending, M-orthonormal.
 
     Sec. 2.3: with M diagonal, form the symmetric S1 = M^{-1/2} K M^{-1/2},
     symmetrise it, take S1 = Q Lambda Q^T, and set T = M^{-1/2} Q (here S);
     its inverse is Q^T M^{1/2} = S^T M (here the forward factor F).
     Returns (lam, S, F).
+
+    The paper leaves the accuracy of the eigenpairs to the library routine.  An
+    FP64 dense eigensolver leaves absolute eigenvalue errors ~ eps * lambda_max,
+    which the divide of eq. 3D-Poisson turns into relative errors of the lowest
+    (dominant) solution modes of ~ eps * cond (~1e-11 at n ~ 1000).  With
+    `refine`, one extended-precision Newton step (Ogita & Aishima 2018, in
+    oracle/eigref.c) brings the pairs to FP64 rounding; it forms K X in long
+    double from the element matrices, since FP64 rounding of K's entries alone
+    shifts the lowest eigenvalues by ~ eps * lambda_max.
     """
     mh = np.sqrt(ops.M)
     s1 = ops.K / (mh[:, None] * mh[None, :])
@@ -153,8 +166,27 @@ def axis_eigen(ops: AxisOps):
     order = np.argsort(lam, kind="stable")
     lam, q = lam[order], q[:, order]
     s = q / mh[:, None]
-    f = (q * mh[:, None]).T
+    if refine and lam.size > 1:
+        from ._native import eig_refine
+        xr, wr = gll(ops.k)
+        lam, s = eig_refine(ops, xr, wr, lam, s)
+        order = np.argsort(lam, kind="stable")
+        lam, s = lam[order], s[:, order]
+    f = (s * ops.M[:, None]).T
     return lam, s, f
+
+
+_EIG_CACHE: dict = {}
+
+
+def _axis_eigen_cached(k, ne, a, b, bc):
+    key = (k, ne, a, b, bc)
+    if key not in _EIG_CACHE:
+        if len(_EIG_CACHE) > 16:
+            _EIG_CACHE.clear()
+        ops = axis_operators(k, ne, a, b, bc)
+        _EIG_CACHE[key] = (ops, axis_eigen(ops))
+    return _EIG_CACHE[key]
 
 
 # ---------------------------------------------------------------------------
@@ -172,9 +204,10 @@ class Problem:
         self.box = tuple(float(v) for v in box)
         self.alpha = float(alpha)
         self.bc = bc
-        self.axes = [axis_operators(self.k, self.ne[a], self.box[2 * a], self.box[2 * a + 1], bc)
-                     for a in range(3)]
-        self.eig = [axis_eigen(o) for o in self.axes]
+        pairs = [_axis_eigen_cached(self.k, self.ne[a], self.box[2 * a], self.box[2 * a + 1], bc)
+                 for a in range(3)]
+        self.axes = [p[0] for p in pairs]
+        self.eig = [p[1] for p in pairs]
 
     @property
     def shape(self):
@@ -211,25 +244,29 @@ def mode_product(x, mat, axis: int, out=None):
     raise ValueError(axis)
 
 
-def fd_solve(prob: Problem, f: np.ndarray) -> np.ndarray:
+def fd_solve(prob: Problem, f: np.ndarray, order=(2, 1, 0)) -> np.ndarray:
     """Fast-diagonalisation solve of eq. (3D-Poisson) with the alpha shift.
 
     u = (S_x (x) S_y (x) S_z) [ (F_x (x) F_y (x) F_z) f ] ./ (Lambda3D + alpha),
-    F = S^T M.  Mode products in the paper's order: z, y, x forward, then the
-    entrywise divide (Appendix Poisson3D adds alpha), then z, y, x backward.
+    F = S^T M.  By default the mode products run in the paper's order: z, y, x
+    forward, then the entrywise divide (Appendix Poisson3D adds alpha), then z, y,
+    x backward.  The Kronecker factors act on different axes and commute, so any
+    `order` gives the same result in exact arithmetic; a second order measures the
+    FP64 rounding floor of the solve itself.
     """
     f = np.ascontiguousarray(f, dtype=np.float64)
-    (lx, sx, fx), (ly, sy, fy), (lz, sz, fz) = prob.eig
+    lams = [e[0] for e in prob.eig]
     buf1 = np.empty_like(f)
     buf2 = np.empty_like(f)
-    mode_product(f, fz, 2, out=buf1)
-    mode_product(buf1, fy, 1, out=buf2)
-    mode_product(buf2, fx, 0, out=buf1)
-    buf1 /= (lx[:, None, None] + ly[None, :, None] + lz[None, None, :] + prob.alpha)
-    mode_product(buf1, sz, 2, out=buf2)
-    mode_product(buf2, sy, 1, out=buf1)
-    mode_product(buf1, sx, 0, out=buf2)
-    return buf2
+    src, dst = f, buf1
+    for a in order:
+        mode_product(src, prob.eig[a][2], a, out=dst)
+        src, dst = dst, (buf2 if dst is buf1 else buf1)
+    src /= (lams[0][:, None, None] + lams[1][None, :, None] + lams[2][None, None, :] + prob.alpha)
+    for a in order:
+        mode_product(src, prob.eig[a][1], a, out=dst)
+        src, dst = dst, (buf2 if dst is buf1 else buf1)
+    return src
 
 
 def apply_h3(prob: Problem, u: np.ndarray) -> np.ndarray:

@@ -1,0 +1,178 @@
+"""ctypes binding of the C ABI in include/sem.h (argument marshalling only).
+
+Every computation runs in the HIP library libsemfd.so; torch provides device
+memory and the current stream.  Importing this module fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libsemfd.so")
+
+SEM_BC_DIRICHLET, SEM_BC_NEUMANN = 0, 1
+SEM_F64, SEM_F32, SEM_BF16, SEM_BF16X3 = 0, 1, 2, 3
+PRECISIONS = {"f64": SEM_F64, "f32": SEM_F32, "bf16": SEM_BF16, "bf16x3": SEM_BF16X3}
+STATUS = {0: "SEM_OK", 1: "SEM_EINVAL", 2: "SEM_ENOMEM", 3: "SEM_EDEVICE", 4: "SEM_ESINGULAR",
+          5: "SEM_ENOCONV", 6: "SEM_ENONFINITE"}
+
+
+class SemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2310_00226_amd.build_lib)")
+    lib = ctypes.CDLL(LIB_PATH)
+    dp = POINTER(c_double)
+    sig = {
+        "sem_plan_create": (c_int, [c_int, POINTER(c_int), dp, c_double, c_int, POINTER(c_void_p)]),
+        "sem_plan_destroy": (None, [c_void_p]),
+        "sem_plan_dims": (c_int, [c_void_p, POINTER(c_int)]),
+        "sem_plan_nodes": (c_int, [c_void_p, c_int, dp]),
+        "sem_plan_eigenvalues": (c_int, [c_void_p, c_int, dp]),
+        "sem_plan_set_stream": (c_int, [c_void_p, c_void_p]),
+        "sem_plan_workspace_bytes": (c_int, [c_void_p, c_int, POINTER(c_size_t)]),
+        "sem_plan_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
+        "sem_solve": (c_int, [c_void_p, c_void_p, c_void_p]),
+        "sem_mode_product": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
+        "sem_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "sem_axis_host": (c_int, [c_int, c_int, c_double, c_double, c_int, POINTER(c_int), dp, dp, dp, dp, dp]),
+        "sem_last_error": (c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def check(status: int) -> None:
+    if status != 0:
+        raise SemError(status, lib.sem_last_error().decode())
+
+
+def _dptr(arr):
+    """ctypes double* for a contiguous float64 numpy array (or None)."""
+    if arr is None:
+        return None
+    return arr.ctypes.data_as(POINTER(c_double))
+
+
+def _dev_ptr(t, name, n=None, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a CUDA/HIP torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+    return c_void_p(t.data_ptr())
+
+
+def axis_host(k: int, ne: int, a: float, b: float, bc: str):
+    """1D operators of one axis as built by the plan (host only): dict of x, mass, lam, S, F."""
+    import numpy as np
+    bcv = SEM_BC_DIRICHLET if bc == "dirichlet" else SEM_BC_NEUMANN
+    n = c_int(0)
+    check(lib.sem_axis_host(k, ne, a, b, bcv, ctypes.byref(n), None, None, None, None, None))
+    n = n.value
+    out = {"x": np.empty(n), "mass": np.empty(n), "lam": np.empty(n), "S": np.empty((n, n)), "F": np.empty((n, n))}
+    check(lib.sem_axis_host(k, ne, a, b, bcv, None, _dptr(out["x"]), _dptr(out["mass"]), _dptr(out["lam"]),
+                            _dptr(out["S"]), _dptr(out["F"])))
+    return out
+
+
+class Plan:
+    """A fast-diagonalisation plan for -Lap u + alpha u = f (sem_plan_create)."""
+
+    def __init__(self, k: int, ne, box, alpha: float, bc: str = "dirichlet", device=None):
+        import torch
+        self._p = c_void_p(None)
+        bcv = {"dirichlet": SEM_BC_DIRICHLET, "neumann": SEM_BC_NEUMANN}[bc]
+        ne_arr = (c_int * 3)(*[int(v) for v in ne])
+        box_arr = (c_double * 6)(*[float(v) for v in box])
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(self.device):
+            check(lib.sem_plan_create(int(k), ne_arr, box_arr, float(alpha), bcv, ctypes.byref(self._p)))
+        self.k, self.ne, self.box, self.alpha, self.bc = int(k), tuple(ne), tuple(box), float(alpha), bc
+        dims = (c_int * 3)()
+        check(lib.sem_plan_dims(self._p, dims))
+        self.shape = tuple(dims)
+        self.numel = self.shape[0] * self.shape[1] * self.shape[2]
+        self._ws = {}
+
+    def __del__(self):
+        p = getattr(self, "_p", None)
+        if p is not None and p.value:
+            lib.sem_plan_destroy(p)
+            self._p = c_void_p(None)
+
+    def close(self):
+        self.__del__()
+
+    def nodes(self, axis: int):
+        import numpy as np
+        x = np.empty(self.shape[axis])
+        check(lib.sem_plan_nodes(self._p, axis, _dptr(x)))
+        return x
+
+    def eigenvalues(self, axis: int):
+        import numpy as np
+        x = np.empty(self.shape[axis])
+        check(lib.sem_plan_eigenvalues(self._p, axis, _dptr(x)))
+        return x
+
+    def _prepare(self, prec: int):
+        """Bind torch's current stream and a torch-allocated workspace."""
+        import torch
+        check(lib.sem_plan_set_stream(self._p, c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+        need = c_size_t(0)
+        check(lib.sem_plan_workspace_bytes(self._p, prec, ctypes.byref(need)))
+        ws = self._ws.get("buf")
+        if ws is None or ws.numel() < need.value:
+            ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device=self.device)
+            self._ws["buf"] = ws
+            check(lib.sem_plan_set_workspace(self._p, c_void_p(ws.data_ptr()), ws.numel()))
+
+    def solve(self, f, u=None):
+        import torch
+        if u is None:
+            u = torch.empty_like(f)
+        fp = _dev_ptr(f, "f", self.numel, torch.float64)
+        up = _dev_ptr(u, "u", self.numel, torch.float64)
+        self._prepare(SEM_F64)
+        check(lib.sem_solve(self._p, fp, up))
+        return u
+
+    def mode_product(self, axis: int, inverse: bool, x, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(x)
+        xp = _dev_ptr(x, "in", self.numel, torch.float64)
+        op = _dev_ptr(out, "out", self.numel, torch.float64)
+        self._prepare(SEM_F64)
+        check(lib.sem_mode_product(self._p, int(axis), int(bool(inverse)), xp, op))
+        return out
+
+    def residual(self, u, f, r=None):
+        import torch
+        if r is None:
+            r = torch.empty_like(u)
+        a = _dev_ptr(u, "u", self.numel, torch.float64)
+        b = _dev_ptr(f, "f", self.numel, torch.float64)
+        c = _dev_ptr(r, "r", self.numel, torch.float64)
+        self._prepare(SEM_F64)
+        check(lib.sem_residual(self._p, a, b, c))
+        return r

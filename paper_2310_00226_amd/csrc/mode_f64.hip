@@ -1,0 +1,315 @@
+// FP64 mode-product kernels on CDNA4 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// A "mode product" contracts one axis of a 3D nodal array with an n x n factor
+// (paper Sec. 2.4, eq. tensorprod and the three-statement listing; eq.
+// 3D-Poisson applies three of them forward and three backward).  Viewing the
+// row-major tensor as X[p][m][q] (p = outer axes, m = contracted axis of length
+// L, q = inner axes), every pass computes
+//        Y[p][l][q] = sum_m A[l][m] X[p][m][q].
+// The factor is stored by the plan as G[m][l] = A[l][m], zero-padded to a
+// multiple of 128 in both dimensions, so tile loads of G need no bounds checks
+// and padded contraction indices contribute exactly zero.
+//
+// Two tile shapes:
+//   NN (q extent > 1: the x and y axes)  C = G^T-tile x X_p-tile
+//        GEMM rows = l (M = L), cols = q (N = Q), batch = p.
+//   NT (q extent = 1: the contiguous z axis)  C = X-tile x G-tile
+//        GEMM rows = p (M = P), cols = l (N = L).
+//
+// Block = 256 threads = 4 waves in a 2 x 2 arrangement; block tile 128 x 128,
+// each wave 64 x 64 = 4 x 4 MFMA tiles of 16 x 16.  Contraction chunks of 16 are
+// staged through double-buffered LDS.  Epilogues: plain store, the eigenvalue
+// divide of eq. 3D-Poisson (fused into the x-axis forward pass), or accumulate
+// into FP64 (solution update of iterative refinement).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace semfd {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+namespace f64k {
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int NT_THREADS = 256;
+constexpr int LDG = BN + 16;    // [BK][LDG] tiles: rows offset by 16 doubles mod 32 -> no bank clash
+constexpr int LDT = BK + 2;     // [BM][LDT] tensor tile of the NT shape
+constexpr int TILE_G = BK * LDG;
+constexpr int TILE_T_NT = BM * LDT;
+
+// XCD-aware tile numbering: hardware hands consecutive block ids to the 8 XCDs
+// in turn; give each XCD a contiguous run of tiles so that the tiles sharing one
+// tensor strip (which differ only in the fastest tile index) run together and
+// hit the same L2.
+__device__ __forceinline__ long xcd_tile(long nblocks_padded) {
+  const long per = nblocks_padded / 8;
+  return (long)(blockIdx.x % 8) * per + (long)(blockIdx.x / 8);
+}
+
+template <int EPI>
+__device__ __forceinline__ void store_out(double* __restrict__ y, size_t off, double v, int row, long col,
+                                          const EpiArgs& e) {
+  if constexpr (EPI == EPI_STORE) {
+    y[off] = v;
+  } else if constexpr (EPI == EPI_DIVIDE) {
+    const long j = col / e.nz;
+    const long kz = col - j * e.nz;
+    y[off] = v / (e.lx[row] + e.ly[j] + e.lz[kz] + e.alpha);
+  } else {  // EPI_ACCUM
+    y[off] += v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// NN: Y[p][l][q] = sum_m G[m][l] X[p][m][q]
+// ---------------------------------------------------------------------------
+template <int EPI>
+__global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __restrict__ x, double* __restrict__ y,
+                                                             const double* __restrict__ g, int ldg, long P, int L,
+                                                             long Q, long tiles_l, long tiles_q, long ntiles,
+                                                             long nblocks_padded, EpiArgs epi) {
+  __shared__ double lds[2 * (TILE_G + TILE_G)];
+  const long t = xcd_tile(nblocks_padded);
+  if (t >= ntiles) return;
+  const long lt = t % tiles_l;
+  const long rest = t / tiles_l;
+  const long qt = rest % tiles_q;
+  const long p = rest / tiles_q;
+  const int l0 = (int)(lt * BM);
+  const long q0 = qt * BN;
+  const double* __restrict__ xp = x + (size_t)p * L * Q;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64;  // wave row offset within the tile (l)
+  const int wn = (wave & 1) * 64;   // wave col offset within the tile (q)
+
+  // global -> register staging: element e = 0..7 of this thread covers
+  // row kk = tid/64 + 4*(e>>1), col c = tid%64 + 64*(e&1) of a [BK][128] tile.
+  double rg[8], rx[8];
+  const int nchunk = (L + BK - 1) / BK;
+
+  auto load_chunk = [&](int c) {
+    const int m0 = c * BK;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int kk = (tid >> 6) + 4 * (e >> 1);
+      const int cc = (tid & 63) + 64 * (e & 1);
+      rg[e] = g[(size_t)(m0 + kk) * ldg + l0 + cc];
+      const int m = m0 + kk;
+      const long q = q0 + cc;
+      rx[e] = (m < L && q < Q) ? xp[(size_t)m * Q + q] : 0.0;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+    double* sa = lds + buf * (2 * TILE_G);
+    double* sb = sa + TILE_G;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int kk = (tid >> 6) + 4 * (e >> 1);
+      const int cc = (tid & 63) + 64 * (e & 1);
+      sa[kk * LDG + cc] = rg[e];
+      sb[kk * LDG + cc] = rx[e];
+    }
+  };
+
+  d4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = lane >> 4;
+  for (int c = 0; c < nchunk; ++c) {
+    if (c + 1 < nchunk) load_chunk(c + 1);
+    const double* sa = lds + (c & 1) * (2 * TILE_G);
+    const double* sb = sa + TILE_G;
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sa[(ks * 4 + fk) * LDG + wm + 16 * i + fr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = sb[(ks * 4 + fk) * LDG + wn + 16 * j + fr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (c + 1 < nchunk) store_chunk((c + 1) & 1);
+    __syncthreads();
+  }
+
+  // f64 16x16 accumulator layout: lane, register r  ->  row 4r + lane/16, col lane%16
+  double* __restrict__ yp = y + (size_t)p * L * Q;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int l = l0 + wm + 16 * i + 4 * r + fk;
+      if (l >= L) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const long q = q0 + wn + 16 * j + fr;
+        if (q < Q) store_out<EPI>(yp, (size_t)l * Q + q, acc[i][j][r], l, q, epi);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// NT: Y[p][l] = sum_m X[p][m] G[m][l]
+// ---------------------------------------------------------------------------
+template <int EPI>
+__global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __restrict__ x, double* __restrict__ y,
+                                                             const double* __restrict__ g, int ldg, long P, int L,
+                                                             long tiles_l, long ntiles, long nblocks_padded,
+                                                             EpiArgs epi) {
+  __shared__ double lds[2 * (TILE_T_NT + TILE_G)];
+  const long t = xcd_tile(nblocks_padded);
+  if (t >= ntiles) return;
+  const long lt = t % tiles_l;
+  const long pt = t / tiles_l;
+  const int l0 = (int)(lt * BN);
+  const long p0 = pt * BM;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64;  // rows: p
+  const int wn = (wave & 1) * 64;   // cols: l
+
+  double rg[8], rx[8];
+  const int nchunk = (L + BK - 1) / BK;
+  auto load_chunk = [&](int c) {
+    const int m0 = c * BK;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      // factor tile [BK][128]
+      const int kk = (tid >> 6) + 4 * (e >> 1);
+      const int cc = (tid & 63) + 64 * (e & 1);
+      rg[e] = g[(size_t)(m0 + kk) * ldg + l0 + cc];
+      // tensor tile [128][BK]: row r = tid/16 + 16 e, col tid%16
+      const int r = (tid >> 4) + 16 * e;
+      const int m = m0 + (tid & 15);
+      const long pp = p0 + r;
+      rx[e] = (m < L && pp < P) ? x[(size_t)pp * L + m] : 0.0;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+    double* st = lds + buf * (TILE_T_NT + TILE_G);
+    double* sg = st + TILE_T_NT;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int kk = (tid >> 6) + 4 * (e >> 1);
+      const int cc = (tid & 63) + 64 * (e & 1);
+      sg[kk * LDG + cc] = rg[e];
+      const int r = (tid >> 4) + 16 * e;
+      st[r * LDT + (tid & 15)] = rx[e];
+    }
+  };
+
+  d4_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = lane >> 4;
+  for (int c = 0; c < nchunk; ++c) {
+    if (c + 1 < nchunk) load_chunk(c + 1);
+    const double* st = lds + (c & 1) * (TILE_T_NT + TILE_G);
+    const double* sg = st + TILE_T_NT;
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = st[(wm + 16 * i + fr) * LDT + ks * 4 + fk];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = sg[(ks * 4 + fk) * LDG + wn + 16 * j + fr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (c + 1 < nchunk) store_chunk((c + 1) & 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long pp = p0 + wm + 16 * i + 4 * r + fk;
+      if (pp >= P) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int l = l0 + wn + 16 * j + fr;
+        if (l < L) store_out<EPI>(y, (size_t)pp * L + l, acc[i][j][r], l, 0, epi);
+      }
+    }
+}
+
+}  // namespace f64k
+
+// ---------------------------------------------------------------------------
+// Host launcher: one mode product along `axis` of an (n0, n1, n2) array.
+// ---------------------------------------------------------------------------
+hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg, const int dims[3], int axis, int epi,
+                           const EpiArgs& ea, hipStream_t stream) {
+  using namespace f64k;
+  long P = 1, Q = 1;
+  const int L = dims[axis];
+  for (int a = 0; a < axis; ++a) P *= dims[a];
+  for (int a = axis + 1; a < 3; ++a) Q *= dims[a];
+  if (P <= 0 || Q <= 0 || L <= 0) return hipSuccess;
+  if (Q > 1) {
+    const long tiles_l = (L + BM - 1) / BM;
+    const long tiles_q = (Q + BN - 1) / BN;
+    const long ntiles = tiles_l * tiles_q * P;
+    const long nbp = ((ntiles + 7) / 8) * 8;
+    if (nbp > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nbp), block(NT_THREADS);
+    switch (epi) {
+      case EPI_STORE:
+        mode_nn_f64<EPI_STORE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, Q, tiles_l, tiles_q, ntiles, nbp, ea);
+        break;
+      case EPI_DIVIDE:
+        mode_nn_f64<EPI_DIVIDE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, Q, tiles_l, tiles_q, ntiles, nbp, ea);
+        break;
+      default:
+        mode_nn_f64<EPI_ACCUM><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, Q, tiles_l, tiles_q, ntiles, nbp, ea);
+        break;
+    }
+  } else {
+    const long tiles_l = (L + BN - 1) / BN;
+    const long tiles_p = (P + BM - 1) / BM;
+    const long ntiles = tiles_l * tiles_p;
+    const long nbp = ((ntiles + 7) / 8) * 8;
+    if (nbp > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nbp), block(NT_THREADS);
+    switch (epi) {
+      case EPI_STORE:
+        mode_nt_f64<EPI_STORE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, tiles_l, ntiles, nbp, ea);
+        break;
+      case EPI_DIVIDE:  // only reached for the x axis with ny = nz = 1
+        mode_nt_f64<EPI_DIVIDE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, tiles_l, ntiles, nbp, ea);
+        break;
+      default:
+        mode_nt_f64<EPI_ACCUM><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, tiles_l, ntiles, nbp, ea);
+        break;
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace semfd

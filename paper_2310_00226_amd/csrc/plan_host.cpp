@@ -1,0 +1,567 @@
+// Host-side (FP64) construction of the 1D spectral-element operators and their
+// generalised eigendecomposition.
+//
+// Paper: Liu, Shen & Zhang, arXiv 2310.00226.
+//   Sec. 2.1       Q^k Lagrange basis on (k+1) Gauss-Lobatto points; 1D stiffness
+//                  <phi_i', phi_j'> and lumped (diagonal) mass <phi_i, phi_j>.
+//   Sec. 2.3       robust eigen-solve through the symmetric M^{-1/2} K M^{-1/2}.
+//   Appendix       SEGenerator1D: uniform mesh, element half-width h, gluing of
+//                  shared end nodes; LegendreD: GLL rule and derivative matrix.
+//
+// Everything here runs once per plan ("offline" in the paper's terms).
+#include "plan_host.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+#include <thread>
+#include <vector>
+
+namespace semfd {
+
+// ----------------------------------------------------------------------------
+// Symmetric tridiagonal eigen-solver: implicit QL with Wilkinson-type shifts.
+// d[0..n-1] diagonal, e[0..n-2] off-diagonal.  If z != nullptr (n x n, row-major)
+// the plane rotations are accumulated into z's columns: on exit column j of z
+// holds the eigenvector of d[j] in z's original basis.  Rotations of one QL sweep
+// are recorded and then applied to the rows of z in parallel.
+// ----------------------------------------------------------------------------
+static void apply_rotations_rows(double* z, int n, int ld, int l, int m,
+                                 const std::vector<double>& cs, const std::vector<double>& sn,
+                                 int nthreads) {
+  // Sweep i = m-1 down to l rotates columns (i, i+1):
+  //   z[:, i+1] <- s z[:, i] + c z[:, i+1];  z[:, i] <- c z[:, i] - s z[:, i+1]
+  auto work = [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      double* row = z + (size_t)r * ld;
+      for (int i = m - 1, t = 0; i >= l; --i, ++t) {
+        const double c = cs[t], s = sn[t];
+        const double f = row[i + 1];
+        row[i + 1] = s * row[i] + c * f;
+        row[i] = c * row[i] - s * f;
+      }
+    }
+  };
+  const long cost = (long)n * (m - l);
+  if (nthreads <= 1 || cost < 200000) {
+    work(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nthreads; ++t) {
+    int r0 = (int)((long)n * t / nthreads), r1 = (int)((long)n * (t + 1) / nthreads);
+    th.emplace_back(work, r0, r1);
+  }
+  for (auto& x : th) x.join();
+}
+
+void tridiag_ql(int n, double* d, double* e_in, double* z, int ldz, int nthreads) {
+  if (n <= 0) return;
+  std::vector<double> e(n, 0.0);
+  for (int i = 0; i + 1 < n; ++i) e[i] = e_in[i];
+  std::vector<double> cs, sn;
+  cs.reserve(n);
+  sn.reserve(n);
+  for (int l = 0; l < n; ++l) {
+    int iter = 0;
+    for (;;) {
+      int m = l;
+      for (; m < n - 1; ++m) {
+        volatile double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        volatile double sum = std::fabs(e[m]) + dd;  // negligible off-diagonal: deflate
+        if (sum == dd) break;
+      }
+      if (m == l) break;
+      if (++iter > 60) throw std::runtime_error("tridiagonal QL did not converge");
+      // shift from the trailing 2x2 of the leading block
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? std::fabs(r) : -std::fabs(r)));
+      double s = 1.0, c = 1.0, p = 0.0;
+      cs.clear();
+      sn.clear();
+      int i;
+      bool deflated = false;
+      for (i = m - 1; i >= l; --i) {
+        double f = s * e[i], b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {  // underflow: deflate
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          deflated = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        cs.push_back(c);
+        sn.push_back(s);
+      }
+      if (z) apply_rotations_rows(z, n, ldz, deflated ? i + 1 : l, m, cs, sn, nthreads);
+      if (deflated) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Householder reduction of a dense symmetric matrix a (n x n, row-major) to
+// tridiagonal form a = Q T Q^T.  On exit a holds Q, d the diagonal, e the
+// off-diagonal (e[i] couples i and i+1).
+// ----------------------------------------------------------------------------
+void householder_tridiag(int n, double* a, double* d, double* e, int nthreads) {
+  std::vector<double> v(n), w(n);
+  std::vector<double> hv;  // Householder vectors, stored in the lower part of a
+  for (int k = 0; k < n - 2; ++k) {
+    // column k below the diagonal: x = a[k+1..n-1][k]
+    double alpha2 = 0.0;
+    for (int i = k + 1; i < n; ++i) alpha2 += a[(size_t)i * n + k] * a[(size_t)i * n + k];
+    double x0 = a[(size_t)(k + 1) * n + k];
+    double alpha = (x0 >= 0 ? -1.0 : 1.0) * std::sqrt(alpha2);
+    if (alpha2 == 0.0 || std::fabs(alpha2 - x0 * x0) <= 1e-300) {
+      // column already reduced: identity reflector, flagged by a zero vector
+      e[k] = x0;
+      for (int i = k + 1; i < n; ++i) a[(size_t)i * n + k] = 0.0;
+      continue;
+    }
+    // v = x - alpha e1, normalised so that H = I - 2 v v^T / (v^T v)
+    for (int i = k + 1; i < n; ++i) v[i] = a[(size_t)i * n + k];
+    v[k + 1] -= alpha;
+    double vnorm2 = 0.0;
+    for (int i = k + 1; i < n; ++i) vnorm2 += v[i] * v[i];
+    const double beta = 2.0 / vnorm2;
+    // w = beta * A v on the trailing block (rows/cols k+1..n-1)
+    auto mv = [&](int r0, int r1) {
+      for (int i = r0; i < r1; ++i) {
+        const double* row = a + (size_t)i * n;
+        double s = 0.0;
+        for (int j = k + 1; j < n; ++j) s += row[j] * v[j];
+        w[i] = beta * s;
+      }
+    };
+    const int m = n - k - 1;
+    if (nthreads > 1 && (long)m * m > 400000) {
+      std::vector<std::thread> th;
+      for (int t = 0; t < nthreads; ++t)
+        th.emplace_back(mv, k + 1 + (int)((long)m * t / nthreads), k + 1 + (int)((long)m * (t + 1) / nthreads));
+      for (auto& x : th) x.join();
+    } else {
+      mv(k + 1, n);
+    }
+    // w <- w - (beta/2)(v^T w) v  ; A <- A - v w^T - w v^T
+    double vw = 0.0;
+    for (int i = k + 1; i < n; ++i) vw += v[i] * w[i];
+    const double kk = 0.5 * beta * vw;
+    for (int i = k + 1; i < n; ++i) w[i] -= kk * v[i];
+    auto upd = [&](int r0, int r1) {
+      for (int i = r0; i < r1; ++i) {
+        double* row = a + (size_t)i * n;
+        const double vi = v[i], wi = w[i];
+        for (int j = k + 1; j < n; ++j) row[j] -= vi * w[j] + wi * v[j];
+      }
+    };
+    if (nthreads > 1 && (long)m * m > 400000) {
+      std::vector<std::thread> th;
+      for (int t = 0; t < nthreads; ++t)
+        th.emplace_back(upd, k + 1 + (int)((long)m * t / nthreads), k + 1 + (int)((long)m * (t + 1) / nthreads));
+      for (auto& x : th) x.join();
+    } else {
+      upd(k + 1, n);
+    }
+    e[k] = alpha;
+    // store v (scaled to unit norm) in column k below the diagonal for the accumulation
+    const double inv = 1.0 / std::sqrt(vnorm2);
+    for (int i = k + 1; i < n; ++i) a[(size_t)i * n + k] = v[i] * inv;
+  }
+  if (n >= 2) e[n - 2] = a[(size_t)(n - 1) * n + (n - 2)];
+  for (int i = 0; i < n; ++i) d[i] = a[(size_t)i * n + i];
+  // Accumulate Q = H_0 H_1 ... H_{n-3} into a fresh matrix q (backward accumulation).
+  std::vector<double> q((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) q[(size_t)i * n + i] = 1.0;
+  for (int k = n - 3; k >= 0; --k) {
+    // u = unit Householder vector in rows k+1..n-1 of column k; H = I - 2 u u^T
+    bool zero = true;
+    for (int i = k + 1; i < n; ++i) {
+      v[i] = a[(size_t)i * n + k];
+      if (v[i] != 0.0) zero = false;
+    }
+    if (zero) continue;
+    // q[k+1.., k+1..] <- H q  : q -= 2 u (u^T q)
+    const int m = n - k - 1;
+    std::fill(w.begin(), w.end(), 0.0);
+    auto colsum = [&](int c0, int c1) {
+      for (int j = c0; j < c1; ++j) {
+        double s = 0.0;
+        for (int i = k + 1; i < n; ++i) s += v[i] * q[(size_t)i * n + j];
+        w[j] = s;
+      }
+    };
+    auto upd = [&](int c0, int c1) {
+      for (int i = k + 1; i < n; ++i) {
+        double* row = q.data() + (size_t)i * n;
+        const double vi = 2.0 * v[i];
+        for (int j = c0; j < c1; ++j) row[j] -= vi * w[j];
+      }
+    };
+    if (nthreads > 1 && (long)m * m > 400000) {
+      std::vector<std::thread> th;
+      for (int t = 0; t < nthreads; ++t)
+        th.emplace_back(colsum, k + 1 + (int)((long)m * t / nthreads), k + 1 + (int)((long)m * (t + 1) / nthreads));
+      for (auto& x : th) x.join();
+      th.clear();
+      for (int t = 0; t < nthreads; ++t)
+        th.emplace_back(upd, k + 1 + (int)((long)m * t / nthreads), k + 1 + (int)((long)m * (t + 1) / nthreads));
+      for (auto& x : th) x.join();
+    } else {
+      colsum(k + 1, n);
+      upd(k + 1, n);
+    }
+  }
+  std::memcpy(a, q.data(), sizeof(double) * (size_t)n * n);
+}
+
+// Symmetric eigen-decomposition a = Q diag(w) Q^T, ascending; a is overwritten by Q.
+void sym_eig(int n, double* a, double* w, int nthreads) {
+  std::vector<double> e(std::max(n, 1), 0.0);
+  if (n == 1) {
+    w[0] = a[0];
+    a[0] = 1.0;
+    return;
+  }
+  householder_tridiag(n, a, w, e.data(), nthreads);
+  tridiag_ql(n, w, e.data(), a, n, nthreads);
+  // sort ascending, permuting columns
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int i, int j) { return w[i] < w[j]; });
+  std::vector<double> ws(n), as((size_t)n * n);
+  for (int c = 0; c < n; ++c) {
+    ws[c] = w[idx[c]];
+    for (int r = 0; r < n; ++r) as[(size_t)r * n + c] = a[(size_t)r * n + idx[c]];
+  }
+  std::memcpy(w, ws.data(), sizeof(double) * n);
+  std::memcpy(a, as.data(), sizeof(double) * (size_t)n * n);
+}
+
+// ----------------------------------------------------------------------------
+// GLL rule.  Interior nodes are the zeros of P_k', i.e. of the Jacobi polynomial
+// P^{(1,1)}_{k-1}: the eigenvalues of its symmetric Jacobi matrix (zero diagonal,
+// off-diagonal sqrt(j(j+2)/((2j+1)(2j+3))), j = 1..k-2)  [Golub-Welsch].
+// Weights 2/(k(k+1) P_k(x)^2).
+// ----------------------------------------------------------------------------
+static double legendre_p(int k, double x) {
+  double p0 = 1.0, p1 = x;
+  if (k == 0) return p0;
+  for (int j = 1; j < k; ++j) {
+    double p2 = ((2.0 * j + 1.0) * x * p1 - j * p0) / (j + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+void gll_rule(int k, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(k + 1, 0.0);
+  w.assign(k + 1, 0.0);
+  x[0] = -1.0;
+  x[k] = 1.0;
+  if (k >= 2) {
+    const int m = k - 1;
+    std::vector<double> d(m, 0.0), e(std::max(m, 1), 0.0);
+    for (int j = 1; j <= m - 1; ++j) e[j - 1] = std::sqrt((double)j * (j + 2) / ((2.0 * j + 1) * (2.0 * j + 3)));
+    tridiag_ql(m, d.data(), e.data(), nullptr, 0, 1);
+    std::sort(d.begin(), d.end());
+    for (int j = 0; j < m; ++j) x[j + 1] = d[j];
+    // enforce the exact symmetry of the rule
+    for (int j = 1; j < k; ++j) {
+      double s = 0.5 * (x[j] - x[k - j]);
+      x[j] = s;
+      x[k - j] = -s;
+    }
+    if (k % 2 == 0) x[k / 2] = 0.0;
+  }
+  for (int j = 0; j <= k; ++j) {
+    double p = legendre_p(k, x[j]);
+    w[j] = 2.0 / (k * (k + 1.0) * p * p);
+  }
+}
+
+// Derivative matrix D[i][j] = l_j'(x_i): closed form for Legendre-Gauss-Lobatto
+// off the diagonal, P_k(x_i) / (P_k(x_j) (x_i - x_j)); diagonal = minus the row sum
+// (so that constants are differentiated to zero exactly).
+static void gll_derivative(int k, const std::vector<double>& x, std::vector<double>& D) {
+  const int np = k + 1;
+  D.assign((size_t)np * np, 0.0);
+  std::vector<double> p(np);
+  for (int i = 0; i < np; ++i) p[i] = legendre_p(k, x[i]);
+  for (int i = 0; i < np; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < np; ++j) {
+      if (i == j) continue;
+      D[(size_t)i * np + j] = p[i] / (p[j] * (x[i] - x[j]));
+      s += D[(size_t)i * np + j];
+    }
+    D[(size_t)i * np + i] = -s;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Extended-precision refinement of the generalised eigenpairs K S = M S Lambda.
+//
+// The FD solve divides by lx_i + ly_j + lz_l + alpha; an FP64 eigensolver leaves
+// absolute eigenvalue errors ~ eps * lambda_max and eigenvector errors
+// ~ eps * lambda_max / gap, which perturb the lowest (dominant) solution modes by
+// ~eps * cond (~1e-11 at n ~ 1000).  One Newton step of Ogita & Aishima (2018),
+// with the Gram matrices in x87 long double, brings them to FP64 rounding:
+//   T = X^T K X,  R = I - X^T M X,  lam_i = T_ii / (1 - R_ii),
+//   E_ii = R_ii / 2,  E_ij = (T_ij + lam_j R_ij) / (lam_j - lam_i),  X <- X (I + E).
+// Pairs closer than 1e-15 * lambda_max keep only the symmetric part R_ij / 2.
+// ----------------------------------------------------------------------------
+template <class F>
+static void parallel_rows(int n, int nthreads, F&& fn) {
+  if (nthreads <= 1 || n < 64) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int chunks = std::min(n, nthreads * 4);
+  std::atomic<int> next{0};
+  for (int t = 0; t < nthreads; ++t)
+    th.emplace_back([&] {
+      for (;;) {
+        const int c = next.fetch_add(1);
+        if (c >= chunks) break;
+        fn((int)((long)n * c / chunks), (int)((long)n * (c + 1) / chunks));
+      }
+    });
+  for (auto& x : th) x.join();
+}
+
+// K X is formed element by element from the long-double element stiffness ke
+// ((k+1)^2, already divided by h): FP64 rounding of K's entries alone would shift
+// the lowest eigenvalues by ~ eps * lambda_max, since they come out of a
+// cancellation of ratio lambda_max / lambda_min.
+static void refine_eigenpairs(int n, int k, int ne, const std::vector<long double>& ke, int off,
+                              const std::vector<double>& mass, std::vector<double>& lam, std::vector<double>& S,
+                              int nthreads) {
+  typedef long double ld;
+  const int np = k + 1, nfull = ne * k + 1;
+  const size_t nn = (size_t)n * n;
+  std::vector<ld> X(nn), KX(nn), T(nn), R(nn), L(n);
+  for (size_t t = 0; t < nn; ++t) X[t] = S[t];
+  parallel_rows(n, nthreads, [&](int p0, int p1) {
+    for (int p = p0; p < p1; ++p) {
+      ld* row = &KX[(size_t)p * n];
+      std::fill(row, row + n, 0.0L);
+      const int pf = p + off;  // full-numbering index
+      // elements containing node pf: e = pf / k (as its left/inner node) and pf / k - 1 (as right end)
+      for (int e = std::max(0, (pf - 1) / k); e <= std::min(ne - 1, pf / k); ++e) {
+        const int li = pf - e * k;
+        if (li < 0 || li > k) continue;
+        for (int lj = 0; lj < np; ++lj) {
+          const int qf = e * k + lj, q = qf - off;
+          if (q < 0 || q >= n || qf >= nfull) continue;
+          const ld kv = ke[(size_t)li * np + lj];
+          const ld* xq = &X[(size_t)q * n];
+          for (int j = 0; j < n; ++j) row[j] += kv * xq[j];
+        }
+      }
+    }
+  });
+  parallel_rows(n, nthreads, [&](int i0, int i1) {
+    for (int i = i0; i < i1; ++i) {
+      ld* ti = &T[(size_t)i * n];
+      ld* ri = &R[(size_t)i * n];
+      std::fill(ti, ti + n, 0.0L);
+      std::fill(ri, ri + n, 0.0L);
+      for (int p = 0; p < n; ++p) {
+        const ld xpi = X[(size_t)p * n + i];
+        const ld mx = (ld)mass[p] * xpi;
+        const ld* kxp = &KX[(size_t)p * n];
+        const ld* xp = &X[(size_t)p * n];
+        for (int j = 0; j < n; ++j) {
+          ti[j] += xpi * kxp[j];
+          ri[j] += mx * xp[j];
+        }
+      }
+      for (int j = 0; j < n; ++j) ri[j] = (i == j ? 1.0L : 0.0L) - ri[j];
+    }
+  });
+  ld lmax = 0;
+  for (int i = 0; i < n; ++i) {
+    L[i] = T[(size_t)i * n + i] / (1.0L - R[(size_t)i * n + i]);
+    lmax = std::max(lmax, std::fabs(L[i]));
+  }
+  const ld tiny = 1e-15L * (lmax > 0 ? lmax : 1.0L);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const size_t ij = (size_t)i * n + j;
+      if (i == j) {
+        T[ij] = 0.5L * R[ij];
+      } else {
+        const ld dl = L[j] - L[i];
+        T[ij] = std::fabs(dl) > tiny ? (T[ij] + L[j] * R[ij]) / dl : 0.5L * R[ij];
+      }
+    }
+  parallel_rows(n, nthreads, [&](int p0, int p1) {
+    std::vector<ld> acc(n);
+    for (int p = p0; p < p1; ++p) {
+      const ld* xp = &X[(size_t)p * n];
+      for (int j = 0; j < n; ++j) acc[j] = xp[j];
+      for (int i = 0; i < n; ++i) {
+        const ld xpi = xp[i];
+        const ld* ei = &T[(size_t)i * n];
+        for (int j = 0; j < n; ++j) acc[j] += xpi * ei[j];
+      }
+      for (int j = 0; j < n; ++j) S[(size_t)p * n + j] = (double)acc[j];
+    }
+  });
+  // keep ascending order
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return L[a] < L[b]; });
+  bool sorted = true;
+  for (int i = 0; i < n; ++i) sorted = sorted && idx[i] == i;
+  std::vector<double> Sn = sorted ? std::vector<double>() : S;
+  for (int c = 0; c < n; ++c) {
+    lam[c] = (double)L[idx[c]];
+    if (!sorted)
+      for (int r = 0; r < n; ++r) S[(size_t)r * n + c] = Sn[(size_t)r * n + idx[c]];
+  }
+}
+
+// Element stiffness (k+1)^2 in long double, divided by the half width h, from the
+// FP64 GLL nodes: closed-form derivative matrix, diagonal = minus the off-diagonal
+// row sum, K_e = D^T W D / h.
+static std::vector<long double> element_stiffness_ld(int k, const std::vector<double>& xr,
+                                                     const std::vector<double>& wr, double a, double b, int ne) {
+  typedef long double ld;
+  const int np = k + 1;
+  std::vector<ld> p(np), D((size_t)np * np, 0.0L), ke((size_t)np * np, 0.0L);
+  for (int i = 0; i < np; ++i) {
+    ld p0 = 1.0L, p1 = xr[i];
+    for (int j = 1; j < k; ++j) {
+      ld p2 = ((2.0L * j + 1.0L) * (ld)xr[i] * p1 - (ld)j * p0) / (ld)(j + 1);
+      p0 = p1;
+      p1 = p2;
+    }
+    p[i] = k == 0 ? 1.0L : p1;
+  }
+  for (int i = 0; i < np; ++i) {
+    ld s = 0.0L;
+    for (int j = 0; j < np; ++j) {
+      if (i == j) continue;
+      D[(size_t)i * np + j] = p[i] / (p[j] * ((ld)xr[i] - (ld)xr[j]));
+      s += D[(size_t)i * np + j];
+    }
+    D[(size_t)i * np + i] = -s;
+  }
+  const ld h = ((ld)b - (ld)a) / (2.0L * ne);
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < np; ++j) {
+      ld acc = 0.0L;
+      for (int q = 0; q < np; ++q) acc += D[(size_t)q * np + i] * (ld)wr[q] * D[(size_t)q * np + j];
+      ke[(size_t)i * np + j] = acc / h;
+    }
+  return ke;
+}
+
+// ----------------------------------------------------------------------------
+// 1D assembled operators and eigen-decomposition for one axis.
+// ----------------------------------------------------------------------------
+void build_axis(const AxisSpec& spec, AxisData& out, int nthreads) {
+  const int k = spec.k, ne = spec.ne;
+  if (k < 1 || ne < 1) throw std::invalid_argument("k >= 1 and ne >= 1 required");
+  const bool dir = spec.dirichlet;
+  const int nfull = ne * k + 1;
+  const int n = dir ? nfull - 2 : nfull;
+  if (n < 1) throw std::invalid_argument("Dirichlet needs ne*k >= 2");
+  std::vector<double> xr, wr, D;
+  gll_rule(k, xr, wr);
+  gll_derivative(k, xr, D);
+  // reference stiffness K_ref = D^T W D
+  const int np = k + 1;
+  std::vector<double> kref((size_t)np * np, 0.0);
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < np; ++j) {
+      double s = 0.0;
+      for (int q = 0; q < np; ++q) s += D[(size_t)q * np + i] * wr[q] * D[(size_t)q * np + j];
+      kref[(size_t)i * np + j] = s;
+    }
+  const double h = (spec.b - spec.a) / (2.0 * ne);
+  // banded assembly: kb[g][d] = K(g, g-k+d), d = 0..2k
+  const int bw = 2 * k + 1;
+  std::vector<double> kb((size_t)nfull * bw, 0.0), mf(nfull, 0.0), xf(nfull, 0.0);
+  for (int el = 0; el < ne; ++el) {
+    const int s = el * k;
+    for (int i = 0; i < np; ++i) {
+      mf[s + i] += h * wr[i];
+      xf[s + i] = spec.a + h * (2.0 * el + 1.0 + xr[i]);
+      for (int j = 0; j < np; ++j) kb[(size_t)(s + i) * bw + (j - i + k)] += kref[(size_t)i * np + j] / h;
+    }
+  }
+  xf[0] = spec.a;
+  xf[nfull - 1] = spec.b;
+  // <grad 1, grad v> = 0: every row of the Neumann stiffness sums to zero up to one
+  // rounding (diagonal = minus the off-diagonal row sum), before any restriction
+  for (int g = 0; g < nfull; ++g) {
+    double s = 0.0;
+    for (int d = 0; d < bw; ++d)
+      if (d != k) s += kb[(size_t)g * bw + d];
+    kb[(size_t)g * bw + k] = -s;
+  }
+  const int off = dir ? 1 : 0;
+  out.n = n;
+  out.k = k;
+  out.h = h;
+  out.x.assign(xf.begin() + off, xf.begin() + off + n);
+  out.mass.assign(mf.begin() + off, mf.begin() + off + n);
+  out.hband.assign((size_t)n * bw, 0.0);
+  for (int g = 0; g < n; ++g)
+    for (int d = 0; d < bw; ++d) {
+      int col = g - k + d;  // in restricted numbering
+      if (col < 0 || col >= n) continue;
+      out.hband[(size_t)g * bw + d] = kb[(size_t)(g + off) * bw + d] / out.mass[g];
+    }
+  // symmetric S1 = M^{-1/2} K M^{-1/2}, dense
+  std::vector<double> mh(n);
+  for (int g = 0; g < n; ++g) mh[g] = std::sqrt(out.mass[g]);
+  std::vector<double> s1((size_t)n * n, 0.0);
+  for (int g = 0; g < n; ++g)
+    for (int d = 0; d < bw; ++d) {
+      int col = g - k + d;
+      if (col < 0 || col >= n) continue;
+      s1[(size_t)g * n + col] = kb[(size_t)(g + off) * bw + d] / (mh[g] * mh[col]);
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      double v = 0.5 * (s1[(size_t)i * n + j] + s1[(size_t)j * n + i]);
+      s1[(size_t)i * n + j] = s1[(size_t)j * n + i] = v;
+    }
+  out.lam.assign(n, 0.0);
+  sym_eig(n, s1.data(), out.lam.data(), nthreads);
+  // S = M^{-1/2} Q  (backward factor)
+  out.S.assign((size_t)n * n, 0.0);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) out.S[(size_t)r * n + c] = s1[(size_t)r * n + c] / mh[r];
+  if (n > 1) {
+    const std::vector<long double> ke = element_stiffness_ld(k, xr, wr, spec.a, spec.b, ne);
+    refine_eigenpairs(n, k, ne, ke, off, out.mass, out.lam, out.S, nthreads);
+  }
+  // forward factor F = S^T M  (= Q^T M^{1/2})
+  out.F.assign((size_t)n * n, 0.0);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) out.F[(size_t)c * n + r] = out.S[(size_t)r * n + c] * out.mass[r];
+}
+
+}  // namespace semfd

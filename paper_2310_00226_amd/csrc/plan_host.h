@@ -1,0 +1,34 @@
+// Host-side 1D operator construction and eigen-solver (FP64).
+#pragma once
+#include <vector>
+
+namespace semfd {
+
+struct AxisSpec {
+  int k;           // polynomial degree
+  int ne;          // number of elements
+  double a, b;     // interval
+  bool dirichlet;  // homogeneous Dirichlet (true) or Neumann (false)
+  bool operator==(const AxisSpec& o) const {
+    return k == o.k && ne == o.ne && a == o.a && b == o.b && dirichlet == o.dirichlet;
+  }
+};
+
+struct AxisData {
+  int n = 0, k = 0;
+  double h = 0;
+  std::vector<double> x;      // node coordinates (n)
+  std::vector<double> mass;   // lumped mass diagonal (n)
+  std::vector<double> hband;  // H = M^{-1} K banded rows: n x (2k+1), entry [g][d] = H(g, g-k+d)
+  std::vector<double> lam;    // eigenvalues ascending (n)
+  std::vector<double> S;      // backward factor S (n x n row-major), K S = M S Lambda, S^T M S = I
+  std::vector<double> F;      // forward factor F = S^T M (n x n row-major)
+};
+
+void tridiag_ql(int n, double* d, double* e, double* z, int ldz, int nthreads);
+void householder_tridiag(int n, double* a, double* d, double* e, int nthreads);
+void sym_eig(int n, double* a, double* w, int nthreads);
+void gll_rule(int k, std::vector<double>& x, std::vector<double>& w);
+void build_axis(const AxisSpec& spec, AxisData& out, int nthreads);
+
+}  // namespace semfd

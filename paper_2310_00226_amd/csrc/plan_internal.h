@@ -1,0 +1,39 @@
+// The plan object behind the opaque sem_plan handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "../../include/sem.h"
+#include "plan_host.h"
+
+struct sem_plan {
+  int device = -1;
+  int k = 0;
+  int ne[3] = {0, 0, 0};
+  int dims[3] = {0, 0, 0};
+  int ld[3] = {0, 0, 0};  // padded factor dimension (multiple of 128)
+  double box[6] = {0, 0, 0, 0, 0, 0};
+  double alpha = 0.0;
+  sem_bc bc = SEM_BC_DIRICHLET;
+  size_t N = 0;
+  semfd::AxisData ax[3];
+  // FP64 device data
+  double* d_gf[3] = {nullptr, nullptr, nullptr};  // forward factor F = S^T M, stored G[m][l] = F[l][m]
+  double* d_gb[3] = {nullptr, nullptr, nullptr};  // backward factor S, stored G[m][l] = S[l][m]
+  double* d_lam[3] = {nullptr, nullptr, nullptr};
+  double* d_hb[3] = {nullptr, nullptr, nullptr};  // banded rows of H = M^{-1} K
+  // execution
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+};
+
+namespace semfd {
+sem_status hip_fail(hipError_t e, const char* what);
+sem_status set_error(sem_status st, const char* msg);
+sem_status plan_workspace(sem_plan* p, size_t need, void** out);
+size_t workspace_need(const sem_plan* p, sem_prec prec);
+void release_lowp(sem_plan* p);
+}  // namespace semfd

@@ -1,0 +1,294 @@
+// C ABI of the fast-diagonalisation solver (declarations and contracts: include/sem.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/sem.h"
+#include "kernels.h"
+#include "plan_host.h"
+#include "plan_internal.h"
+
+using namespace semfd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sem_status fail(sem_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+int host_threads() {
+  unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(hc, 16u));
+}
+
+}  // namespace
+
+namespace semfd {
+
+sem_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(SEM_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(SEM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+sem_status set_error(sem_status st, const char* msg) { return fail(st, "%s", msg); }
+
+// Device copy of one factor in the G[m][l] = A[l][m] layout, zero-padded to ld x ld.
+static hipError_t upload_factor(const std::vector<double>& A, int n, int ld, double** dst) {
+  std::vector<double> g((size_t)ld * ld, 0.0);
+  for (int l = 0; l < n; ++l)
+    for (int m = 0; m < n; ++m) g[(size_t)m * ld + l] = A[(size_t)l * n + m];
+  hipError_t e = hipMalloc(dst, sizeof(double) * g.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice);
+}
+
+static hipError_t upload_vec(const std::vector<double>& v, double** dst) {
+  hipError_t e = hipMalloc(dst, sizeof(double) * std::max<size_t>(v.size(), 1));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice);
+}
+
+sem_status plan_workspace(sem_plan* p, size_t need, void** out) {
+  if (p->ws && p->ws_bytes >= need) {
+    *out = p->ws;
+    return SEM_OK;
+  }
+  if (p->ws_owned && p->ws) {
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "workspace resize");
+    (void)hipFree(p->ws);
+  }
+  p->ws = nullptr;
+  p->ws_bytes = 0;
+  p->ws_owned = false;
+  hipError_t e = hipMalloc(&p->ws, need);
+  if (e != hipSuccess) {
+    p->ws = nullptr;
+    return hip_fail(e, "workspace allocation");
+  }
+  p->ws_bytes = need;
+  p->ws_owned = true;
+  *out = p->ws;
+  return SEM_OK;
+}
+
+}  // namespace semfd
+
+extern "C" {
+
+const char* sem_last_error(void) { return g_last_error.c_str(); }
+
+sem_status sem_axis_host(int k, int ne, double a, double b, sem_bc bc, int* n, double* x, double* mass, double* lam,
+                         double* S, double* F) {
+  if (k < 1 || ne < 1 || !(a < b) || !std::isfinite(a) || !std::isfinite(b) ||
+      (bc != SEM_BC_DIRICHLET && bc != SEM_BC_NEUMANN))
+    return fail(SEM_EINVAL, "sem_axis_host: invalid argument");
+  if (bc == SEM_BC_DIRICHLET && ne * k < 2) return fail(SEM_EINVAL, "Dirichlet needs ne*k >= 2");
+  const int nn = bc == SEM_BC_DIRICHLET ? ne * k - 1 : ne * k + 1;
+  if (n) *n = nn;
+  if (!x && !mass && !lam && !S && !F) return SEM_OK;
+  try {
+    AxisData d;
+    build_axis(AxisSpec{k, ne, a, b, bc == SEM_BC_DIRICHLET}, d, host_threads());
+    if (x) std::memcpy(x, d.x.data(), sizeof(double) * nn);
+    if (mass) std::memcpy(mass, d.mass.data(), sizeof(double) * nn);
+    if (lam) std::memcpy(lam, d.lam.data(), sizeof(double) * nn);
+    if (S) std::memcpy(S, d.S.data(), sizeof(double) * nn * nn);
+    if (F) std::memcpy(F, d.F.data(), sizeof(double) * nn * nn);
+  } catch (const std::exception& ex) {
+    return fail(SEM_EINVAL, "sem_axis_host: %s", ex.what());
+  }
+  return SEM_OK;
+}
+
+sem_status sem_plan_create(int k, const int ne[3], const double box[6], double alpha, sem_bc bc, sem_plan** out) {
+  if (!out || !ne || !box) return fail(SEM_EINVAL, "sem_plan_create: null argument");
+  *out = nullptr;
+  if (k < 1 || k > 64) return fail(SEM_EINVAL, "sem_plan_create: k must be in [1, 64]");
+  if (bc != SEM_BC_DIRICHLET && bc != SEM_BC_NEUMANN) return fail(SEM_EINVAL, "sem_plan_create: bad bc");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SEM_EINVAL, "sem_plan_create: alpha must be finite, >= 0");
+  long total = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (ne[a] < 1) return fail(SEM_EINVAL, "sem_plan_create: ne[%d] < 1", a);
+    if (!(box[2 * a] < box[2 * a + 1]) || !std::isfinite(box[2 * a]) || !std::isfinite(box[2 * a + 1]))
+      return fail(SEM_EINVAL, "sem_plan_create: degenerate box on axis %d", a);
+    const long n = bc == SEM_BC_DIRICHLET ? (long)ne[a] * k - 1 : (long)ne[a] * k + 1;
+    if (n < 1) return fail(SEM_EINVAL, "sem_plan_create: Dirichlet axis %d has no interior node", a);
+    if (n > 4096) return fail(SEM_EINVAL, "sem_plan_create: axis %d has %ld > 4096 unknowns", a, n);
+    total *= n;
+  }
+  if (total > (1L << 36)) return fail(SEM_EINVAL, "sem_plan_create: problem too large");
+
+  sem_plan* p = new (std::nothrow) sem_plan();
+  if (!p) return fail(SEM_ENOMEM, "sem_plan_create: host allocation");
+  p->k = k;
+  p->alpha = alpha;
+  p->bc = bc;
+  for (int a = 0; a < 6; ++a) p->box[a] = box[a];
+  try {
+    for (int a = 0; a < 3; ++a) {
+      p->ne[a] = ne[a];
+      AxisSpec s{k, ne[a], box[2 * a], box[2 * a + 1], bc == SEM_BC_DIRICHLET};
+      int same = -1;
+      for (int b = 0; b < a; ++b)
+        if (AxisSpec{k, ne[b], box[2 * b], box[2 * b + 1], bc == SEM_BC_DIRICHLET} == s) same = b;
+      if (same >= 0)
+        p->ax[a] = p->ax[same];
+      else
+        build_axis(s, p->ax[a], host_threads());
+      p->dims[a] = p->ax[a].n;
+    }
+  } catch (const std::exception& ex) {
+    delete p;
+    return fail(SEM_EINVAL, "sem_plan_create: %s", ex.what());
+  }
+  p->N = (size_t)p->dims[0] * p->dims[1] * p->dims[2];
+  const double lmin = p->ax[0].lam[0] + p->ax[1].lam[0] + p->ax[2].lam[0] + alpha;
+  const double lmax = p->ax[0].lam.back() + p->ax[1].lam.back() + p->ax[2].lam.back() + alpha;
+  if (!(lmin > 1e-13 * lmax)) {
+    delete p;
+    return fail(SEM_ESINGULAR, "sem_plan_create: operator is singular (min eigenvalue sum %.3e)", lmin);
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "sem_plan_create: no HIP device");
+  }
+  for (int a = 0; a < 3; ++a) {
+    const int n = p->dims[a];
+    p->ld[a] = ((n + 127) / 128) * 128;
+    if ((e = upload_factor(p->ax[a].F, n, p->ld[a], &p->d_gf[a])) != hipSuccess ||
+        (e = upload_factor(p->ax[a].S, n, p->ld[a], &p->d_gb[a])) != hipSuccess ||
+        (e = upload_vec(p->ax[a].lam, &p->d_lam[a])) != hipSuccess ||
+        (e = upload_vec(p->ax[a].hband, &p->d_hb[a])) != hipSuccess) {
+      sem_plan_destroy(p);
+      return hip_fail(e, "sem_plan_create: factor upload");
+    }
+  }
+  *out = p;
+  return SEM_OK;
+}
+
+void sem_plan_destroy(sem_plan* p) {
+  if (!p) return;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (p->device >= 0) (void)hipSetDevice(p->device);
+  if (p->stream || p->ws_owned) (void)hipStreamSynchronize(p->stream);
+  for (int a = 0; a < 3; ++a) {
+    (void)hipFree(p->d_gf[a]);
+    (void)hipFree(p->d_gb[a]);
+    (void)hipFree(p->d_lam[a]);
+    (void)hipFree(p->d_hb[a]);
+  }
+  release_lowp(p);
+  if (p->ws_owned) (void)hipFree(p->ws);
+  if (cur >= 0) (void)hipSetDevice(cur);
+  delete p;
+}
+
+sem_status sem_plan_dims(const sem_plan* p, int n[3]) {
+  if (!p || !n) return fail(SEM_EINVAL, "sem_plan_dims: null argument");
+  for (int a = 0; a < 3; ++a) n[a] = p->dims[a];
+  return SEM_OK;
+}
+
+sem_status sem_plan_nodes(const sem_plan* p, int axis, double* x) {
+  if (!p || !x || axis < 0 || axis > 2) return fail(SEM_EINVAL, "sem_plan_nodes: invalid argument");
+  std::memcpy(x, p->ax[axis].x.data(), sizeof(double) * p->dims[axis]);
+  return SEM_OK;
+}
+
+sem_status sem_plan_eigenvalues(const sem_plan* p, int axis, double* lam) {
+  if (!p || !lam || axis < 0 || axis > 2) return fail(SEM_EINVAL, "sem_plan_eigenvalues: invalid argument");
+  std::memcpy(lam, p->ax[axis].lam.data(), sizeof(double) * p->dims[axis]);
+  return SEM_OK;
+}
+
+sem_status sem_plan_set_stream(sem_plan* p, void* s) {
+  if (!p) return fail(SEM_EINVAL, "sem_plan_set_stream: null plan");
+  p->stream = (hipStream_t)s;
+  return SEM_OK;
+}
+
+sem_status sem_plan_workspace_bytes(const sem_plan* p, sem_prec prec, size_t* bytes) {
+  if (!p || !bytes) return fail(SEM_EINVAL, "sem_plan_workspace_bytes: null argument");
+  *bytes = workspace_need(p, prec);
+  if (*bytes == 0) return fail(SEM_EINVAL, "sem_plan_workspace_bytes: unknown precision");
+  return SEM_OK;
+}
+
+sem_status sem_plan_set_workspace(sem_plan* p, void* ptr, size_t bytes) {
+  if (!p) return fail(SEM_EINVAL, "sem_plan_set_workspace: null plan");
+  if (ptr && ((uintptr_t)ptr % 256) != 0) return fail(SEM_EINVAL, "sem_plan_set_workspace: pointer not 256-B aligned");
+  if (p->ws_owned && p->ws) {
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipFree(p->ws);
+  }
+  p->ws = ptr;
+  p->ws_bytes = ptr ? bytes : 0;
+  p->ws_owned = false;
+  return SEM_OK;
+}
+
+sem_status sem_mode_product(sem_plan* p, int axis, int inverse, const double* in, double* out) {
+  if (!p || !in || !out || axis < 0 || axis > 2) return fail(SEM_EINVAL, "sem_mode_product: invalid argument");
+  if (in == out) return fail(SEM_EINVAL, "sem_mode_product: in and out must not alias");
+  EpiArgs ea;
+  hipError_t e = launch_mode_f64(in, out, inverse ? p->d_gb[axis] : p->d_gf[axis], p->ld[axis], p->dims, axis,
+                                 EPI_STORE, ea, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "sem_mode_product");
+  return SEM_OK;
+}
+
+sem_status sem_solve(sem_plan* p, const double* f, double* u) {
+  if (!p || !f || !u) return fail(SEM_EINVAL, "sem_solve: null argument");
+  void* ws = nullptr;
+  sem_status st = plan_workspace(p, workspace_need(p, SEM_F64), &ws);
+  if (st != SEM_OK) return st;
+  double* tmp = (double*)ws;
+  EpiArgs none;
+  EpiArgs div;
+  div.lx = p->d_lam[0];
+  div.ly = p->d_lam[1];
+  div.lz = p->d_lam[2];
+  div.alpha = p->alpha;
+  div.nz = p->dims[2];
+  hipError_t e;
+  if ((e = launch_mode_f64(f, tmp, p->d_gf[2], p->ld[2], p->dims, 2, EPI_STORE, none, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(tmp, u, p->d_gf[1], p->ld[1], p->dims, 1, EPI_STORE, none, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(u, tmp, p->d_gf[0], p->ld[0], p->dims, 0, EPI_DIVIDE, div, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(tmp, u, p->d_gb[2], p->ld[2], p->dims, 2, EPI_STORE, none, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(u, tmp, p->d_gb[1], p->ld[1], p->dims, 1, EPI_STORE, none, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(tmp, u, p->d_gb[0], p->ld[0], p->dims, 0, EPI_STORE, none, p->stream)) != hipSuccess)
+    return hip_fail(e, "sem_solve");
+  return SEM_OK;
+}
+
+sem_status sem_residual(sem_plan* p, const double* u, const double* f, double* r) {
+  if (!p || !u || !f || !r) return fail(SEM_EINVAL, "sem_residual: null argument");
+  if (r == u) return fail(SEM_EINVAL, "sem_residual: r must not alias u");
+  const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
+  hipError_t e = launch_residual_f64(u, f, r, hb, p->k, p->dims, p->alpha, p->stream);
+  if (e != hipSuccess) return hip_fail(e, "sem_residual");
+  return SEM_OK;
+}
+
+}  // extern "C"

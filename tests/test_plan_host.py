@@ -1,0 +1,83 @@
+"""Host side of the library (no GPU): the plan's 1D operators and eigenpairs
+against the oracle, eigen invariants, argument validation, and the exported
+C ABI."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2310_00226_amd as P
+    return P
+
+
+def test_library_exports_every_declared_symbol(P):
+    with open(os.path.join(ROOT, "include", "sem.h")) as fh:
+        text = fh.read()
+    names = sorted(set(re.findall(r"\b(sem_[a-z0-9_]+)\s*\(", text)))
+    assert len(names) >= 10
+    lib = ctypes.CDLL(P.binding.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("k,ne,a,b,bc", [
+    (1, 9, -1.0, 1.0, "dirichlet"), (2, 3, -1.0, 1.0, "neumann"), (4, 8, -1.0, 1.0, "dirichlet"),
+    (5, 7, 0.0, 3.0, "neumann"), (8, 5, -2.0, 1.0, "dirichlet"), (20, 3, -16.0, 16.0, "neumann"),
+])
+def test_plan_axis_matches_oracle(P, k, ne, a, b, bc):
+    d = P.axis_host(k, ne, a, b, bc)
+    o = O.axis_operators(k, ne, a, b, bc)
+    lam_o, _, _ = O.axis_eigen(o)
+    np.testing.assert_allclose(d["x"], o.x, rtol=0, atol=1e-14 * max(1, abs(a), abs(b)))
+    np.testing.assert_allclose(d["mass"], o.M, rtol=1e-14)
+    # backward-stable eigenvalues: |dlam| <~ eps * ||S1||
+    assert np.max(np.abs(d["lam"] - lam_o)) <= 1e-13 * lam_o[-1]
+    n = lam_o.size
+    S, F, M = d["S"], d["F"], d["mass"]
+    assert np.max(np.abs(S.T @ (M[:, None] * S) - np.eye(n))) <= 1e-13
+    res = o.K @ S - (M[:, None] * S) * d["lam"][None, :]
+    kinf = np.max(np.sum(np.abs(o.K), axis=1))
+    assert np.max(np.max(np.abs(res), axis=0) / (kinf * np.max(np.abs(S), axis=0))) <= 1e-13
+    np.testing.assert_allclose(F, S.T * M[None, :], atol=1e-14 * np.max(np.abs(F)))
+
+
+def test_plan_axis_n999_invariants(P):
+    d = P.axis_host(4, 250, -1.0, 1.0, "dirichlet")
+    o = O.axis_operators(4, 250, -1.0, 1.0, "dirichlet")
+    S, M, lam = d["S"], d["mass"], d["lam"]
+    assert np.max(np.abs(S.T @ (M[:, None] * S) - np.eye(999))) <= 1e-13
+    res = o.K @ S - (M[:, None] * S) * lam[None, :]
+    kinf = np.max(np.sum(np.abs(o.K), axis=1))
+    assert np.max(np.max(np.abs(res), axis=0) / (kinf * np.max(np.abs(S), axis=0))) <= 1e-13
+    assert abs(lam[0] - (math.pi / 2) ** 2) < 1e-9
+
+
+@pytest.mark.parametrize("args", [
+    (0, 4, -1.0, 1.0, "dirichlet"),     # k < 1
+    (4, 0, -1.0, 1.0, "dirichlet"),     # ne < 1
+    (4, 4, 1.0, 1.0, "dirichlet"),      # empty interval
+    (4, 4, 1.0, -1.0, "neumann"),       # reversed interval
+    (1, 1, -1.0, 1.0, "dirichlet"),     # no interior node
+])
+def test_axis_host_rejects_invalid(P, args):
+    with pytest.raises(P.SemError) as ei:
+        P.axis_host(*args)
+    assert ei.value.status == 1  # SEM_EINVAL
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
+def test_plan_lowest_eigenvalues_match_continuous_spectrum_n999(P, bc):
+    # see the oracle's test of the same name: the low modes are refined to rounding
+    d = P.axis_host(4, 250, -1.0, 1.0, bc)
+    j = np.arange(1, 6) if bc == "dirichlet" else np.arange(0, 5)
+    np.testing.assert_allclose(d["lam"][:5], (j * np.pi / 2) ** 2, rtol=0, atol=5e-14 * (1 + j ** 2))
