@@ -39,6 +39,9 @@ def main() -> int:
     ap.add_argument("--ne", type=int, default=250, help="elements per axis (250 -> n = 999)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=5)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain elementwise copy of f (N*8 bytes read + written) so that HBM "
+                         "counters of the kernels can be scaled against a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only",
@@ -97,8 +100,12 @@ def main() -> int:
     launch_ms = e0.elapsed_time(e1) / args.kernel_reps
     flops_launch = 2.0 * N * ny
     achieved = flops_launch / (launch_ms * 1e-3) / 1e12
-    solve_tflops = 2.0 * N * (nx + ny + nz) / (ms * 1e-3) / 1e12
+    solve_tflops = 4.0 * N * (nx + ny + nz) / (ms * 1e-3) / 1e12  # six mode products
     log(f"mode product (y, NN): {launch_ms:.3f} ms/launch, {achieved:.1f} TFLOP/s; solve {solve_tflops:.1f} TFLOP/s")
+    if args.calib_copy:
+        tmp.copy_(f)           # device-to-device copy: reads and writes N * 8 bytes
+        torch.neg(f, out=tmp)  # elementwise kernel with the same traffic
+        torch.cuda.synchronize()
     del tmp
 
     out = {

@@ -49,20 +49,6 @@ __device__ __forceinline__ long xcd_tile(long nblocks_padded) {
   return (long)(blockIdx.x % 8) * per + (long)(blockIdx.x / 8);
 }
 
-template <int EPI>
-__device__ __forceinline__ void store_out(double* __restrict__ y, size_t off, double v, int row, long col,
-                                          const EpiArgs& e) {
-  if constexpr (EPI == EPI_STORE) {
-    y[off] = v;
-  } else if constexpr (EPI == EPI_DIVIDE) {
-    const long j = col / e.nz;
-    const long kz = col - j * e.nz;
-    y[off] = v / (e.lx[row] + e.ly[j] + e.lz[kz] + e.alpha);
-  } else {  // EPI_ACCUM
-    y[off] += v;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // NN: Y[p][l][q] = sum_m G[m][l] X[p][m][q]
 // ---------------------------------------------------------------------------
@@ -88,32 +74,46 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
   const int wm = (wave >> 1) * 64;  // wave row offset within the tile (l)
   const int wn = (wave & 1) * 64;   // wave col offset within the tile (q)
 
-  // global -> register staging: element e = 0..7 of this thread covers
-  // row kk = tid/64 + 4*(e>>1), col c = tid%64 + 64*(e&1) of a [BK][128] tile.
+  // global -> register staging: element e = 0..7 of this thread covers row
+  // kk = tid/64 + 4*(e>>1), col c = tid%64 + 64*(e&1) of a [BK][128] tile.  Loads
+  // are branch-free: tensor columns past Q are clamped to a valid address (they
+  // only feed output columns that are never stored); contraction rows past L are
+  // clamped and zeroed (the padded factor rows are zero too).
+  // The rows of each wave are wave-uniform (row pointers in scalar registers,
+  // 32-bit lane offsets).
   double rg[8], rx[8];
   const int nchunk = (L + BK - 1) / BK;
+  const int r0 = __builtin_amdgcn_readfirstlane(tid >> 6), c0 = tid & 63;
+  const unsigned qa = (unsigned)(q0 + c0 < Q ? q0 + c0 : Q - 1);
+  const unsigned qb = (unsigned)(q0 + c0 + 64 < Q ? q0 + c0 + 64 : Q - 1);
+  const double* __restrict__ gw = g + (size_t)r0 * ldg + l0;
 
   auto load_chunk = [&](int c) {
     const int m0 = c * BK;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int kk = (tid >> 6) + 4 * (e >> 1);
-      const int cc = (tid & 63) + 64 * (e & 1);
-      rg[e] = g[(size_t)(m0 + kk) * ldg + l0 + cc];
-      const int m = m0 + kk;
-      const long q = q0 + cc;
-      rx[e] = (m < L && q < Q) ? xp[(size_t)m * Q + q] : 0.0;
+    for (int j = 0; j < 4; ++j) {
+      const double* __restrict__ gr = gw + (size_t)(m0 + 4 * j) * ldg;
+      rg[2 * j] = gr[c0];
+      rg[2 * j + 1] = gr[c0 + 64];
+      const int m = m0 + r0 + 4 * j;
+      const double* __restrict__ xr = xp + (size_t)(m < L ? m : L - 1) * Q;
+      rx[2 * j] = xr[qa];
+      rx[2 * j + 1] = xr[qb];
     }
   };
-  auto store_chunk = [&](int buf) {
+  // the zeroing of rows past L happens here, after the MFMA block, so that no wait
+  // for the loads in flight is needed before it
+  auto store_chunk = [&](int buf, int c) {
     double* sa = lds + buf * (2 * TILE_G);
     double* sb = sa + TILE_G;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int kk = (tid >> 6) + 4 * (e >> 1);
-      const int cc = (tid & 63) + 64 * (e & 1);
-      sa[kk * LDG + cc] = rg[e];
-      sb[kk * LDG + cc] = rx[e];
+    for (int j = 0; j < 4; ++j) {
+      const int kk = r0 + 4 * j;
+      const bool ok = c * BK + kk < L;
+      sa[kk * LDG + c0] = rg[2 * j];
+      sa[kk * LDG + c0 + 64] = rg[2 * j + 1];
+      sb[kk * LDG + c0] = ok ? rx[2 * j] : 0.0;
+      sb[kk * LDG + c0 + 64] = ok ? rx[2 * j + 1] : 0.0;
     }
   };
 
@@ -123,13 +123,9 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
   const int fr = lane & 15, fk = lane >> 4;
-  for (int c = 0; c < nchunk; ++c) {
-    if (c + 1 < nchunk) load_chunk(c + 1);
-    const double* sa = lds + (c & 1) * (2 * TILE_G);
+  auto compute_chunk = [&](int buf) {
+    const double* sa = lds + buf * (2 * TILE_G);
     const double* sb = sa + TILE_G;
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
@@ -143,22 +139,51 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (c + 1 < nchunk) store_chunk((c + 1) & 1);
+  };
+
+  // steady state: loads of chunk c+1 are in flight while chunk c is multiplied
+  load_chunk(0);
+  store_chunk(0, 0);
+  __syncthreads();
+  for (int c = 0; c + 1 < nchunk; ++c) {
+    load_chunk(c + 1);
+    // keep the LDS stores (which wait for the loads) after the whole MFMA block
+    __builtin_amdgcn_sched_barrier(0);
+    compute_chunk(c & 1);
+    __builtin_amdgcn_sched_barrier(0);
+    store_chunk((c + 1) & 1, c + 1);
     __syncthreads();
   }
+  compute_chunk((nchunk - 1) & 1);
 
   // f64 16x16 accumulator layout: lane, register r  ->  row 4r + lane/16, col lane%16
   double* __restrict__ yp = y + (size_t)p * L * Q;
+  double cden[4] = {0.0, 0.0, 0.0, 0.0};
+  if constexpr (EPI == EPI_DIVIDE) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long q = q0 + wn + 16 * j + fr;
+      const int qi = (int)(q < Q ? q : Q - 1);
+      const int jy = qi / (int)epi.nz;
+      cden[j] = epi.ly[jy] + epi.lz[qi - jy * (int)epi.nz] + epi.alpha;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int l = l0 + wm + 16 * i + 4 * r + fk;
       if (l >= L) continue;
+      double* __restrict__ yrow = yp + (size_t)l * Q;
+      const double lxl = EPI == EPI_DIVIDE ? epi.lx[l] : 0.0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const long q = q0 + wn + 16 * j + fr;
-        if (q < Q) store_out<EPI>(yp, (size_t)l * Q + q, acc[i][j][r], l, q, epi);
+        if (q >= Q) continue;
+        const double v = acc[i][j][r];
+        if constexpr (EPI == EPI_STORE) yrow[q] = v;
+        else if constexpr (EPI == EPI_DIVIDE) yrow[q] = v / (lxl + cden[j]);
+        else yrow[q] += v;
       }
     }
 }
@@ -185,34 +210,50 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
   const int wm = (wave >> 1) * 64;  // rows: p
   const int wn = (wave & 1) * 64;   // cols: l
 
+  // Factor tile [BK][128] as in the NN shape; tensor tile [128][BK]: element e of
+  // this thread is row r = tid/16 + 16 e, contraction column tid%16.  Rows past P
+  // are clamped to a valid address (their outputs are never stored); contraction
+  // columns past L are clamped and zeroed.
+  // Uniform tile base, 32-bit lane offsets (128 rows x L < 2^32 elements).
   double rg[8], rx[8];
   const int nchunk = (L + BK - 1) / BK;
+  const int r0 = __builtin_amdgcn_readfirstlane(tid >> 6), c0 = tid & 63;
+  const double* __restrict__ gw = g + (size_t)r0 * ldg + l0;
+  const int tr = tid >> 4, tc = tid & 15;
+  const double* __restrict__ tb = x + (size_t)p0 * L;
+  const int rmax = (int)(P - 1 - p0);
+  unsigned xoff[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int rr = tr + 16 * e;
+    xoff[e] = (unsigned)(rr < rmax ? rr : rmax) * (unsigned)L;
+  }
   auto load_chunk = [&](int c) {
     const int m0 = c * BK;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      // factor tile [BK][128]
-      const int kk = (tid >> 6) + 4 * (e >> 1);
-      const int cc = (tid & 63) + 64 * (e & 1);
-      rg[e] = g[(size_t)(m0 + kk) * ldg + l0 + cc];
-      // tensor tile [128][BK]: row r = tid/16 + 16 e, col tid%16
-      const int r = (tid >> 4) + 16 * e;
-      const int m = m0 + (tid & 15);
-      const long pp = p0 + r;
-      rx[e] = (m < L && pp < P) ? x[(size_t)pp * L + m] : 0.0;
+    for (int j = 0; j < 4; ++j) {
+      const double* __restrict__ gr = gw + (size_t)(m0 + 4 * j) * ldg;
+      rg[2 * j] = gr[c0];
+      rg[2 * j + 1] = gr[c0 + 64];
     }
+    const int m = m0 + tc;
+    const unsigned mm = (unsigned)(m < L ? m : L - 1);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rx[e] = tb[xoff[e] + mm];
   };
-  auto store_chunk = [&](int buf) {
+  // contraction columns past L are zeroed at LDS-store time (after the MFMA block)
+  auto store_chunk = [&](int buf, int c) {
+    const bool ok = c * BK + tc < L;
     double* st = lds + buf * (TILE_T_NT + TILE_G);
     double* sg = st + TILE_T_NT;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int kk = (tid >> 6) + 4 * (e >> 1);
-      const int cc = (tid & 63) + 64 * (e & 1);
-      sg[kk * LDG + cc] = rg[e];
-      const int r = (tid >> 4) + 16 * e;
-      st[r * LDT + (tid & 15)] = rx[e];
+    for (int j = 0; j < 4; ++j) {
+      const int kk = r0 + 4 * j;
+      sg[kk * LDG + c0] = rg[2 * j];
+      sg[kk * LDG + c0 + 64] = rg[2 * j + 1];
     }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) st[(tr + 16 * e) * LDT + tc] = ok ? rx[e] : 0.0;
   };
 
   d4_t acc[4][4];
@@ -221,13 +262,9 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
   const int fr = lane & 15, fk = lane >> 4;
-  for (int c = 0; c < nchunk; ++c) {
-    if (c + 1 < nchunk) load_chunk(c + 1);
-    const double* st = lds + (c & 1) * (TILE_T_NT + TILE_G);
+  auto compute_chunk = [&](int buf) {
+    const double* st = lds + buf * (TILE_T_NT + TILE_G);
     const double* sg = st + TILE_T_NT;
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
@@ -241,9 +278,21 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (c + 1 < nchunk) store_chunk((c + 1) & 1);
+  };
+
+  load_chunk(0);
+  store_chunk(0, 0);
+  __syncthreads();
+  for (int c = 0; c + 1 < nchunk; ++c) {
+    load_chunk(c + 1);
+    // keep the LDS stores (which wait for the loads) after the whole MFMA block
+    __builtin_amdgcn_sched_barrier(0);
+    compute_chunk(c & 1);
+    __builtin_amdgcn_sched_barrier(0);
+    store_chunk((c + 1) & 1, c + 1);
     __syncthreads();
   }
+  compute_chunk((nchunk - 1) & 1);
 
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -251,10 +300,15 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
     for (int r = 0; r < 4; ++r) {
       const long pp = p0 + wm + 16 * i + 4 * r + fk;
       if (pp >= P) continue;
+      double* __restrict__ yrow = y + (size_t)pp * L;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int l = l0 + wn + 16 * j + fr;
-        if (l < L) store_out<EPI>(y, (size_t)pp * L + l, acc[i][j][r], l, 0, epi);
+        if (l >= L) continue;
+        const double v = acc[i][j][r];
+        if constexpr (EPI == EPI_STORE) yrow[l] = v;
+        else if constexpr (EPI == EPI_DIVIDE) yrow[l] = v / (epi.lx[l] + epi.ly[0] + epi.lz[0] + epi.alpha);
+        else yrow[l] += v;
       }
     }
 }
