@@ -2,10 +2,17 @@
 solve of -Lap u + alpha u = f at n = 999 per axis (250^3 elements, alpha = 1,
 homogeneous Dirichlet on [-1, 1]^3, ~1e9 unknowns), on one MI355X.
 
-One step = one FP64 solve (sem_solve: six mode products with the fused
-eigenvalue divide) of a right-hand side already resident in HBM.
+Variants (each timed over K steps; one step = one complete solve of a right-hand
+side already resident in HBM):
+  f64     sem_solve: six FP64 mode products with the fused eigenvalue divide;
+  f32 / bf16 / bf16x3 refined
+          sem_solve_refined: low-precision mode products + FP64 residual and
+          update, iterated until ||delta|| <= 1e-11 ||u||  (every iteration,
+          residual and norm read-back inside the timed region).
+Each refined result is checked against the FP64 solve (relative max error); the
+headline value is the fastest variant within 1e-10.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--variants f64,bf16,...]
 
 Prints one JSON line.  Besides the headline value it reports the dominant
 kernel's roofline fraction (per-launch duration measured with HIP events on the
@@ -39,6 +46,8 @@ def main() -> int:
     ap.add_argument("--ne", type=int, default=250, help="elements per axis (250 -> n = 999)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=5)
+    ap.add_argument("--variants", default="f64,f32,bf16,bf16x3")
+    ap.add_argument("--tol", type=float, default=1e-11, help="refinement stop: ||delta|| <= tol ||u||")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain elementwise copy of f (N*8 bytes read + written) so that HBM "
                          "counters of the kernels can be scaled against a kernel of known traffic")
@@ -88,6 +97,34 @@ def main() -> int:
     value = N / (ms * 1e-3)
     log(f"FP64 solve: {ms:.2f} ms/step, {value:.3e} unknowns/s")
 
+    variants = {"f64": {"ms_per_solve": ms, "unknowns_per_s": value, "iterations": 1, "rel_err_vs_f64": 0.0}}
+    want = [v for v in args.variants.split(",") if v and v != "f64"]
+    if want:
+        ur = torch.empty_like(f)
+        scale = float(u.abs().max())
+        for prec in want:
+            _, it, rel, st = plan.solve_refined(f, ur, prec=prec, tol=args.tol, max_iter=40, raise_on_error=False)
+            torch.cuda.synchronize()
+            for _ in range(max(0, args.warmup - 1)):
+                plan.solve_refined(f, ur, prec=prec, tol=args.tol, max_iter=40, raise_on_error=False)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(args.steps):
+                _, it, rel, st = plan.solve_refined(f, ur, prec=prec, tol=args.tol, max_iter=40,
+                                                    raise_on_error=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            vms = e0.elapsed_time(e1) / args.steps
+            err = float((ur - u).abs().max()) / scale
+            variants[f"{prec}_refined"] = {"ms_per_solve": vms, "unknowns_per_s": N / (vms * 1e-3),
+                                           "iterations": it, "last_update_rel": rel, "status": st,
+                                           "rel_err_vs_f64": err}
+            log(f"{prec} refined: {vms:.2f} ms/solve, {N / (vms * 1e-3):.3e} unknowns/s, {it} iterations, "
+                f"rel err vs FP64 {err:.2e}, status {st}")
+        del ur
+    ok = {k: v for k, v in variants.items() if v["rel_err_vs_f64"] <= 1e-10 and v.get("status", 0) == 0}
+    best = max(ok, key=lambda k: ok[k]["unknowns_per_s"])
+
     # dominant kernel: the batched NN mode product (y axis), timed alone per launch
     tmp = torch.empty_like(f)
     plan.mode_product(1, False, f, tmp)
@@ -110,16 +147,18 @@ def main() -> int:
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": variants[best]["unknowns_per_s"],
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": variants[best]["ms_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if best == "f64" else best.split("_")[0] + " mode products, f64 residual/update",
+        "best_variant": best,
+        "variants": variants,
         "data": "synthetic: f = (3 pi^2 + 1) sin(pi x) sin(pi y) sin(pi z) + 1e-3 N(0,1), seed 2310",
         "config": {"workload": f"Q^4 SEM Helmholtz alpha=1, Dirichlet [-1,1]^3, {ne[0]}^3 elements, "
                                f"n={nx} per axis ({N} unknowns), FP64 fast-diagonalisation solve",

@@ -104,6 +104,21 @@ sem_status sem_mode_product(sem_plan *p, int axis, int inverse, const double *in
  * H = M^{-1} K (eq. matvec3D in H-form), FP64, matrix-free.  r must not alias u. */
 sem_status sem_residual(sem_plan *p, const double *u, const double *f, double *r);
 
+/* Mixed-precision solve with FP64 iterative refinement:
+ *   u = 0, r = f;  repeat  delta = FD_prec(r),  u += delta,  r = f - M_3^{-1} A u
+ *   until ||delta||_inf <= tol * ||u||_inf  (iterations <= max_iter).
+ * FD_prec is eq. 3D-Poisson with its six mode products in precision `prec`
+ * (SEM_F32, SEM_BF16, SEM_BF16X3; SEM_F64 performs one FP64 solve); the update
+ * of u and the residual are FP64.  tol = 0 runs exactly max_iter iterations.
+ * f, u: device arrays of n_x n_y n_z doubles; u must not alias f.  Synchronises
+ * the plan stream once per iteration (16-byte norm read-back).
+ * Outputs: *iters = iterations run, *last_update_rel = ||delta||/||u|| of the last
+ * one (either may be NULL).  Returns SEM_ENOCONV if tol > 0 was not met (u holds
+ * the last iterate) or the updates grew for two consecutive iterations, and
+ * SEM_ENONFINITE if an update became NaN / Inf. */
+sem_status sem_solve_refined(sem_plan *p, sem_prec prec, double tol, int max_iter, const double *f, double *u,
+                             int *iters, double *last_update_rel);
+
 /* Host-only helper (no device needed): the 1D operators of one axis as built by
  * sem_plan_create.  Call with all output pointers NULL to get n; then pass
  * buffers of n (x, mass, lam) and n*n (S, F, row-major) doubles; any output may

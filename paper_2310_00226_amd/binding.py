@@ -43,6 +43,8 @@ def _load():
         "sem_solve": (c_int, [c_void_p, c_void_p, c_void_p]),
         "sem_mode_product": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
         "sem_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "sem_solve_refined": (c_int, [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, POINTER(c_int),
+                                      POINTER(c_double)]),
         "sem_axis_host": (c_int, [c_int, c_int, c_double, c_double, c_int, POINTER(c_int), dp, dp, dp, dp, dp]),
         "sem_last_error": (c_char_p, []),
     }
@@ -155,6 +157,25 @@ class Plan:
         self._prepare(SEM_F64)
         check(lib.sem_solve(self._p, fp, up))
         return u
+
+    def solve_refined(self, f, u=None, prec: str = "bf16", tol: float = 1e-11, max_iter: int = 30,
+                      raise_on_error: bool = True):
+        """Mixed-precision solve with FP64 refinement (sem_solve_refined).
+
+        Returns (u, iterations, last relative update, status)."""
+        import torch
+        if u is None:
+            u = torch.empty_like(f)
+        pv = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        fp = _dev_ptr(f, "f", self.numel, torch.float64)
+        up = _dev_ptr(u, "u", self.numel, torch.float64)
+        self._prepare(pv)
+        it = c_int(0)
+        rel = c_double(0.0)
+        st = lib.sem_solve_refined(self._p, pv, float(tol), int(max_iter), fp, up, ctypes.byref(it), ctypes.byref(rel))
+        if raise_on_error:
+            check(st)
+        return u, it.value, rel.value, st
 
     def mode_product(self, axis: int, inverse: bool, x, out=None):
         import torch

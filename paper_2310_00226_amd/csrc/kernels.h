@@ -26,9 +26,53 @@ struct EpiArgs {
 hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg, const int dims[3], int axis, int epi,
                            const EpiArgs& ea, hipStream_t stream);
 
+// ---- low-precision rotating mode products (mode_lp.hip) ----
+enum { LP_F32 = 1, LP_BF16 = 2, LP_BF16X3 = 3 };
+
+// Epilogue arguments: divide by l0[l] + l1[a] + l2[b] + alpha (third forward
+// pass), or accumulate into FP64 (first = 1: u = delta) recording
+// norms[0] = max|delta|, norms[1] = max|u| (bit patterns, atomic max).
+struct EpiLP {
+  const double* l0 = nullptr;
+  const double* l1 = nullptr;
+  const double* l2 = nullptr;
+  double alpha = 0.0;
+  int first = 0;
+  unsigned long long* norms = nullptr;
+};
+
+// One pass  Y[l][a][b] = sum_k F[l][k] X[a][b][k]:
+//   x: input rows (P = A*B rows of K elements, row pitch ldx), kind in_kind
+//      (0 FP64, 1 FP32, 2 BF16 bits);
+//   y: output (L, A, B) with row pitch ldy, kind out_kind (1 FP32, 2 BF16, 0 FP64
+//      accumulate);
+//   f_hi / f_lo: factor [l][k] (FP32 or BF16 bits), padded with zeros to ldf
+//      columns and to a multiple of 128 rows.
+struct LpPass {
+  int mode = LP_BF16;
+  const void* x = nullptr;
+  int ldx = 0;
+  long P = 0;
+  int K = 0;
+  void* y = nullptr;
+  int ldy = 0;
+  int A = 0, B = 0, L = 0;
+  const void* f_hi = nullptr;
+  const void* f_lo = nullptr;
+  int ldf = 0;
+  int in_kind = 0, out_kind = 0, epi_kind = EPI_STORE;
+  EpiLP epi;
+};
+hipError_t launch_mode_lp(const LpPass& ps, hipStream_t stream);
+
 // Nodal residual r = f - alpha u - (H_x + H_y + H_z) u with banded H rows
 // hb[a][g * (2k+1) + d] = H_a(g, g - k + d).
 hipError_t launch_residual_f64(const double* u, const double* f, double* r, const double* const hb[3], int k,
                                const int dims[3], double alpha, hipStream_t stream);
+
+// Same residual, written with row pitch ldr as FP32 (r_kind 1) or BF16 (2) for
+// the low-precision solves of the refinement loop.
+hipError_t launch_residual_lp(const double* u, const double* f, void* r, int r_kind, int ldr, const double* const hb[3],
+                              int k, const int dims[3], double alpha, hipStream_t stream);
 
 }  // namespace semfd

@@ -23,6 +23,13 @@ struct sem_plan {
   double* d_gb[3] = {nullptr, nullptr, nullptr};  // backward factor S, stored G[m][l] = S[l][m]
   double* d_lam[3] = {nullptr, nullptr, nullptr};
   double* d_hb[3] = {nullptr, nullptr, nullptr};  // banded rows of H = M^{-1} K
+  // low-precision factors (created on first use): [axis][0 = forward, 1 = backward],
+  // layout [l][k], zero-padded to lp_ld x lp_ld
+  void* lp_f32[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  void* lp_hi[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  void* lp_lo[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  int lp_ld[3] = {0, 0, 0};
+  int lp_ready = 0;
   // execution
   hipStream_t stream = nullptr;
   void* ws = nullptr;

@@ -1,21 +1,265 @@
-// Workspace sizing and (later) the mixed-precision paths.
+// Mixed-precision solve with FP64 iterative refinement.
+//
+//   u = 0, r = f
+//   repeat: delta = S_3 [ (F_3 r) ./ (Lambda3D + alpha) ]   (mode products in low precision)
+//           u += delta                                      (FP64, fused into the last pass)
+//           r  = f - M_3^{-1} A u                           (FP64 matrix-free residual)
+//   until ||delta||_inf <= tol ||u||_inf.
+// The low-precision solve is eq. 3D-Poisson of the paper (Sec. 2.4) with its
+// mode products rounded to FP32 / BF16; the refinement around it is not in the
+// paper (its single-precision runs plateau without it, Table 10).
+//
+// Each low-precision solve is six rotating mode products (mode_lp.hip):
+//   (x,y,z) -z-> (z,x,y) -y-> (y,z,x) -x,divide-> (x,y,z) -z-> (z,x,y) -y-> (y,z,x) -x-> u
+// Intermediates live in the workspace with their contiguous axis padded to a
+// multiple of 8 elements (16-byte rows for BF16).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "kernels.h"
 #include "plan_internal.h"
 
 namespace semfd {
 
+namespace {
+
+inline int pad8(int n) { return (n + 7) / 8 * 8; }
+inline int pad128(int n) { return (n + 127) / 128 * 128; }
+
+unsigned short host_f2bf(float f) {
+  unsigned u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+float host_bf2f(unsigned short b) {
+  unsigned u = ((unsigned)b) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+size_t lp_elem(sem_prec prec) { return prec == SEM_BF16 ? 2 : 4; }
+
+// largest of the three rotated padded layouts (z,x,y'), (y,z,x'), (x,y,z')
+size_t lp_tmp_elems(const sem_plan* p) {
+  const size_t nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
+  return std::max({nz * nx * (size_t)pad8((int)ny), ny * nz * (size_t)pad8((int)nx), nx * ny * (size_t)pad8((int)nz)});
+}
+
+// residual buffer of the refinement: (nx, ny, pad8(nz)) in the intermediate type
+size_t lp_r_bytes(const sem_plan* p, sem_prec prec) {
+  const size_t e = (size_t)p->dims[0] * p->dims[1] * pad8(p->dims[2]) * lp_elem(prec);
+  return ((e + 255) / 256) * 256;
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+}  // namespace
+
 size_t workspace_need(const sem_plan* p, sem_prec prec) {
   const size_t n = p->N;
   switch (prec) {
     case SEM_F64:
       return ((n * sizeof(double) + 255) / 256) * 256;
+    case SEM_F32:
+    case SEM_BF16:
+    case SEM_BF16X3: {
+      const size_t r = lp_r_bytes(p, prec);
+      const size_t t = ((lp_tmp_elems(p) * lp_elem(prec) + 255) / 256) * 256;
+      return r + 2 * t + 256;
+    }
     default:
       return 0;
   }
 }
 
-void release_lowp(sem_plan*) {}
+void release_lowp(sem_plan* p) {
+  for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < 2; ++d) {
+      (void)hipFree(p->lp_f32[a][d]);
+      (void)hipFree(p->lp_hi[a][d]);
+      (void)hipFree(p->lp_lo[a][d]);
+      p->lp_f32[a][d] = p->lp_hi[a][d] = p->lp_lo[a][d] = nullptr;
+    }
+  p->lp_ready = 0;
+}
+
+// Low-precision copies of the factors, layout [l][k] (row l = output mode,
+// contraction k contiguous), zero-padded to pad128(n) x pad128(n).
+static sem_status ensure_lowp(sem_plan* p) {
+  if (p->lp_ready) return SEM_OK;
+  for (int a = 0; a < 3; ++a) {
+    const int n = p->dims[a], ld = pad128(n);
+    p->lp_ld[a] = ld;
+    for (int d = 0; d < 2; ++d) {
+      const std::vector<double>& M = d == 0 ? p->ax[a].F : p->ax[a].S;
+      std::vector<float> f32((size_t)ld * ld, 0.0f);
+      std::vector<unsigned short> hi((size_t)ld * ld, 0), lo((size_t)ld * ld, 0);
+      for (int l = 0; l < n; ++l)
+        for (int k = 0; k < n; ++k) {
+          const double v = M[(size_t)l * n + k];
+          const float fv = (float)v;
+          f32[(size_t)l * ld + k] = fv;
+          const unsigned short h = host_f2bf(fv);
+          hi[(size_t)l * ld + k] = h;
+          lo[(size_t)l * ld + k] = host_f2bf((float)(v - (double)host_bf2f(h)));
+        }
+      hipError_t e;
+      if ((e = hipMalloc(&p->lp_f32[a][d], f32.size() * 4)) != hipSuccess ||
+          (e = hipMemcpy(p->lp_f32[a][d], f32.data(), f32.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+          (e = hipMalloc(&p->lp_hi[a][d], hi.size() * 2)) != hipSuccess ||
+          (e = hipMemcpy(p->lp_hi[a][d], hi.data(), hi.size() * 2, hipMemcpyHostToDevice)) != hipSuccess ||
+          (e = hipMalloc(&p->lp_lo[a][d], lo.size() * 2)) != hipSuccess ||
+          (e = hipMemcpy(p->lp_lo[a][d], lo.data(), lo.size() * 2, hipMemcpyHostToDevice)) != hipSuccess) {
+        release_lowp(p);
+        return hip_fail(e, "low-precision factor upload");
+      }
+    }
+  }
+  p->lp_ready = 1;
+  return SEM_OK;
+}
+
+// One low-precision FD solve of `src`, accumulated into u.  src is the FP64
+// right-hand side in the caller's layout (src_lp = 0) or the residual in the
+// intermediate type with row pitch pad8(nz) (src_lp = 1).
+static hipError_t lp_solve(sem_plan* p, sem_prec prec, const void* src, int src_lp, double* u, void* t0, void* t1,
+                           unsigned long long* norms, int first) {
+  const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
+  const int mode = prec == SEM_F32 ? LP_F32 : prec == SEM_BF16 ? LP_BF16 : LP_BF16X3;
+  const int lpk = prec == SEM_BF16 ? 2 : 1;  // intermediate kind
+  auto fac = [&](int axis, int dir, LpPass& ps) {
+    if (mode == LP_F32) {
+      ps.f_hi = p->lp_f32[axis][dir];
+      ps.f_lo = nullptr;
+    } else {
+      ps.f_hi = p->lp_hi[axis][dir];
+      ps.f_lo = p->lp_lo[axis][dir];
+    }
+    ps.ldf = p->lp_ld[axis];
+  };
+  // the six passes: (input, ldx, A, B, K) -> (output, ldy); axis contracted = K's axis
+  struct Step {
+    const void* x;
+    int ldx, A, B, K, axis, dir;
+    void* y;
+    int ldy, in_kind, out_kind, epi;
+  };
+  const Step st[6] = {
+      {src, src_lp ? pad8(nz) : nz, nx, ny, nz, 2, 0, t0, pad8(ny), src_lp ? lpk : 0, lpk, EPI_STORE},
+      {t0, pad8(ny), nz, nx, ny, 1, 0, t1, pad8(nx), lpk, lpk, EPI_STORE},
+      {t1, pad8(nx), ny, nz, nx, 0, 0, t0, pad8(nz), lpk, lpk, EPI_DIVIDE},
+      {t0, pad8(nz), nx, ny, nz, 2, 1, t1, pad8(ny), lpk, lpk, EPI_STORE},
+      {t1, pad8(ny), nz, nx, ny, 1, 1, t0, pad8(nx), lpk, lpk, EPI_STORE},
+      {t0, pad8(nx), ny, nz, nx, 0, 1, u, nz, lpk, 0, EPI_ACCUM},
+  };
+  for (int s = 0; s < 6; ++s) {
+    LpPass ps;
+    ps.mode = mode;
+    ps.x = st[s].x;
+    ps.ldx = st[s].ldx;
+    ps.P = (long)st[s].A * st[s].B;
+    ps.K = st[s].K;
+    ps.y = st[s].y;
+    ps.ldy = st[s].ldy;
+    ps.A = st[s].A;
+    ps.B = st[s].B;
+    ps.L = st[s].K;
+    fac(st[s].axis, st[s].dir, ps);
+    ps.in_kind = st[s].in_kind;
+    ps.out_kind = st[s].out_kind;
+    ps.epi_kind = st[s].epi;
+    if (st[s].epi == EPI_DIVIDE) {
+      // output (x, y, z): l = x mode, a = y mode, b = z mode
+      ps.epi.l0 = p->d_lam[0];
+      ps.epi.l1 = p->d_lam[1];
+      ps.epi.l2 = p->d_lam[2];
+      ps.epi.alpha = p->alpha;
+    }
+    if (st[s].epi == EPI_ACCUM) {
+      ps.epi.first = first;
+      ps.epi.norms = norms;
+    }
+    hipError_t e = launch_mode_lp(ps, p->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 }  // namespace semfd
+
+using namespace semfd;
+
+extern "C" sem_status sem_solve_refined(sem_plan* p, sem_prec prec, double tol, int max_iter, const double* f,
+                                        double* u, int* iters, double* last_update_rel) {
+  if (!p || !f || !u || max_iter < 1 || !(tol >= 0.0) || !std::isfinite(tol))
+    return set_error(SEM_EINVAL, "sem_solve_refined: invalid argument");
+  if (f == u) return set_error(SEM_EINVAL, "sem_solve_refined: u must not alias f");
+  if (iters) *iters = 0;
+  if (last_update_rel) *last_update_rel = NAN;
+  if (prec == SEM_F64) {
+    sem_status st = sem_solve(p, f, u);
+    if (st == SEM_OK && iters) *iters = 1;
+    if (st == SEM_OK && last_update_rel) *last_update_rel = 0.0;
+    return st;
+  }
+  if (prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3)
+    return set_error(SEM_EINVAL, "sem_solve_refined: unknown precision");
+  if (p->dims[0] > 46340 || (long)p->dims[1] * p->dims[2] > 0x7fffffffL ||
+      (long)p->dims[0] * p->dims[2] > 0x7fffffffL || (long)p->dims[0] * p->dims[1] > 0x7fffffffL)
+    return set_error(SEM_EINVAL, "sem_solve_refined: problem too large for the low-precision kernels");
+  sem_status st = ensure_lowp(p);
+  if (st != SEM_OK) return st;
+  void* ws = nullptr;
+  st = plan_workspace(p, workspace_need(p, prec), &ws);
+  if (st != SEM_OK) return st;
+  char* w = (char*)ws;
+  void* r = w;
+  const size_t rbytes = lp_r_bytes(p, prec);
+  const int rkind = prec == SEM_BF16 ? 2 : 1;
+  const size_t tbytes = ((lp_tmp_elems(p) * lp_elem(prec) + 255) / 256) * 256;
+  void* t0 = w + rbytes;
+  void* t1 = w + rbytes + tbytes;
+  unsigned long long* norms = (unsigned long long*)(w + rbytes + 2 * tbytes);
+  const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
+
+  double prev = INFINITY, prev2 = INFINITY;
+  for (int it = 0; it < max_iter; ++it) {
+    hipError_t e;
+    if (it > 0 && (e = launch_residual_lp(u, f, r, rkind, pad8(p->dims[2]), hb, p->k, p->dims, p->alpha,
+                                          p->stream)) != hipSuccess)
+      return hip_fail(e, "sem_solve_refined: residual");
+    zero_u64_kernel<<<1, 64, 0, p->stream>>>(norms, 2);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sem_solve_refined: norm reset");
+    if ((e = lp_solve(p, prec, it == 0 ? (const void*)f : (const void*)r, it == 0 ? 0 : 1, u, t0, t1, norms,
+                      it == 0 ? 1 : 0)) != hipSuccess)
+      return hip_fail(e, "sem_solve_refined: low-precision solve");
+    unsigned long long hn[2];
+    if ((e = hipMemcpyAsync(hn, norms, sizeof(hn), hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(p->stream)) != hipSuccess)
+      return hip_fail(e, "sem_solve_refined: norm readback");
+    double dmax, umax;
+    std::memcpy(&dmax, &hn[0], 8);
+    std::memcpy(&umax, &hn[1], 8);
+    if (iters) *iters = it + 1;
+    if (!std::isfinite(dmax) || !std::isfinite(umax))
+      return set_error(SEM_ENONFINITE, "sem_solve_refined: non-finite update");
+    const double rel = umax > 0 ? dmax / umax : (dmax > 0 ? INFINITY : 0.0);
+    if (last_update_rel) *last_update_rel = rel;
+    if (tol > 0 && rel <= tol) return SEM_OK;
+    if (it >= 2 && rel > prev && prev > prev2)
+      return set_error(SEM_ENOCONV, "sem_solve_refined: updates grow; refinement diverges at this precision");
+    prev2 = prev;
+    prev = rel;
+  }
+  if (tol > 0) return set_error(SEM_ENOCONV, "sem_solve_refined: tolerance not met within max_iter");
+  return SEM_OK;
+}

@@ -1,0 +1,109 @@
+"""GPU parity of the mixed-precision refined solve (FP32 / BF16 / split-BF16 mode
+products, FP64 residual and update) against the FP64 oracle (needs an MI355X).
+
+Bar: the refined solution meets ||u - u_oracle||_inf <= 1e-10 ||u_oracle||_inf
+(+ 10x the oracle's own FP64 rounding floor for white-noise right-hand sides).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import helmholtz_rhs, normal_noise
+
+pytestmark = pytest.mark.gpu
+
+TOL_REFINED = 1e-10
+PRECS = ["f32", "bf16", "bf16x3"]
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2310_00226_amd as P
+    return P
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _bound(u_ref, f, prob):
+    floor = np.max(np.abs(u_ref - O.fd_solve(prob, f, order=(0, 1, 2))))
+    return TOL_REFINED * np.max(np.abs(u_ref)) + 10 * floor
+
+
+CASES = [
+    (4, (8, 8, 8), (-1, 1, -1, 1, -1, 1), 0.0, "dirichlet", "smooth"),
+    (4, (40, 33, 37), (-1, 1, -1, 1, -1, 1), 1.0, "dirichlet", "smooth"),
+    (3, (50, 45, 43), (0, 2, -1, 1, 0, 3), 0.5, "neumann", "noise"),
+    (5, (20, 31, 26), (-1, 1, -1, 1, -1, 1), 2.0, "dirichlet", "noise"),
+    (2, (1, 1, 1), (-1, 1, -1, 1, -1, 1), 0.0, "dirichlet", "noise"),
+    (2, (2, 2, 1), (-1, 1, -1, 1, -1, 1), 1.0, "dirichlet", "noise"),
+    (1, (200, 3, 1), (0, 1, 0, 1, 0, 1), 1.0, "neumann", "noise"),
+    (6, (3, 20, 17), (0, 1, 0, 5, -1, 1), 3.0, "neumann", "noise"),
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"k{c[0]}-{c[1]}-{c[4]}-{c[5]}")
+def test_refined_parity(torch, P, case, prec):
+    k, ne, box, alpha, bc, kind = case
+    _log(f"[refined] {prec} k={k} ne={ne} {bc} {kind}")
+    prob = O.Problem(k, ne, box, alpha, bc)
+    plan = P.Plan(k, ne, box, alpha, bc)
+    if kind == "smooth":
+        f = helmholtz_rhs(*(o.x for o in prob.axes), alpha)
+    else:
+        f = normal_noise(prob.shape, seed=31 + k)
+    u_ref = O.fd_solve(prob, f)
+    u, iters, rel, st = plan.solve_refined(_dev(torch, f), prec=prec, tol=1e-12, max_iter=40)
+    u = u.cpu().numpy()
+    err = np.max(np.abs(u - u_ref))
+    _log(f"    iters={iters} last_rel={rel:.2e} err={err / np.max(np.abs(u_ref)):.2e}")
+    assert err <= _bound(u_ref, f, prob), (err, iters, rel)
+
+
+def test_refined_stops_without_convergence(torch, P):
+    # one iteration cannot meet 1e-16: SEM_ENOCONV, u holds the first iterate
+    plan = P.Plan(4, (10, 10, 10), (-1, 1, -1, 1, -1, 1), 1.0, "dirichlet")
+    f = _dev(torch, normal_noise(plan.shape, seed=4))
+    u, iters, rel, st = plan.solve_refined(f, prec="bf16", tol=1e-16, max_iter=1, raise_on_error=False)
+    assert st == 5 and iters == 1 and rel > 1e-16
+
+
+def test_refined_fixed_iterations(torch, P):
+    # tol = 0 runs exactly max_iter iterations
+    plan = P.Plan(3, (10, 12, 9), (-1, 1, -1, 1, -1, 1), 1.0, "dirichlet")
+    f = _dev(torch, normal_noise(plan.shape, seed=6))
+    u, iters, rel, st = plan.solve_refined(f, prec="f32", tol=0.0, max_iter=3)
+    assert st == 0 and iters == 3
+
+
+def test_refined_full_size_n999(torch, P):
+    k, ne, box, alpha = 4, (250, 250, 250), (-1, 1, -1, 1, -1, 1), 1.0
+    plan = P.Plan(k, ne, box, alpha, "dirichlet")
+    prob = O.Problem(k, ne, box, alpha, "dirichlet")
+    f = helmholtz_rhs(*(o.x for o in prob.axes), alpha)
+    _log("[n999 refined] oracle solve")
+    u_ref = O.fd_solve(prob, f)
+    scale = np.max(np.abs(u_ref))
+    fd = _dev(torch, f)
+    ud = torch.empty_like(fd)
+    for prec in PRECS:
+        _log(f"[n999 refined] {prec}")
+        _, iters, rel, st = plan.solve_refined(fd, ud, prec=prec, tol=1e-11, max_iter=40)
+        err = float((ud.cpu() - torch.from_numpy(u_ref)).abs().max()) / scale
+        _log(f"    iters={iters} last_rel={rel:.2e} rel err vs oracle {err:.2e}")
+        assert err <= TOL_REFINED
