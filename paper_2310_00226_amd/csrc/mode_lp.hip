@@ -36,8 +36,17 @@ typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
 
 namespace lpk {
 
-constexpr int BM = 128, BN = 128;
-constexpr int NTHREADS = 256;
+// Block tile BM (l) x BN (p) on WL x WP waves; each wave owns a (BM/WL) x (BN/WP)
+// sub-tile of 16 x 16 MFMA tiles.
+template <int BM_, int BN_, int WL_, int WP_>
+struct Tile {
+  static constexpr int BM = BM_, BN = BN_, WL = WL_, WP = WP_;
+  static constexpr int NTHREADS = 64 * WL * WP;
+  static constexpr int TL = BM / WL, TP = BN / WP;  // wave tile
+  static constexpr int FL = TL / 16, FP = TP / 16;  // MFMA tiles per wave
+};
+typedef Tile<128, 128, 2, 2> TileS;  // 4 waves, 64 x 64 per wave
+typedef Tile<256, 256, 2, 4> TileL;  // 8 waves, 128 x 64 per wave
 
 // float -> bf16 bits, round to nearest even (NaN kept quiet)
 __device__ __forceinline__ unsigned short f2bf(float f) {
@@ -75,14 +84,16 @@ struct OpT<LP_F32> {
 // BK (contraction chunk): 32 for FP32 (8 MFMA steps of 4), for FP64 input
 // (register budget) and for split BF16 (four LDS tiles); 64 otherwise (2 BF16
 // MFMA steps of 32).
-template <int MODE, class TIn>
+template <int MODE, class TIn, class TT>
 struct Cfg {
+  static constexpr int BM = TT::BM, BN = TT::BN, NTHREADS = TT::NTHREADS;
   static constexpr int BK = (MODE == LP_F32 || MODE == LP_BF16X3 || sizeof(TIn) == 8) ? 32 : 64;
   typedef typename OpT<MODE>::type op_t;
   static constexpr int PAD = 16 / (int)sizeof(op_t);      // 16 bytes of row padding
   static constexpr int LDS_ROW = BK + PAD;                 // elements per LDS row
   static constexpr int NSPLIT = MODE == LP_BF16X3 ? 2 : 1;  // hi (+ lo) copies
-  static constexpr int TILE = BM * LDS_ROW;                 // elements per [128][BK] tile
+  static_assert(BM == BN, "factor and tensor tiles share one row count");
+  static constexpr int TILE = BM * LDS_ROW;                 // elements per [BM][BK] tile
   // tensor staging: each thread handles groups of G consecutive contraction
   // elements (16 bytes of operand type); a group is read with 16-byte vector
   // loads, or 8-byte loads for FP64 input (whose rows may be odd-sized).
@@ -95,15 +106,16 @@ struct Cfg {
   static constexpr int NLOAD_F = BM * BK / VEC_F / NTHREADS;
 };
 
-template <int MODE, class TIn, class TOut, int EPI>
-__global__ __launch_bounds__(NTHREADS, 2) void mode_rot_lp(const TIn* __restrict__ x, int ldx, long P, int K,
+template <int MODE, class TIn, class TOut, int EPI, class TT>
+__global__ __launch_bounds__(TT::NTHREADS) void mode_rot_lp(const TIn* __restrict__ x, int ldx, long P, int K,
                                                            TOut* __restrict__ y, int ldy, int A, int B, int L,
                                                            const void* __restrict__ f_hi,
                                                            const void* __restrict__ f_lo, int ldf, long tiles_l,
                                                            long ntiles, long nblocks_padded, EpiLP epi) {
-  typedef Cfg<MODE, TIn> C;
+  typedef Cfg<MODE, TIn, TT> C;
   typedef typename C::op_t op_t;
   constexpr int BK = C::BK, LR = C::LDS_ROW, NS = C::NSPLIT;
+  constexpr int BM = TT::BM, BN = TT::BN, NTHREADS = TT::NTHREADS, FL = TT::FL, FP = TT::FP;
   // per stage: NS factor tiles + NS tensor tiles
   __shared__ __attribute__((aligned(16))) op_t lds[2 * 2 * NS * C::TILE];
 
@@ -115,8 +127,8 @@ __global__ __launch_bounds__(NTHREADS, 2) void mode_rot_lp(const TIn* __restrict
   const long p0 = pt * BN;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64;  // rows: l
-  const int wn = (wave & 1) * 64;   // cols: p
+  const int wm = (wave / TT::WP) * TT::TL;  // rows: l
+  const int wn = (wave % TT::WP) * TT::TP;  // cols: p
 
   // ---- global load mapping -------------------------------------------------
   // Consecutive lanes take consecutive groups of one row, so loads are contiguous.
@@ -174,12 +186,24 @@ __global__ __launch_bounds__(NTHREADS, 2) void mode_rot_lp(const TIn* __restrict
       *reinterpret_cast<us8_t*>(sf_hi + row * LR + kk) = rf_hi[v];
       if constexpr (NS == 2) *reinterpret_cast<us8_t*>(sf_lo + row * LR + kk) = rf_lo[v];
     }
+    constexpr bool passthrough = NS == 1 && sizeof(TIn) == sizeof(op_t);
 #pragma unroll
     for (int g = 0; g < C::NGROUP; ++g) {
       const int idx = g * NTHREADS + tid;
       const int row = idx / G_PER_ROW;
       const int kg = (idx % G_PER_ROW) * C::G;
-      // gather the group as floats (or pass through when no conversion is needed)
+      if constexpr (passthrough) {
+        // same element type in HBM and LDS: store the loaded 16 bytes as they are
+        xvec_t v = rx[g][0];
+        if (tail) {
+#pragma unroll
+          for (int e = 0; e < C::G; ++e)
+            if (k0 + kg + e >= K) v[e] = (TIn)0;
+        }
+        *reinterpret_cast<xvec_t*>(sx_hi + row * LR + kg) = v;
+        continue;
+      }
+      // gather the group as floats and convert
       float fv[C::G];
 #pragma unroll
       for (int v = 0; v < C::LOADS_PER_G; ++v)
@@ -206,11 +230,11 @@ __global__ __launch_bounds__(NTHREADS, 2) void mode_rot_lp(const TIn* __restrict
     }
   };
 
-  f4_t acc[4][4];
+  f4_t acc[FL][FP];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FL; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < FP; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
   const int fr = lane & 15, fg = lane >> 4;
   auto compute_chunk = [&](int buf) {
@@ -222,36 +246,36 @@ __global__ __launch_bounds__(NTHREADS, 2) void mode_rot_lp(const TIn* __restrict
     if constexpr (MODE == LP_F32) {
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
-        float a[4], b[4];
+        float a[FL], b[FP];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = sf_hi[(wm + 16 * i + fr) * LR + ks * 4 + fg];
+        for (int i = 0; i < FL; ++i) a[i] = sf_hi[(wm + 16 * i + fr) * LR + ks * 4 + fg];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = sx_hi[(wn + 16 * j + fr) * LR + ks * 4 + fg];
+        for (int j = 0; j < FP; ++j) b[j] = sx_hi[(wn + 16 * j + fr) * LR + ks * 4 + fg];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FL; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     } else {
 #pragma unroll
       for (int ks = 0; ks < BK / 32; ++ks) {
-        bf8_t a[4], b[4], alo[NS == 2 ? 4 : 1], blo[NS == 2 ? 4 : 1];
+        bf8_t a[FL], b[FP], alo[NS == 2 ? FL : 1], blo[NS == 2 ? FP : 1];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < FL; ++i) {
           const int off = (wm + 16 * i + fr) * LR + ks * 32 + 8 * fg;
           a[i] = *reinterpret_cast<const bf8_t*>(sf_hi + off);
           if constexpr (NS == 2) alo[i] = *reinterpret_cast<const bf8_t*>(sf_lo + off);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < FP; ++j) {
           const int off = (wn + 16 * j + fr) * LR + ks * 32 + 8 * fg;
           b[j] = *reinterpret_cast<const bf8_t*>(sx_hi + off);
           if constexpr (NS == 2) blo[j] = *reinterpret_cast<const bf8_t*>(sx_lo + off);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FL; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
+          for (int j = 0; j < FP; ++j) {
             if constexpr (NS == 2) {
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], b[j], acc[i][j], 0, 0, 0);
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], blo[j], acc[i][j], 0, 0, 0);
@@ -276,10 +300,10 @@ __global__ __launch_bounds__(NTHREADS, 2) void mode_rot_lp(const TIn* __restrict
   compute_chunk((nchunk - 1) & 1);
 
   // ---- epilogue: f32 16x16 layout: lane, reg r -> row 4*(lane/16) + r, col lane%16
-  int aidx[4], bidx[4];
-  bool pok[4];
+  int aidx[FP], bidx[FP];
+  bool pok[FP];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < FP; ++j) {
     const long p = p0 + wn + 16 * j + fr;
     pok[j] = p < P;
     const int pi = (int)(pok[j] ? p : 0);
@@ -287,20 +311,18 @@ __global__ __launch_bounds__(NTHREADS, 2) void mode_rot_lp(const TIn* __restrict
     bidx[j] = pi - aidx[j] * B;
   }
   double dmax = 0.0, umax = 0.0;
-  double dab[4] = {0.0, 0.0, 0.0, 0.0};  // divide: l1[a] + l2[b] + alpha per column
-  if constexpr (EPI == EPI_DIVIDE) {
+  double dab[FP];  // divide: l1[a] + l2[b] + alpha per column
 #pragma unroll
-    for (int j = 0; j < 4; ++j) dab[j] = epi.l1[aidx[j]] + epi.l2[bidx[j]] + epi.alpha;
-  }
+  for (int j = 0; j < FP; ++j) dab[j] = EPI == EPI_DIVIDE ? epi.l1[aidx[j]] + epi.l2[bidx[j]] + epi.alpha : 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FL; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int l = l0 + wm + 16 * i + 4 * fg + r;
       if (l >= L) continue;
       const double dl = EPI == EPI_DIVIDE ? epi.l0[l] : 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < FP; ++j) {
         if (!pok[j]) continue;
         const size_t off = ((size_t)l * A + aidx[j]) * ldy + bidx[j];
         const float v = acc[i][j][r];
@@ -309,7 +331,7 @@ __global__ __launch_bounds__(NTHREADS, 2) void mode_rot_lp(const TIn* __restrict
           // the quotient is rounded to FP32 / BF16 anyway: a fast float divide suffices
           if constexpr (EPI == EPI_DIVIDE) w = __fdividef(v, (float)(dl + dab[j]));
           if constexpr (sizeof(TOut) == 2)
-            y[off] = f2bf(w);
+            y[off] = __builtin_bit_cast(unsigned short, (__bf16)w);
           else
             y[off] = (TOut)w;
         } else {  // EPI_ACCUM into FP64 (TOut = double)
@@ -342,18 +364,30 @@ __global__ __launch_bounds__(NTHREADS, 2) void mode_rot_lp(const TIn* __restrict
 }  // namespace lpk
 
 // ---------------------------------------------------------------------------
-template <int MODE, class TIn, class TOut, int EPI>
-static hipError_t launch_one(const LpPass& ps, hipStream_t stream) {
+template <int MODE, class TIn, class TOut, int EPI, class TT>
+static hipError_t launch_tile(const LpPass& ps, hipStream_t stream) {
   using namespace lpk;
-  const long tiles_l = (ps.L + BM - 1) / BM;
-  const long tiles_p = (ps.P + BN - 1) / BN;
+  const long tiles_l = (ps.L + TT::BM - 1) / TT::BM;
+  const long tiles_p = (ps.P + TT::BN - 1) / TT::BN;
   const long ntiles = tiles_l * tiles_p;
   const long nbp = ((ntiles + 7) / 8) * 8;
   if (nbp > 0x7fffffffL || ntiles == 0) return ntiles == 0 ? hipSuccess : hipErrorInvalidValue;
-  mode_rot_lp<MODE, TIn, TOut, EPI><<<dim3((unsigned)nbp), dim3(NTHREADS), 0, stream>>>(
+  mode_rot_lp<MODE, TIn, TOut, EPI, TT><<<dim3((unsigned)nbp), dim3(TT::NTHREADS), 0, stream>>>(
       (const TIn*)ps.x, ps.ldx, ps.P, ps.K, (TOut*)ps.y, ps.ldy, ps.A, ps.B, ps.L, ps.f_hi, ps.f_lo, ps.ldf, tiles_l,
       ntiles, nbp, ps.epi);
   return hipGetLastError();
+}
+
+// The 256 x 256 tile halves the L2 traffic per flop of the BF16 modes (whose
+// passes are bound by it); it is used when padding the factor rows to 256 costs
+// no more than ~8 % extra work and the tensor has enough rows to fill the chip.
+// The FP32 mode is MFMA-bound and keeps the 128 x 128 tile.
+template <int MODE, class TIn, class TOut, int EPI>
+static hipError_t launch_one(const LpPass& ps, hipStream_t stream) {
+  const long pad256 = (ps.L + 255) / 256 * 256;
+  if (MODE != LP_F32 && ps.P >= 65536 && pad256 * 100 <= (long)ps.L * 108 && ps.ldf >= pad256)
+    return launch_tile<MODE, TIn, TOut, EPI, lpk::TileL>(ps, stream);
+  return launch_tile<MODE, TIn, TOut, EPI, lpk::TileS>(ps, stream);
 }
 
 // in_kind: 0 = FP64, 1 = FP32, 2 = BF16 (bits);  out_kind: 1 = FP32, 2 = BF16, 0 = FP64 accumulate

@@ -79,51 +79,76 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* _
                                                                   const double* __restrict__ hz, int nx, int ny,
                                                                   int nz, int xchunk, double alpha) {
   constexpr int BW = 2 * KH + 1;
+  // one wave = one y row (RZ = 64 lanes along z): j and everything derived from it
+  // is wave-uniform and lives in scalar registers
   const int l = blockIdx.x * RZ + (threadIdx.x % RZ);
-  const int j = blockIdx.y * RY + (threadIdx.x / RZ);
+  const int j = __builtin_amdgcn_readfirstlane(blockIdx.y * RY + (threadIdx.x / RZ));
   const int i0 = blockIdx.z * xchunk;
   const int i1 = min(nx, i0 + xchunk);
   if (l >= nz || j >= ny) return;  // no barriers below: early exit is safe
   const long plane = (long)ny * nz;
   const long col = (long)j * nz + l;
-  double cy[BW], cz[BW];
+  double cz[BW];
+  int oz[BW];
+  bool okz[BW];
+  // Neighbour offsets clamped into range (fixed for the march).  Out-of-range
+  // neighbours are loaded from a valid address and selected away (their band
+  // coefficients are zero too), so every load is unconditional.
 #pragma unroll
   for (int d = 0; d < BW; ++d) {
-    cy[d] = hy[(size_t)j * BW + d];
     cz[d] = hz[(size_t)l * BW + d];
+    const int ll = l - KH + d;
+    okz[d] = ll >= 0 && ll < nz;
+    oz[d] = (okz[d] ? ll : l) - l;
   }
-  // neighbour validity along y and z (fixed for the march)
-  bool oky[BW], okz[BW];
-#pragma unroll
-  for (int d = 0; d < BW; ++d) {
-    oky[d] = j - KH + d >= 0 && j - KH + d < ny;
-    okz[d] = l - KH + d >= 0 && l - KH + d < nz;
-  }
+  const double* __restrict__ cyr = hy + (size_t)j * BW;  // uniform
   // x window: w[d] = u[i - KH + d], zero outside [0, nx)
   double w[BW];
 #pragma unroll
   for (int d = 0; d < BW; ++d) {
     const int ii = i0 - KH + d;
-    w[d] = (ii >= 0 && ii < nx) ? u[(size_t)ii * plane + col] : 0.0;
+    const double v = u[(size_t)(ii < 0 ? 0 : (ii >= nx ? nx - 1 : ii)) * plane + col];
+    w[d] = (ii >= 0 && ii < nx) ? v : 0.0;
   }
-  for (int i = i0; i < i1; ++i) {
+  // software pipeline: the loads of plane i+1 are issued before plane i is reduced
+  double vy[BW], vz[BW], wn, fv;
+  auto load_plane = [&](int i) {
     const size_t idx = (size_t)i * plane + col;
+#pragma unroll
+    for (int d = 0; d < BW; ++d) {
+      const int jj = j - KH + d;
+      vy[d] = u[idx + (long)((jj >= 0 && jj < ny ? jj : j) - j) * nz];
+      vz[d] = u[idx + oz[d]];
+    }
+    const int inext = i + KH + 1;
+    wn = u[(size_t)(inext < nx ? inext : nx - 1) * plane + col];
+    fv = f[idx];
+  };
+  if (i0 < i1) load_plane(i0);
+  for (int i = i0; i < i1; ++i) {
+    double cy_vy[BW], cz_vz[BW];
+#pragma unroll
+    for (int d = 0; d < BW; ++d) {
+      const int jj = j - KH + d;
+      cy_vy[d] = (jj >= 0 && jj < ny) ? vy[d] : 0.0;
+      cz_vz[d] = okz[d] ? vz[d] : 0.0;
+    }
+    const double wnext = i + KH + 1 < nx ? wn : 0.0;
+    const double fcur = fv;
+    load_plane(i + 1 < i1 ? i + 1 : i);  // unconditional (the last step reloads a valid plane)
+    __builtin_amdgcn_sched_barrier(0);    // keep the prefetch ahead of the reduction
     const double* __restrict__ hxr = hx + (size_t)i * BW;
     double s = alpha * w[KH];
 #pragma unroll
-    for (int d = 0; d < BW; ++d) s += hxr[d] * w[d];
-#pragma unroll
-    for (int d = 0; d < BW; ++d)
-      if (oky[d]) s += cy[d] * u[idx + (long)(d - KH) * nz];
-#pragma unroll
-    for (int d = 0; d < BW; ++d)
-      if (okz[d]) s += cz[d] * u[idx + (d - KH)];
-    put(r, ((size_t)i * ny + j) * ldr + l, f[idx] - s);
-    // advance the window
+    for (int d = 0; d < BW; ++d) {
+      s += hxr[d] * w[d];
+      s += cyr[d] * cy_vy[d];
+      s += cz[d] * cz_vz[d];
+    }
+    put(r, ((size_t)i * ny + j) * ldr + l, fcur - s);
 #pragma unroll
     for (int d = 0; d + 1 < BW; ++d) w[d] = w[d + 1];
-    const int inext = i + KH + 1;
-    w[BW - 1] = inext < nx ? u[(size_t)inext * plane + col] : 0.0;
+    w[BW - 1] = wnext;
   }
 }
 
@@ -132,7 +157,7 @@ static void launch_march(const double* u, const double* f, TR* r, int ldr, const
                          const int dims[3], double alpha, hipStream_t stream) {
   // split x into chunks so that the grid fills the chip even for thin (y, z) planes
   const long cols = (long)((dims[2] + RZ - 1) / RZ) * ((dims[1] + RY - 1) / RY);
-  int nchunks = (int)std::min<long>(dims[0], std::max<long>(1, (2048 + cols - 1) / cols));
+  int nchunks = (int)std::min<long>(dims[0], std::max<long>(1, (16384 + cols - 1) / cols));
   const int xchunk = (dims[0] + nchunks - 1) / nchunks;
   nchunks = (dims[0] + xchunk - 1) / xchunk;
   dim3 grid((unsigned)((dims[2] + RZ - 1) / RZ), (unsigned)((dims[1] + RY - 1) / RY), (unsigned)nchunks);
