@@ -48,6 +48,9 @@ struct EpiLP {
 //      accumulate);
 //   f_hi / f_lo: factor [l][k] (FP32 or BF16 bits), padded with zeros to ldf
 //      columns and to a multiple of 128 rows.
+// The direct-to-LDS kernels (mode_dma.hip) take BF16 operands only: split-BF16
+// operands are two planes, the second xplane / yplane / fplane elements after
+// the first (f_lo unused).
 struct LpPass {
   int mode = LP_BF16;
   const void* x = nullptr;
@@ -61,18 +64,31 @@ struct LpPass {
   const void* f_lo = nullptr;
   int ldf = 0;
   int in_kind = 0, out_kind = 0, epi_kind = EPI_STORE;
+  long xplane = 0, yplane = 0, fplane = 0;
   EpiLP epi;
 };
 hipError_t launch_mode_lp(const LpPass& ps, hipStream_t stream);
+
+// ---- BF16 / split-BF16 passes with direct global -> LDS loads (mode_dma.hip) ----
+// Requirements: in_kind 2, ldx and ldf multiples of 8, ldx >= K, ldf >= L and K
+// rounded up to 256; tensor pitch padding [K, ldx) holds finite values; factor
+// zero outside L x K.  Output BF16 planes get their pitch padding [B, ldy) zeroed.
+bool dma_supported(const LpPass& ps);
+hipError_t launch_mode_dma(const LpPass& ps, hipStream_t stream);
+// FP64 array (rows dims[0]*dims[1], pitch dims[2]) -> BF16 hi (+ lo plane plane_o
+// elements later when split) with pitch ldo, padding zeroed.
+hipError_t launch_to_lowp(const double* f, void* out, long plane_o, int split, const int dims[3], int ldo,
+                          hipStream_t stream);
 
 // Nodal residual r = f - alpha u - (H_x + H_y + H_z) u with banded H rows
 // hb[a][g * (2k+1) + d] = H_a(g, g - k + d).
 hipError_t launch_residual_f64(const double* u, const double* f, double* r, const double* const hb[3], int k,
                                const int dims[3], double alpha, hipStream_t stream);
 
-// Same residual, written with row pitch ldr as FP32 (r_kind 1) or BF16 (2) for
-// the low-precision solves of the refinement loop.
-hipError_t launch_residual_lp(const double* u, const double* f, void* r, int r_kind, int ldr, const double* const hb[3],
-                              int k, const int dims[3], double alpha, hipStream_t stream);
+// Same residual, written with row pitch ldr as FP32 (r_kind 1), BF16 (2) or split
+// BF16 (3: hi plane, lo plane rplane elements later) for the low-precision solves
+// of the refinement loop; the pitch padding [dims[2], ldr) is written with zeros.
+hipError_t launch_residual_lp(const double* u, const double* f, void* r, int r_kind, int ldr, long rplane,
+                              const double* const hb[3], int k, const int dims[3], double alpha, hipStream_t stream);
 
 }  // namespace semfd

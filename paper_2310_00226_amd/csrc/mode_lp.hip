@@ -24,6 +24,8 @@
 // recording max|delta| and max|u| for the refinement stop test.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
+
 #include <cstdint>
 
 #include "kernels.h"
@@ -338,8 +340,9 @@ __global__ __launch_bounds__(TT::NTHREADS) void mode_rot_lp(const TIn* __restric
           const double dv = (double)v;
           const double un = epi.first ? dv : (double)y[off] + dv;
           y[off] = (TOut)un;
-          dmax = fmax(dmax, fabs(dv));
-          umax = fmax(umax, fabs(un));
+          // a NaN / Inf turns the norm into +Inf (fmax alone would drop NaN)
+          dmax = fabs(dv) <= DBL_MAX ? fmax(dmax, fabs(dv)) : INFINITY;
+          umax = fabs(un) <= DBL_MAX ? fmax(umax, fabs(un)) : INFINITY;
         }
       }
     }

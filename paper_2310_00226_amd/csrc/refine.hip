@@ -9,10 +9,14 @@
 // mode products rounded to FP32 / BF16; the refinement around it is not in the
 // paper (its single-precision runs plateau without it, Table 10).
 //
-// Each low-precision solve is six rotating mode products (mode_lp.hip):
+// Each low-precision solve is six rotating mode products:
 //   (x,y,z) -z-> (z,x,y) -y-> (y,z,x) -x,divide-> (x,y,z) -z-> (z,x,y) -y-> (y,z,x) -x-> u
 // Intermediates live in the workspace with their contiguous axis padded to a
-// multiple of 8 elements (16-byte rows for BF16).
+// multiple of 8 elements (16-byte rows for BF16).  FP32 runs the register-staged
+// kernels of mode_lp.hip; BF16 and split BF16 run the direct-to-LDS kernels of
+// mode_dma.hip, with every operand in BF16 planes (split: a hi plane and a lo
+// plane): the right-hand side is converted once, the residual is written in that
+// format directly.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,7 +32,7 @@ namespace semfd {
 namespace {
 
 inline int pad8(int n) { return (n + 7) / 8 * 8; }
-inline int pad128(int n) { return (n + 127) / 128 * 128; }
+inline int pad256(int n) { return (n + 255) / 256 * 256; }
 
 unsigned short host_f2bf(float f) {
   unsigned u;
@@ -44,7 +48,9 @@ float host_bf2f(unsigned short b) {
   return f;
 }
 
+// bytes per element of the intermediates (split BF16: two 2-byte planes)
 size_t lp_elem(sem_prec prec) { return prec == SEM_BF16 ? 2 : 4; }
+bool lp_split(sem_prec prec) { return prec == SEM_BF16X3; }
 
 // largest of the three rotated padded layouts (z,x,y'), (y,z,x'), (x,y,z')
 size_t lp_tmp_elems(const sem_plan* p) {
@@ -53,10 +59,8 @@ size_t lp_tmp_elems(const sem_plan* p) {
 }
 
 // residual buffer of the refinement: (nx, ny, pad8(nz)) in the intermediate type
-size_t lp_r_bytes(const sem_plan* p, sem_prec prec) {
-  const size_t e = (size_t)p->dims[0] * p->dims[1] * pad8(p->dims[2]) * lp_elem(prec);
-  return ((e + 255) / 256) * 256;
-}
+size_t lp_r_elems(const sem_plan* p) { return (size_t)p->dims[0] * p->dims[1] * pad8(p->dims[2]); }
+size_t lp_r_bytes(const sem_plan* p, sem_prec prec) { return ((lp_r_elems(p) * lp_elem(prec) + 255) / 256) * 256; }
 
 __global__ void zero_u64_kernel(unsigned long long* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
@@ -85,81 +89,77 @@ void release_lowp(sem_plan* p) {
   for (int a = 0; a < 3; ++a)
     for (int d = 0; d < 2; ++d) {
       (void)hipFree(p->lp_f32[a][d]);
-      (void)hipFree(p->lp_hi[a][d]);
-      (void)hipFree(p->lp_lo[a][d]);
+      (void)hipFree(p->lp_hi[a][d]);  // lp_lo points into the same allocation
       p->lp_f32[a][d] = p->lp_hi[a][d] = p->lp_lo[a][d] = nullptr;
     }
   p->lp_ready = 0;
 }
 
 // Low-precision copies of the factors, layout [l][k] (row l = output mode,
-// contraction k contiguous), zero-padded to pad128(n) x pad128(n).
+// contraction k contiguous), zero-padded to pad256(n) x pad256(n): FP32, and
+// BF16 hi followed by BF16 lo = bf16(v - hi) in one allocation (lp_lo = lp_hi +
+// ld * ld elements).
 static sem_status ensure_lowp(sem_plan* p) {
   if (p->lp_ready) return SEM_OK;
   for (int a = 0; a < 3; ++a) {
-    const int n = p->dims[a], ld = pad128(n);
+    const int n = p->dims[a], ld = pad256(n);
+    const size_t plane = (size_t)ld * ld;
     p->lp_ld[a] = ld;
     for (int d = 0; d < 2; ++d) {
       const std::vector<double>& M = d == 0 ? p->ax[a].F : p->ax[a].S;
-      std::vector<float> f32((size_t)ld * ld, 0.0f);
-      std::vector<unsigned short> hi((size_t)ld * ld, 0), lo((size_t)ld * ld, 0);
+      std::vector<float> f32(plane, 0.0f);
+      std::vector<unsigned short> hl(2 * plane, 0);
       for (int l = 0; l < n; ++l)
         for (int k = 0; k < n; ++k) {
           const double v = M[(size_t)l * n + k];
           const float fv = (float)v;
           f32[(size_t)l * ld + k] = fv;
           const unsigned short h = host_f2bf(fv);
-          hi[(size_t)l * ld + k] = h;
-          lo[(size_t)l * ld + k] = host_f2bf((float)(v - (double)host_bf2f(h)));
+          hl[(size_t)l * ld + k] = h;
+          hl[plane + (size_t)l * ld + k] = host_f2bf((float)(v - (double)host_bf2f(h)));
         }
       hipError_t e;
       if ((e = hipMalloc(&p->lp_f32[a][d], f32.size() * 4)) != hipSuccess ||
           (e = hipMemcpy(p->lp_f32[a][d], f32.data(), f32.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-          (e = hipMalloc(&p->lp_hi[a][d], hi.size() * 2)) != hipSuccess ||
-          (e = hipMemcpy(p->lp_hi[a][d], hi.data(), hi.size() * 2, hipMemcpyHostToDevice)) != hipSuccess ||
-          (e = hipMalloc(&p->lp_lo[a][d], lo.size() * 2)) != hipSuccess ||
-          (e = hipMemcpy(p->lp_lo[a][d], lo.data(), lo.size() * 2, hipMemcpyHostToDevice)) != hipSuccess) {
+          (e = hipMalloc(&p->lp_hi[a][d], hl.size() * 2)) != hipSuccess ||
+          (e = hipMemcpy(p->lp_hi[a][d], hl.data(), hl.size() * 2, hipMemcpyHostToDevice)) != hipSuccess) {
         release_lowp(p);
         return hip_fail(e, "low-precision factor upload");
       }
+      p->lp_lo[a][d] = (unsigned short*)p->lp_hi[a][d] + plane;
     }
   }
   p->lp_ready = 1;
   return SEM_OK;
 }
 
-// One low-precision FD solve of `src`, accumulated into u.  src is the FP64
-// right-hand side in the caller's layout (src_lp = 0) or the residual in the
-// intermediate type with row pitch pad8(nz) (src_lp = 1).
-static hipError_t lp_solve(sem_plan* p, sem_prec prec, const void* src, int src_lp, double* u, void* t0, void* t1,
-                           unsigned long long* norms, int first) {
+// One low-precision FD solve of `src`, accumulated into u.
+//  FP32: src is the FP64 right-hand side in the caller's layout (src_lp = 0) or
+//        the FP32 residual with row pitch pad8(nz) (src_lp = 1);
+//  BF16 / split BF16: src is always in BF16 planes with row pitch pad8(nz)
+//        (rplane = offset of the lo plane); t0 / t1 have planes tplane apart.
+static hipError_t lp_solve(sem_plan* p, sem_prec prec, const void* src, int src_lp, long rplane, double* u, void* t0,
+                           void* t1, long tplane, unsigned long long* norms, int first) {
   const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
   const int mode = prec == SEM_F32 ? LP_F32 : prec == SEM_BF16 ? LP_BF16 : LP_BF16X3;
-  const int lpk = prec == SEM_BF16 ? 2 : 1;  // intermediate kind
-  auto fac = [&](int axis, int dir, LpPass& ps) {
-    if (mode == LP_F32) {
-      ps.f_hi = p->lp_f32[axis][dir];
-      ps.f_lo = nullptr;
-    } else {
-      ps.f_hi = p->lp_hi[axis][dir];
-      ps.f_lo = p->lp_lo[axis][dir];
-    }
-    ps.ldf = p->lp_ld[axis];
-  };
+  const bool dma = mode != LP_F32;
+  const int lpk = mode == LP_F32 ? 1 : 2;  // intermediate kind (FP32 / BF16 planes)
   // the six passes: (input, ldx, A, B, K) -> (output, ldy); axis contracted = K's axis
   struct Step {
     const void* x;
     int ldx, A, B, K, axis, dir;
     void* y;
     int ldy, in_kind, out_kind, epi;
+    long xplane, yplane;
   };
+  const int in0 = (src_lp || dma) ? lpk : 0;
   const Step st[6] = {
-      {src, src_lp ? pad8(nz) : nz, nx, ny, nz, 2, 0, t0, pad8(ny), src_lp ? lpk : 0, lpk, EPI_STORE},
-      {t0, pad8(ny), nz, nx, ny, 1, 0, t1, pad8(nx), lpk, lpk, EPI_STORE},
-      {t1, pad8(nx), ny, nz, nx, 0, 0, t0, pad8(nz), lpk, lpk, EPI_DIVIDE},
-      {t0, pad8(nz), nx, ny, nz, 2, 1, t1, pad8(ny), lpk, lpk, EPI_STORE},
-      {t1, pad8(ny), nz, nx, ny, 1, 1, t0, pad8(nx), lpk, lpk, EPI_STORE},
-      {t0, pad8(nx), ny, nz, nx, 0, 1, u, nz, lpk, 0, EPI_ACCUM},
+      {src, in0 ? pad8(nz) : nz, nx, ny, nz, 2, 0, t0, pad8(ny), in0, lpk, EPI_STORE, rplane, tplane},
+      {t0, pad8(ny), nz, nx, ny, 1, 0, t1, pad8(nx), lpk, lpk, EPI_STORE, tplane, tplane},
+      {t1, pad8(nx), ny, nz, nx, 0, 0, t0, pad8(nz), lpk, lpk, EPI_DIVIDE, tplane, tplane},
+      {t0, pad8(nz), nx, ny, nz, 2, 1, t1, pad8(ny), lpk, lpk, EPI_STORE, tplane, tplane},
+      {t1, pad8(ny), nz, nx, ny, 1, 1, t0, pad8(nx), lpk, lpk, EPI_STORE, tplane, tplane},
+      {t0, pad8(nx), ny, nz, nx, 0, 1, u, nz, lpk, 0, EPI_ACCUM, tplane, 0},
   };
   for (int s = 0; s < 6; ++s) {
     LpPass ps;
@@ -173,10 +173,18 @@ static hipError_t lp_solve(sem_plan* p, sem_prec prec, const void* src, int src_
     ps.A = st[s].A;
     ps.B = st[s].B;
     ps.L = st[s].K;
-    fac(st[s].axis, st[s].dir, ps);
+    const int axis = st[s].axis, dir = st[s].dir;
+    ps.f_hi = mode == LP_F32 ? p->lp_f32[axis][dir] : p->lp_hi[axis][dir];
+    ps.f_lo = mode == LP_F32 ? nullptr : p->lp_lo[axis][dir];
+    ps.ldf = p->lp_ld[axis];
     ps.in_kind = st[s].in_kind;
     ps.out_kind = st[s].out_kind;
     ps.epi_kind = st[s].epi;
+    if (mode == LP_BF16X3) {
+      ps.xplane = st[s].xplane;
+      ps.yplane = st[s].yplane;
+      ps.fplane = (long)ps.ldf * ps.ldf;
+    }
     if (st[s].epi == EPI_DIVIDE) {
       // output (x, y, z): l = x mode, a = y mode, b = z mode
       ps.epi.l0 = p->d_lam[0];
@@ -188,7 +196,13 @@ static hipError_t lp_solve(sem_plan* p, sem_prec prec, const void* src, int src_
       ps.epi.first = first;
       ps.epi.norms = norms;
     }
-    hipError_t e = launch_mode_lp(ps, p->stream);
+    hipError_t e;
+    if (dma) {
+      if (!dma_supported(ps)) return hipErrorInvalidValue;
+      e = launch_mode_dma(ps, p->stream);
+    } else {
+      e = launch_mode_lp(ps, p->stream);
+    }
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -224,23 +238,34 @@ extern "C" sem_status sem_solve_refined(sem_plan* p, sem_prec prec, double tol, 
   char* w = (char*)ws;
   void* r = w;
   const size_t rbytes = lp_r_bytes(p, prec);
-  const int rkind = prec == SEM_BF16 ? 2 : 1;
+  const bool split = lp_split(prec);
+  const bool dma = prec != SEM_F32;
+  const int rkind = prec == SEM_F32 ? 1 : split ? 3 : 2;
+  const long rplane = split ? (long)lp_r_elems(p) : 0;
   const size_t tbytes = ((lp_tmp_elems(p) * lp_elem(prec) + 255) / 256) * 256;
+  const long tplane = split ? (long)lp_tmp_elems(p) : 0;
   void* t0 = w + rbytes;
   void* t1 = w + rbytes + tbytes;
   unsigned long long* norms = (unsigned long long*)(w + rbytes + 2 * tbytes);
   const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
+  const int ldr = pad8(p->dims[2]);
 
   double prev = INFINITY, prev2 = INFINITY;
   for (int it = 0; it < max_iter; ++it) {
     hipError_t e;
-    if (it > 0 && (e = launch_residual_lp(u, f, r, rkind, pad8(p->dims[2]), hb, p->k, p->dims, p->alpha,
-                                          p->stream)) != hipSuccess)
-      return hip_fail(e, "sem_solve_refined: residual");
+    if (it > 0) {
+      if ((e = launch_residual_lp(u, f, r, rkind, ldr, rplane, hb, p->k, p->dims, p->alpha, p->stream)) !=
+          hipSuccess)
+        return hip_fail(e, "sem_solve_refined: residual");
+    } else if (dma) {
+      if ((e = launch_to_lowp(f, r, rplane, split ? 1 : 0, p->dims, ldr, p->stream)) != hipSuccess)
+        return hip_fail(e, "sem_solve_refined: right-hand side conversion");
+    }
     zero_u64_kernel<<<1, 64, 0, p->stream>>>(norms, 2);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sem_solve_refined: norm reset");
-    if ((e = lp_solve(p, prec, it == 0 ? (const void*)f : (const void*)r, it == 0 ? 0 : 1, u, t0, t1, norms,
-                      it == 0 ? 1 : 0)) != hipSuccess)
+    const bool from_r = it > 0 || dma;
+    if ((e = lp_solve(p, prec, from_r ? (const void*)r : (const void*)f, from_r ? 1 : 0, rplane, u, t0, t1, tplane,
+                      norms, it == 0 ? 1 : 0)) != hipSuccess)
       return hip_fail(e, "sem_solve_refined: low-precision solve");
     unsigned long long hn[2];
     if ((e = hipMemcpyAsync(hn, norms, sizeof(hn), hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||

@@ -21,17 +21,28 @@
 
 namespace semfd {
 
-__device__ __forceinline__ void put(double* r, size_t i, double v) { r[i] = v; }
-__device__ __forceinline__ void put(float* r, size_t i, double v) { r[i] = (float)v; }
-__device__ __forceinline__ void put(unsigned short* r, size_t i, double v) {
-  r[i] = __builtin_bit_cast(unsigned short, (__bf16)(float)v);
+// Stores of one residual value; BF16 with a nonzero plane offset stores the split
+// pair (hi at i, lo = v - hi at i + plane).
+__device__ __forceinline__ void put(double* r, size_t i, double v, long) { r[i] = v; }
+__device__ __forceinline__ void put(float* r, size_t i, double v, long) { r[i] = (float)v; }
+__device__ __forceinline__ void put(unsigned short* r, size_t i, double v, long plane) {
+  const float fv = (float)v;
+  const __bf16 h = (__bf16)fv;
+  r[i] = __builtin_bit_cast(unsigned short, h);
+  if (plane) r[i + plane] = __builtin_bit_cast(unsigned short, (__bf16)(fv - (float)h));
+}
+// zero the pitch padding [nz, ldr) of one row (done by the row's last node)
+template <class TR>
+__device__ __forceinline__ void zero_pad(TR* r, size_t row0, int nz, int ldr, long plane) {
+  for (int e = nz; e < ldr; ++e) put(r, row0 + e, 0.0, plane);
 }
 
 // r is written with row pitch ldr (>= nz) in type TR: FP64 for sem_residual,
-// FP32 / BF16 when it only feeds a low-precision solve (refinement).
+// FP32 / BF16 / split BF16 when it only feeds a low-precision solve (refinement).
 template <int KH, class TR>
 __global__ __launch_bounds__(256) void residual_f64_kernel(const double* __restrict__ u, const double* __restrict__ f,
-                                                           TR* __restrict__ r, int ldr, const double* __restrict__ hx,
+                                                           TR* __restrict__ r, int ldr, long rplane,
+                                                           const double* __restrict__ hx,
                                                            const double* __restrict__ hy,
                                                            const double* __restrict__ hz, int kh, int nx, int ny,
                                                            int nz, double alpha) {
@@ -66,7 +77,9 @@ __global__ __launch_bounds__(256) void residual_f64_kernel(const double* __restr
     const int d1 = i + k >= nx ? k + (nx - 1 - i) : 2 * k;
     for (int d = d0; d <= d1; ++d) s += hrow[d] * u[idx + (long)(d - k) * plane];
   }
-  put(r, ((size_t)i * ny + j) * ldr + l, f[idx] - s);
+  const size_t row0 = ((size_t)i * ny + j) * ldr;
+  put(r, row0 + l, f[idx] - s, rplane);
+  if (l == nz - 1) zero_pad(r, row0, nz, ldr, rplane);
 }
 
 constexpr int RY = 4, RZ = 64;
@@ -74,7 +87,8 @@ constexpr int RY = 4, RZ = 64;
 template <int KH, class TR>
 __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* __restrict__ u,
                                                                   const double* __restrict__ f, TR* __restrict__ r,
-                                                                  int ldr, const double* __restrict__ hx,
+                                                                  int ldr, long rplane,
+                                                                  const double* __restrict__ hx,
                                                                   const double* __restrict__ hy,
                                                                   const double* __restrict__ hz, int nx, int ny,
                                                                   int nz, int xchunk, double alpha) {
@@ -145,7 +159,9 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* _
       s += cyr[d] * cy_vy[d];
       s += cz[d] * cz_vz[d];
     }
-    put(r, ((size_t)i * ny + j) * ldr + l, fcur - s);
+    const size_t row0 = ((size_t)i * ny + j) * ldr;
+    put(r, row0 + l, fcur - s, rplane);
+    if (l == nz - 1) zero_pad(r, row0, nz, ldr, rplane);
 #pragma unroll
     for (int d = 0; d + 1 < BW; ++d) w[d] = w[d + 1];
     w[BW - 1] = wnext;
@@ -153,7 +169,7 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* _
 }
 
 template <int KH, class TR>
-static void launch_march(const double* u, const double* f, TR* r, int ldr, const double* const hb[3],
+static void launch_march(const double* u, const double* f, TR* r, int ldr, long rplane, const double* const hb[3],
                          const int dims[3], double alpha, hipStream_t stream) {
   // split x into chunks so that the grid fills the chip even for thin (y, z) planes
   const long cols = (long)((dims[2] + RZ - 1) / RZ) * ((dims[1] + RY - 1) / RY);
@@ -161,28 +177,29 @@ static void launch_march(const double* u, const double* f, TR* r, int ldr, const
   const int xchunk = (dims[0] + nchunks - 1) / nchunks;
   nchunks = (dims[0] + xchunk - 1) / xchunk;
   dim3 grid((unsigned)((dims[2] + RZ - 1) / RZ), (unsigned)((dims[1] + RY - 1) / RY), (unsigned)nchunks);
-  residual_march_kernel<KH, TR><<<grid, dim3(RY * RZ), 0, stream>>>(u, f, r, ldr, hb[0], hb[1], hb[2], dims[0],
+  residual_march_kernel<KH, TR><<<grid, dim3(RY * RZ), 0, stream>>>(u, f, r, ldr, rplane, hb[0], hb[1], hb[2], dims[0],
                                                                      dims[1], dims[2], xchunk, alpha);
 }
 
 template <class TR>
-static hipError_t launch_res(const double* u, const double* f, TR* r, int ldr, const double* const hb[3], int k,
+static hipError_t launch_res(const double* u, const double* f, TR* r, int ldr, long rplane, const double* const hb[3],
+                             int k,
                              const int dims[3], double alpha, hipStream_t stream) {
   const long plane = (long)dims[1] * dims[2];
   if (dims[0] <= 0 || plane <= 0) return hipSuccess;
   if ((dims[1] + RY - 1) / RY > 65535 || dims[0] > 65535) return hipErrorInvalidValue;
   switch (k) {
-    case 1: launch_march<1, TR>(u, f, r, ldr, hb, dims, alpha, stream); break;
-    case 2: launch_march<2, TR>(u, f, r, ldr, hb, dims, alpha, stream); break;
-    case 3: launch_march<3, TR>(u, f, r, ldr, hb, dims, alpha, stream); break;
-    case 4: launch_march<4, TR>(u, f, r, ldr, hb, dims, alpha, stream); break;
-    case 5: launch_march<5, TR>(u, f, r, ldr, hb, dims, alpha, stream); break;
-    case 6: launch_march<6, TR>(u, f, r, ldr, hb, dims, alpha, stream); break;
-    case 7: launch_march<7, TR>(u, f, r, ldr, hb, dims, alpha, stream); break;
-    case 8: launch_march<8, TR>(u, f, r, ldr, hb, dims, alpha, stream); break;
+    case 1: launch_march<1, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
+    case 2: launch_march<2, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
+    case 3: launch_march<3, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
+    case 4: launch_march<4, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
+    case 5: launch_march<5, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
+    case 6: launch_march<6, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
+    case 7: launch_march<7, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
+    case 8: launch_march<8, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
     default: {
       dim3 block(256), grid((unsigned)((plane + 255) / 256), (unsigned)dims[0]);
-      residual_f64_kernel<0, TR><<<grid, block, 0, stream>>>(u, f, r, ldr, hb[0], hb[1], hb[2], k, dims[0], dims[1],
+      residual_f64_kernel<0, TR><<<grid, block, 0, stream>>>(u, f, r, ldr, rplane, hb[0], hb[1], hb[2], k, dims[0], dims[1],
                                                             dims[2], alpha);
     }
   }
@@ -191,14 +208,19 @@ static hipError_t launch_res(const double* u, const double* f, TR* r, int ldr, c
 
 hipError_t launch_residual_f64(const double* u, const double* f, double* r, const double* const hb[3], int k,
                                const int dims[3], double alpha, hipStream_t stream) {
-  return launch_res<double>(u, f, r, dims[2], hb, k, dims, alpha, stream);
+  return launch_res<double>(u, f, r, dims[2], 0, hb, k, dims, alpha, stream);
 }
 
-hipError_t launch_residual_lp(const double* u, const double* f, void* r, int r_kind, int ldr, const double* const hb[3],
-                              int k, const int dims[3], double alpha, hipStream_t stream) {
-  if (r_kind == 1) return launch_res<float>(u, f, (float*)r, ldr, hb, k, dims, alpha, stream);
-  if (r_kind == 2) return launch_res<unsigned short>(u, f, (unsigned short*)r, ldr, hb, k, dims, alpha, stream);
-  return launch_res<double>(u, f, (double*)r, ldr, hb, k, dims, alpha, stream);
+hipError_t launch_residual_lp(const double* u, const double* f, void* r, int r_kind, int ldr, long rplane,
+                              const double* const hb[3], int k, const int dims[3], double alpha, hipStream_t stream) {
+  if (ldr < dims[2]) return hipErrorInvalidValue;
+  if (r_kind == 1) return launch_res<float>(u, f, (float*)r, ldr, 0, hb, k, dims, alpha, stream);
+  if (r_kind == 2) return launch_res<unsigned short>(u, f, (unsigned short*)r, ldr, 0, hb, k, dims, alpha, stream);
+  if (r_kind == 3) {
+    if (rplane <= 0) return hipErrorInvalidValue;
+    return launch_res<unsigned short>(u, f, (unsigned short*)r, ldr, rplane, hb, k, dims, alpha, stream);
+  }
+  return launch_res<double>(u, f, (double*)r, ldr, 0, hb, k, dims, alpha, stream);
 }
 
 }  // namespace semfd
