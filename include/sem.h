@@ -119,6 +119,39 @@ sem_status sem_residual(sem_plan *p, const double *u, const double *f, double *r
 sem_status sem_solve_refined(sem_plan *p, sem_prec prec, double tol, int max_iter, const double *f, double *u,
                              int *iters, double *last_update_rel);
 
+/* ---- Cahn-Hilliard IMEX time stepping (Sec. 3.6) ---------------------------- */
+
+typedef struct sem_ch sem_ch;
+
+/* Stepper of eq. chscheme-2 (BDF2 in time, nonlinear term extrapolated) for
+ *   phi_t = m Lap w,  w = -eps Lap phi + (1/eps) F'(phi),  F'(phi) = phi^3 - phi,
+ * Q^k SEM in space with homogeneous Neumann conditions on the box (all nodes are
+ * unknowns, n_a = ne_a*k + 1).  One step solves
+ *   (a I + m dt eps H_3^2) phi_{n+1} = phi_hat - (m dt / eps) H_3 F'(phi_bar),
+ *   a = 3/2, phi_hat = 2 phi_n - phi_{n-1}/2, phi_bar = 2 phi_n - phi_{n-1},
+ * H_3 = -Lap_h = M_3^{-1} K_3, by one fast-diagonalisation application with the
+ * spectral multiplier 1 / (a + m dt eps Lambda3D^2) in precision `prec`, followed
+ * by refine_sweeps (0..64) FP64 iterative-refinement sweeps against that operator
+ * (matrix-free residual).  eps, mob (m), dt > 0.  Creates the plan, an internal
+ * stream and all device buffers (5 arrays of N doubles plus the solve workspace)
+ * up front.  Synchronous.  SEM_EINVAL on invalid arguments. */
+sem_status sem_ch_create(int k, const int ne[3], const double box[6], double eps, double mob, double dt,
+                         sem_prec prec, int refine_sweeps, sem_ch **out);
+void sem_ch_destroy(sem_ch *c);
+sem_status sem_ch_dims(const sem_ch *c, int n[3]);
+/* Order the stepper's work after earlier work on this hipStream_t and before later
+ * work on it (NULL = the null stream).  The steps themselves run on the stepper's
+ * own stream. */
+sem_status sem_ch_set_stream(sem_ch *c, void *hip_stream);
+/* enable = 1 (default): each step is a replay of a captured HIP graph (captured on
+ * the first call, and again whenever phi_n / phi_nm1 change address); 0: the same
+ * kernels launched one by one. */
+sem_status sem_ch_set_graphs(sem_ch *c, int enable);
+/* Advance nsteps >= 0 steps.  phi_n, phi_nm1: device arrays of N doubles (distinct),
+ * holding phi_n and phi_{n-1} on entry (first step: pass phi_0 in both) and
+ * phi_{n+nsteps}, phi_{n+nsteps-1} on return.  Asynchronous. */
+sem_status sem_ch_step(sem_ch *c, double *phi_n, double *phi_nm1, int nsteps);
+
 /* Host-only helper (no device needed): the 1D operators of one axis as built by
  * sem_plan_create.  Call with all output pointers NULL to get n; then pass
  * buffers of n (x, mass, lam) and n*n (S, F, row-major) doubles; any output may

@@ -46,6 +46,13 @@ def _load():
         "sem_solve_refined": (c_int, [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, POINTER(c_int),
                                       POINTER(c_double)]),
         "sem_axis_host": (c_int, [c_int, c_int, c_double, c_double, c_int, POINTER(c_int), dp, dp, dp, dp, dp]),
+        "sem_ch_create": (c_int, [c_int, POINTER(c_int), dp, c_double, c_double, c_double, c_int, c_int,
+                                  POINTER(c_void_p)]),
+        "sem_ch_destroy": (None, [c_void_p]),
+        "sem_ch_dims": (c_int, [c_void_p, POINTER(c_int)]),
+        "sem_ch_set_stream": (c_int, [c_void_p, c_void_p]),
+        "sem_ch_set_graphs": (c_int, [c_void_p, c_int]),
+        "sem_ch_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
         "sem_last_error": (c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -197,3 +204,44 @@ class Plan:
         self._prepare(SEM_F64)
         check(lib.sem_residual(self._p, a, b, c))
         return r
+
+
+class CahnHilliard:
+    """Cahn-Hilliard IMEX stepper (sem_ch_create / sem_ch_step), homogeneous Neumann."""
+
+    def __init__(self, k: int, ne, box, eps: float, mob: float, dt: float, prec: str = "f32",
+                 refine_sweeps: int = 2, graphs: bool = True, device=None):
+        import torch
+        self._c = c_void_p(None)
+        ne_arr = (c_int * 3)(*[int(v) for v in ne])
+        box_arr = (c_double * 6)(*[float(v) for v in box])
+        pv = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(self.device):
+            check(lib.sem_ch_create(int(k), ne_arr, box_arr, float(eps), float(mob), float(dt), pv,
+                                    int(refine_sweeps), ctypes.byref(self._c)))
+        dims = (c_int * 3)()
+        check(lib.sem_ch_dims(self._c, dims))
+        self.shape = tuple(dims)
+        self.numel = self.shape[0] * self.shape[1] * self.shape[2]
+        check(lib.sem_ch_set_graphs(self._c, 1 if graphs else 0))
+
+    def __del__(self):
+        c = getattr(self, "_c", None)
+        if c is not None and c.value:
+            lib.sem_ch_destroy(c)
+            self._c = c_void_p(None)
+
+    def close(self):
+        self.__del__()
+
+    def set_graphs(self, enable: bool):
+        check(lib.sem_ch_set_graphs(self._c, 1 if enable else 0))
+
+    def step(self, phi_n, phi_nm1, nsteps: int = 1):
+        """Advance in place: on return phi_n, phi_nm1 hold phi_{n+nsteps}, phi_{n+nsteps-1}."""
+        import torch
+        a = _dev_ptr(phi_n, "phi_n", self.numel, torch.float64)
+        b = _dev_ptr(phi_nm1, "phi_nm1", self.numel, torch.float64)
+        check(lib.sem_ch_set_stream(self._c, c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+        check(lib.sem_ch_step(self._c, a, b, int(nsteps)))

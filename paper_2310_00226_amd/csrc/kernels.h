@@ -10,15 +10,22 @@ namespace semfd {
 enum { EPI_STORE = 0, EPI_DIVIDE = 1, EPI_ACCUM = 2 };
 
 // Arguments of the fused epilogues.
-//   EPI_DIVIDE: out = acc / (lx[row] + ly[col / nz] + lz[col % nz] + alpha)
+//   EPI_DIVIDE: out = acc / (alpha + b1 L + b2 L^2),  L = lx[row] + ly[col / nz] + lz[col % nz]
+//               (Helmholtz: b1 = 1, b2 = 0; the Cahn-Hilliard operator a + m dt eps L^2:
+//               b1 = 0, b2 = m dt eps)
 //   EPI_ACCUM : out += acc
 struct EpiArgs {
   const double* lx = nullptr;
   const double* ly = nullptr;
   const double* lz = nullptr;
-  double alpha = 0.0;
+  double alpha = 0.0, b1 = 1.0, b2 = 0.0;
   long nz = 1;
 };
+
+// Denominator of the spectral divide, FP64.
+__host__ __device__ inline double spectral_den(double lam, double alpha, double b1, double b2) {
+  return alpha + lam * (b1 + b2 * lam);
+}
 
 // One FP64 mode product along `axis` of a row-major (dims[0], dims[1], dims[2])
 // array: y[.., l, ..] = sum_m A[l][m] x[.., m, ..] with g[m * ldg + l] = A[l][m]
@@ -29,14 +36,15 @@ hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg,
 // ---- low-precision rotating mode products (mode_lp.hip) ----
 enum { LP_F32 = 1, LP_BF16 = 2, LP_BF16X3 = 3 };
 
-// Epilogue arguments: divide by l0[l] + l1[a] + l2[b] + alpha (third forward
-// pass), or accumulate into FP64 (first = 1: u = delta) recording
-// norms[0] = max|delta|, norms[1] = max|u| (bit patterns, atomic max).
+// Epilogue arguments: divide by alpha + b1 L + b2 L^2 with L = l0[l] + l1[a] +
+// l2[b] (third forward pass), or accumulate into FP64 (first = 1: u = delta)
+// recording norms[0] = max|delta|, norms[1] = max|u| (bit patterns, atomic max;
+// skipped when norms is null).
 struct EpiLP {
   const double* l0 = nullptr;
   const double* l1 = nullptr;
   const double* l2 = nullptr;
-  double alpha = 0.0;
+  double alpha = 0.0, b1 = 1.0, b2 = 0.0;
   int first = 0;
   unsigned long long* norms = nullptr;
 };
@@ -80,15 +88,24 @@ hipError_t launch_mode_dma(const LpPass& ps, hipStream_t stream);
 hipError_t launch_to_lowp(const double* f, void* out, long plane_o, int split, const int dims[3], int ldo,
                           hipStream_t stream);
 
-// Nodal residual r = f - alpha u - (H_x + H_y + H_z) u with banded H rows
-// hb[a][g * (2k+1) + d] = H_a(g, g - k + d).
-hipError_t launch_residual_f64(const double* u, const double* f, double* r, const double* const hb[3], int k,
-                               const int dims[3], double alpha, hipStream_t stream);
-
-// Same residual, written with row pitch ldr as FP32 (r_kind 1), BF16 (2) or split
-// BF16 (3: hi plane, lo plane rplane elements later) for the low-precision solves
-// of the refinement loop; the pitch padding [dims[2], ldr) is written with zeros.
-hipError_t launch_residual_lp(const double* u, const double* f, void* r, int r_kind, int ldr, long rplane,
-                              const double* const hb[3], int k, const int dims[3], double alpha, hipStream_t stream);
+// Generalised nodal residual  r = cf f - cd d - ch (H_x + H_y + H_z) v  with banded
+// H rows hb[a][g * (2k+1) + d] = H_a(g, g - k + d), FP64 arithmetic.
+//   f == nullptr: the f term is absent;  d == nullptr: d is v itself.
+//   Helmholtz residual f - alpha u - H u: (v = u, f, d = null, cf = 1, cd = alpha, ch = 1).
+// r is written with row pitch ldr >= dims[2] as FP64 (r_kind 0), FP32 (1), BF16
+// (2) or split BF16 (3: hi plane, lo plane rplane elements later); the pitch
+// padding [dims[2], ldr) is written with zeros.  r must not alias v.
+struct ResidualArgs {
+  const double* v = nullptr;
+  const double* f = nullptr;
+  const double* d = nullptr;
+  void* r = nullptr;
+  int r_kind = 0;
+  int ldr = 0;
+  long rplane = 0;
+  double cf = 1.0, cd = 0.0, ch = 1.0;
+};
+hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], int k, const int dims[3],
+                           hipStream_t stream);
 
 }  // namespace semfd

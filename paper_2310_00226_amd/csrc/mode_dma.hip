@@ -227,7 +227,7 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
   }
   double dab[FP];
 #pragma unroll
-  for (int j = 0; j < FP; ++j) dab[j] = EPI == EPI_DIVIDE ? epi.l1[aidx[j]] + epi.l2[bidx[j]] + epi.alpha : 0.0;
+  for (int j = 0; j < FP; ++j) dab[j] = EPI == EPI_DIVIDE ? epi.l1[aidx[j]] + epi.l2[bidx[j]] : 0.0;
   double dmax = 0.0, umax = 0.0;
 #pragma unroll
   for (int i = 0; i < FL; ++i)
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
           umax = fabs(un) <= DBL_MAX ? fmax(umax, fabs(un)) : INFINITY;
         } else {
           float w = v;
-          if constexpr (EPI == EPI_DIVIDE) w = __fdividef(v, (float)(dl + dab[j]));
+          if constexpr (EPI == EPI_DIVIDE) w = __fdividef(v, (float)spectral_den(dl + dab[j], epi.alpha, epi.b1, epi.b2));
           const __bf16 h = (__bf16)w;
           y[off] = __builtin_bit_cast(unsigned short, h);
           if constexpr (NS == 2) y[off + yplane] = __builtin_bit_cast(unsigned short, (__bf16)(w - (float)h));

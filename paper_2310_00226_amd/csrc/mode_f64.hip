@@ -165,7 +165,7 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
       const long q = q0 + wn + 16 * j + fr;
       const int qi = (int)(q < Q ? q : Q - 1);
       const int jy = qi / (int)epi.nz;
-      cden[j] = epi.ly[jy] + epi.lz[qi - jy * (int)epi.nz] + epi.alpha;
+      cden[j] = epi.ly[jy] + epi.lz[qi - jy * (int)epi.nz];  // partial eigenvalue sum
     }
   }
 #pragma unroll
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
         if (q >= Q) continue;
         const double v = acc[i][j][r];
         if constexpr (EPI == EPI_STORE) yrow[q] = v;
-        else if constexpr (EPI == EPI_DIVIDE) yrow[q] = v / (lxl + cden[j]);
+        else if constexpr (EPI == EPI_DIVIDE) yrow[q] = v / spectral_den(lxl + cden[j], epi.alpha, epi.b1, epi.b2);
         else yrow[q] += v;
       }
     }
@@ -307,7 +307,8 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
         if (l >= L) continue;
         const double v = acc[i][j][r];
         if constexpr (EPI == EPI_STORE) yrow[l] = v;
-        else if constexpr (EPI == EPI_DIVIDE) yrow[l] = v / (epi.lx[l] + epi.ly[0] + epi.lz[0] + epi.alpha);
+        else if constexpr (EPI == EPI_DIVIDE)
+          yrow[l] = v / spectral_den(epi.lx[l] + epi.ly[0] + epi.lz[0], epi.alpha, epi.b1, epi.b2);
         else yrow[l] += v;
       }
     }

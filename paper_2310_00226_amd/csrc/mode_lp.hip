@@ -313,9 +313,9 @@ __global__ __launch_bounds__(TT::NTHREADS) void mode_rot_lp(const TIn* __restric
     bidx[j] = pi - aidx[j] * B;
   }
   double dmax = 0.0, umax = 0.0;
-  double dab[FP];  // divide: l1[a] + l2[b] + alpha per column
+  double dab[FP];  // divide: l1[a] + l2[b] per column
 #pragma unroll
-  for (int j = 0; j < FP; ++j) dab[j] = EPI == EPI_DIVIDE ? epi.l1[aidx[j]] + epi.l2[bidx[j]] + epi.alpha : 0.0;
+  for (int j = 0; j < FP; ++j) dab[j] = EPI == EPI_DIVIDE ? epi.l1[aidx[j]] + epi.l2[bidx[j]] : 0.0;
 #pragma unroll
   for (int i = 0; i < FL; ++i)
 #pragma unroll
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(TT::NTHREADS) void mode_rot_lp(const TIn* __restric
         if constexpr (EPI == EPI_STORE || EPI == EPI_DIVIDE) {
           float w = v;
           // the quotient is rounded to FP32 / BF16 anyway: a fast float divide suffices
-          if constexpr (EPI == EPI_DIVIDE) w = __fdividef(v, (float)(dl + dab[j]));
+          if constexpr (EPI == EPI_DIVIDE) w = __fdividef(v, (float)spectral_den(dl + dab[j], epi.alpha, epi.b1, epi.b2));
           if constexpr (sizeof(TOut) == 2)
             y[off] = __builtin_bit_cast(unsigned short, (__bf16)w);
           else

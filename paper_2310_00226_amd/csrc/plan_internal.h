@@ -38,6 +38,27 @@ struct sem_plan {
 };
 
 namespace semfd {
+// Spectral multiplier of an FD application: 1 / (alpha + b1 L + b2 L^2) with L the
+// sum of the three 1D eigenvalues (Helmholtz: {alpha, 1, 0}).
+struct Spectral {
+  double alpha, b1, b2;
+};
+// Buffers of the low-precision solves inside the plan workspace.
+struct LpWork {
+  sem_prec prec = SEM_F32;
+  void* r = nullptr;        // residual / right-hand side in the intermediate format
+  void* t0 = nullptr;       // rotating intermediates
+  void* t1 = nullptr;
+  unsigned long long* norms = nullptr;  // 2 x FP64 bit patterns
+  int rkind = 1, ldr = 0;   // ResidualArgs.r_kind and row pitch of r
+  long rplane = 0, tplane = 0;
+};
+sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w);
+hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u, int first,
+                 unsigned long long* norms);
+hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp);
+hipError_t zero_norms(unsigned long long* norms, hipStream_t stream);
+
 sem_status hip_fail(hipError_t e, const char* what);
 sem_status set_error(sem_status st, const char* msg);
 sem_status plan_workspace(sem_plan* p, size_t need, void** out);

@@ -133,17 +133,56 @@ static sem_status ensure_lowp(sem_plan* p) {
   return SEM_OK;
 }
 
-// One low-precision FD solve of `src`, accumulated into u.
-//  FP32: src is the FP64 right-hand side in the caller's layout (src_lp = 0) or
-//        the FP32 residual with row pitch pad8(nz) (src_lp = 1);
-//  BF16 / split BF16: src is always in BF16 planes with row pitch pad8(nz)
-//        (rplane = offset of the lo plane); t0 / t1 have planes tplane apart.
-static hipError_t lp_solve(sem_plan* p, sem_prec prec, const void* src, int src_lp, long rplane, double* u, void* t0,
-                           void* t1, long tplane, unsigned long long* norms, int first) {
+// Workspace layout of the low-precision solves (see workspace_need).
+sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w) {
+  if (prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3) return set_error(SEM_EINVAL, "unknown precision");
+  if (p->dims[0] > 46340 || (long)p->dims[1] * p->dims[2] > 0x7fffffffL ||
+      (long)p->dims[0] * p->dims[2] > 0x7fffffffL || (long)p->dims[0] * p->dims[1] > 0x7fffffffL)
+    return set_error(SEM_EINVAL, "problem too large for the low-precision kernels");
+  sem_status st = ensure_lowp(p);
+  if (st != SEM_OK) return st;
+  void* ws = nullptr;
+  st = plan_workspace(p, workspace_need(p, prec), &ws);
+  if (st != SEM_OK) return st;
+  char* b = (char*)ws;
+  const bool split = lp_split(prec);
+  const size_t rbytes = lp_r_bytes(p, prec);
+  const size_t tbytes = ((lp_tmp_elems(p) * lp_elem(prec) + 255) / 256) * 256;
+  w->prec = prec;
+  w->r = b;
+  w->t0 = b + rbytes;
+  w->t1 = b + rbytes + tbytes;
+  w->norms = (unsigned long long*)(b + rbytes + 2 * tbytes);
+  w->rkind = prec == SEM_F32 ? 1 : split ? 3 : 2;
+  w->ldr = pad8(p->dims[2]);
+  w->rplane = split ? (long)lp_r_elems(p) : 0;
+  w->tplane = split ? (long)lp_tmp_elems(p) : 0;
+  return SEM_OK;
+}
+
+// One low-precision FD application  u (+)= S_3 [ (F_3 src) / (alpha + b1 L + b2 L^2) ].
+//  f64_src != null: the FP64 right-hand side in the caller's layout (FP32 reads it
+//    directly; the BF16 modes first convert it into w.r);
+//  f64_src == null: src is w.r, written by the residual kernel in the
+//    intermediate format (row pitch w.ldr).
+//  first = 1 stores u = delta, else u += delta; norms (may be null) receive
+//  max|delta| and max|u| as FP64 bit patterns (the caller zeroes them).
+hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u, int first,
+                 unsigned long long* norms) {
+  const sem_prec prec = w.prec;
   const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
   const int mode = prec == SEM_F32 ? LP_F32 : prec == SEM_BF16 ? LP_BF16 : LP_BF16X3;
   const bool dma = mode != LP_F32;
   const int lpk = mode == LP_F32 ? 1 : 2;  // intermediate kind (FP32 / BF16 planes)
+  if (f64_src && dma) {
+    hipError_t e = launch_to_lowp(f64_src, w.r, w.rplane, mode == LP_BF16X3 ? 1 : 0, p->dims, w.ldr, p->stream);
+    if (e != hipSuccess) return e;
+  }
+  const bool from_r = !f64_src || dma;
+  const void* src = from_r ? w.r : (const void*)f64_src;
+  void* t0 = w.t0;
+  void* t1 = w.t1;
+  const long tplane = w.tplane;
   // the six passes: (input, ldx, A, B, K) -> (output, ldy); axis contracted = K's axis
   struct Step {
     const void* x;
@@ -152,9 +191,9 @@ static hipError_t lp_solve(sem_plan* p, sem_prec prec, const void* src, int src_
     int ldy, in_kind, out_kind, epi;
     long xplane, yplane;
   };
-  const int in0 = (src_lp || dma) ? lpk : 0;
+  const int in0 = from_r ? lpk : 0;
   const Step st[6] = {
-      {src, in0 ? pad8(nz) : nz, nx, ny, nz, 2, 0, t0, pad8(ny), in0, lpk, EPI_STORE, rplane, tplane},
+      {src, from_r ? w.ldr : nz, nx, ny, nz, 2, 0, t0, pad8(ny), in0, lpk, EPI_STORE, w.rplane, tplane},
       {t0, pad8(ny), nz, nx, ny, 1, 0, t1, pad8(nx), lpk, lpk, EPI_STORE, tplane, tplane},
       {t1, pad8(nx), ny, nz, nx, 0, 0, t0, pad8(nz), lpk, lpk, EPI_DIVIDE, tplane, tplane},
       {t0, pad8(nz), nx, ny, nz, 2, 1, t1, pad8(ny), lpk, lpk, EPI_STORE, tplane, tplane},
@@ -190,7 +229,9 @@ static hipError_t lp_solve(sem_plan* p, sem_prec prec, const void* src, int src_
       ps.epi.l0 = p->d_lam[0];
       ps.epi.l1 = p->d_lam[1];
       ps.epi.l2 = p->d_lam[2];
-      ps.epi.alpha = p->alpha;
+      ps.epi.alpha = sp.alpha;
+      ps.epi.b1 = sp.b1;
+      ps.epi.b2 = sp.b2;
     }
     if (st[s].epi == EPI_ACCUM) {
       ps.epi.first = first;
@@ -206,6 +247,34 @@ static hipError_t lp_solve(sem_plan* p, sem_prec prec, const void* src, int src_
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// FP64 FD application u = S_3 [ (F_3 f) / (alpha + b1 L + b2 L^2) ]; tmp holds N
+// doubles; u may alias f.
+hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp) {
+  EpiArgs none;
+  EpiArgs div;
+  div.lx = p->d_lam[0];
+  div.ly = p->d_lam[1];
+  div.lz = p->d_lam[2];
+  div.alpha = sp.alpha;
+  div.b1 = sp.b1;
+  div.b2 = sp.b2;
+  div.nz = p->dims[2];
+  hipError_t e;
+  if ((e = launch_mode_f64(f, tmp, p->d_gf[2], p->ld[2], p->dims, 2, EPI_STORE, none, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(tmp, u, p->d_gf[1], p->ld[1], p->dims, 1, EPI_STORE, none, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(u, tmp, p->d_gf[0], p->ld[0], p->dims, 0, EPI_DIVIDE, div, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(tmp, u, p->d_gb[2], p->ld[2], p->dims, 2, EPI_STORE, none, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(u, tmp, p->d_gb[1], p->ld[1], p->dims, 1, EPI_STORE, none, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(tmp, u, p->d_gb[0], p->ld[0], p->dims, 0, EPI_STORE, none, p->stream)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
+hipError_t zero_norms(unsigned long long* norms, hipStream_t stream) {
+  zero_u64_kernel<<<1, 64, 0, stream>>>(norms, 2);
+  return hipGetLastError();
 }
 
 }  // namespace semfd
@@ -227,48 +296,32 @@ extern "C" sem_status sem_solve_refined(sem_plan* p, sem_prec prec, double tol, 
   }
   if (prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3)
     return set_error(SEM_EINVAL, "sem_solve_refined: unknown precision");
-  if (p->dims[0] > 46340 || (long)p->dims[1] * p->dims[2] > 0x7fffffffL ||
-      (long)p->dims[0] * p->dims[2] > 0x7fffffffL || (long)p->dims[0] * p->dims[1] > 0x7fffffffL)
-    return set_error(SEM_EINVAL, "sem_solve_refined: problem too large for the low-precision kernels");
-  sem_status st = ensure_lowp(p);
+  LpWork w;
+  sem_status st = lp_prepare(p, prec, &w);
   if (st != SEM_OK) return st;
-  void* ws = nullptr;
-  st = plan_workspace(p, workspace_need(p, prec), &ws);
-  if (st != SEM_OK) return st;
-  char* w = (char*)ws;
-  void* r = w;
-  const size_t rbytes = lp_r_bytes(p, prec);
-  const bool split = lp_split(prec);
-  const bool dma = prec != SEM_F32;
-  const int rkind = prec == SEM_F32 ? 1 : split ? 3 : 2;
-  const long rplane = split ? (long)lp_r_elems(p) : 0;
-  const size_t tbytes = ((lp_tmp_elems(p) * lp_elem(prec) + 255) / 256) * 256;
-  const long tplane = split ? (long)lp_tmp_elems(p) : 0;
-  void* t0 = w + rbytes;
-  void* t1 = w + rbytes + tbytes;
-  unsigned long long* norms = (unsigned long long*)(w + rbytes + 2 * tbytes);
   const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
-  const int ldr = pad8(p->dims[2]);
+  const Spectral sp{p->alpha, 1.0, 0.0};
+  ResidualArgs ra;  // r = f - alpha u - H_3 u in the intermediate format
+  ra.v = u;
+  ra.f = f;
+  ra.r = w.r;
+  ra.r_kind = w.rkind;
+  ra.ldr = w.ldr;
+  ra.rplane = w.rplane;
+  ra.cf = 1.0;
+  ra.cd = p->alpha;
+  ra.ch = 1.0;
 
   double prev = INFINITY, prev2 = INFINITY;
   for (int it = 0; it < max_iter; ++it) {
     hipError_t e;
-    if (it > 0) {
-      if ((e = launch_residual_lp(u, f, r, rkind, ldr, rplane, hb, p->k, p->dims, p->alpha, p->stream)) !=
-          hipSuccess)
-        return hip_fail(e, "sem_solve_refined: residual");
-    } else if (dma) {
-      if ((e = launch_to_lowp(f, r, rplane, split ? 1 : 0, p->dims, ldr, p->stream)) != hipSuccess)
-        return hip_fail(e, "sem_solve_refined: right-hand side conversion");
-    }
-    zero_u64_kernel<<<1, 64, 0, p->stream>>>(norms, 2);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sem_solve_refined: norm reset");
-    const bool from_r = it > 0 || dma;
-    if ((e = lp_solve(p, prec, from_r ? (const void*)r : (const void*)f, from_r ? 1 : 0, rplane, u, t0, t1, tplane,
-                      norms, it == 0 ? 1 : 0)) != hipSuccess)
+    if (it > 0 && (e = launch_residual(ra, hb, p->k, p->dims, p->stream)) != hipSuccess)
+      return hip_fail(e, "sem_solve_refined: residual");
+    if ((e = zero_norms(w.norms, p->stream)) != hipSuccess) return hip_fail(e, "sem_solve_refined: norm reset");
+    if ((e = lp_fd(p, w, sp, it == 0 ? f : nullptr, u, it == 0 ? 1 : 0, w.norms)) != hipSuccess)
       return hip_fail(e, "sem_solve_refined: low-precision solve");
     unsigned long long hn[2];
-    if ((e = hipMemcpyAsync(hn, norms, sizeof(hn), hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
+    if ((e = hipMemcpyAsync(hn, w.norms, sizeof(hn), hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(p->stream)) != hipSuccess)
       return hip_fail(e, "sem_solve_refined: norm readback");
     double dmax, umax;

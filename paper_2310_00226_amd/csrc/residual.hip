@@ -7,12 +7,16 @@
 // elements it belongs to); the plan stores its rows densely as
 // hb[g * (2k+1) + d] = H(g, g - k + d), zero outside the matrix.
 //
-// HBM-bound: per node it reads u and f and writes r (24 bytes).  A block owns a
-// (4 y) x (64 z) column of nodes and marches along x: the 2k+1 values of u along
-// x that a node needs sit in a register window (each u value is loaded once, as
-// the window front), the y and z neighbours of the current plane come through
-// the L1 cache, and the band coefficients of H_y, H_z of the thread's (j, l)
-// stay in registers for the whole march.
+// The kernels evaluate the general form  r = cf f - cd d - ch H_3 v  (see
+// ResidualArgs), which also gives H_3 v alone and the residual of the
+// Cahn-Hilliard operator a I + c H_3^2 in two passes.
+//
+// HBM-bound: per node it reads v and f and writes r (24 bytes in FP64).  A block
+// owns a (4 y) x (64 z) column of nodes and marches along x: the 2k+1 values of v
+// along x that a node needs sit in a register window (each v value is loaded
+// once, as the window front), the y and z neighbours of the current plane come
+// through the L1 cache, and the band coefficients of H_y, H_z of the thread's
+// (j, l) stay in registers for the whole march.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +24,8 @@
 #include "kernels.h"
 
 namespace semfd {
+
+namespace {
 
 // Stores of one residual value; BF16 with a nonzero plane offset stores the split
 // pair (hi at i, lo = v - hi at i + plane).
@@ -37,16 +43,18 @@ __device__ __forceinline__ void zero_pad(TR* r, size_t row0, int nz, int ldr, lo
   for (int e = nz; e < ldr; ++e) put(r, row0 + e, 0.0, plane);
 }
 
-// r is written with row pitch ldr (>= nz) in type TR: FP64 for sem_residual,
-// FP32 / BF16 / split BF16 when it only feeds a low-precision solve (refinement).
-template <int KH, class TR>
-__global__ __launch_bounds__(256) void residual_f64_kernel(const double* __restrict__ u, const double* __restrict__ f,
-                                                           TR* __restrict__ r, int ldr, long rplane,
-                                                           const double* __restrict__ hx,
+struct Coef {
+  double cf, cd, ch;
+};
+
+// Generic kernel (any k): one thread per node.
+template <class TR>
+__global__ __launch_bounds__(256) void residual_any_kernel(const double* __restrict__ v, const double* __restrict__ f,
+                                                           const double* __restrict__ dg, TR* __restrict__ r, int ldr,
+                                                           long rplane, const double* __restrict__ hx,
                                                            const double* __restrict__ hy,
-                                                           const double* __restrict__ hz, int kh, int nx, int ny,
-                                                           int nz, double alpha) {
-  const int k = KH > 0 ? KH : kh;
+                                                           const double* __restrict__ hz, int k, int nx, int ny,
+                                                           int nz, Coef c) {
   const int bw = 2 * k + 1;
   const long jl = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long plane = (long)ny * nz;
@@ -55,43 +63,43 @@ __global__ __launch_bounds__(256) void residual_f64_kernel(const double* __restr
   const int j = (int)(jl / nz);
   const int l = (int)(jl - (long)j * nz);
   const size_t idx = (size_t)i * plane + jl;
-  double s = alpha * u[idx];
-  // z (contiguous)
+  double s = 0.0;
   {
     const double* hrow = hz + (size_t)l * bw;
     const int d0 = l - k < 0 ? k - l : 0;
     const int d1 = l + k >= nz ? k + (nz - 1 - l) : 2 * k;
-    for (int d = d0; d <= d1; ++d) s += hrow[d] * u[idx + (d - k)];
+    for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (d - k)];
   }
-  // y
   {
     const double* hrow = hy + (size_t)j * bw;
     const int d0 = j - k < 0 ? k - j : 0;
     const int d1 = j + k >= ny ? k + (ny - 1 - j) : 2 * k;
-    for (int d = d0; d <= d1; ++d) s += hrow[d] * u[idx + (long)(d - k) * nz];
+    for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (long)(d - k) * nz];
   }
-  // x
   {
     const double* hrow = hx + (size_t)i * bw;
     const int d0 = i - k < 0 ? k - i : 0;
     const int d1 = i + k >= nx ? k + (nx - 1 - i) : 2 * k;
-    for (int d = d0; d <= d1; ++d) s += hrow[d] * u[idx + (long)(d - k) * plane];
+    for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (long)(d - k) * plane];
   }
+  const double dv = dg ? dg[idx] : v[idx];
+  const double fv = f ? f[idx] : 0.0;
   const size_t row0 = ((size_t)i * ny + j) * ldr;
-  put(r, row0 + l, f[idx] - s, rplane);
+  put(r, row0 + l, c.cf * fv - c.cd * dv - c.ch * s, rplane);
   if (l == nz - 1) zero_pad(r, row0, nz, ldr, rplane);
 }
 
 constexpr int RY = 4, RZ = 64;
 
 template <int KH, class TR>
-__global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* __restrict__ u,
-                                                                  const double* __restrict__ f, TR* __restrict__ r,
+__global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* __restrict__ v,
+                                                                  const double* __restrict__ f,
+                                                                  const double* __restrict__ dg, TR* __restrict__ r,
                                                                   int ldr, long rplane,
                                                                   const double* __restrict__ hx,
                                                                   const double* __restrict__ hy,
                                                                   const double* __restrict__ hz, int nx, int ny,
-                                                                  int nz, int xchunk, double alpha) {
+                                                                  int nz, int xchunk, Coef c) {
   constexpr int BW = 2 * KH + 1;
   // one wave = one y row (RZ = 64 lanes along z): j and everything derived from it
   // is wave-uniform and lives in scalar registers
@@ -102,6 +110,7 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* _
   if (l >= nz || j >= ny) return;  // no barriers below: early exit is safe
   const long plane = (long)ny * nz;
   const long col = (long)j * nz + l;
+  const bool has_f = f != nullptr, has_d = dg != nullptr;  // uniform
   double cz[BW];
   int oz[BW];
   bool okz[BW];
@@ -116,27 +125,28 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* _
     oz[d] = (okz[d] ? ll : l) - l;
   }
   const double* __restrict__ cyr = hy + (size_t)j * BW;  // uniform
-  // x window: w[d] = u[i - KH + d], zero outside [0, nx)
+  // x window: w[d] = v[i - KH + d], zero outside [0, nx)
   double w[BW];
 #pragma unroll
   for (int d = 0; d < BW; ++d) {
     const int ii = i0 - KH + d;
-    const double v = u[(size_t)(ii < 0 ? 0 : (ii >= nx ? nx - 1 : ii)) * plane + col];
-    w[d] = (ii >= 0 && ii < nx) ? v : 0.0;
+    const double x = v[(size_t)(ii < 0 ? 0 : (ii >= nx ? nx - 1 : ii)) * plane + col];
+    w[d] = (ii >= 0 && ii < nx) ? x : 0.0;
   }
   // software pipeline: the loads of plane i+1 are issued before plane i is reduced
-  double vy[BW], vz[BW], wn, fv;
+  double vy[BW], vz[BW], wn, fv, dv;
   auto load_plane = [&](int i) {
     const size_t idx = (size_t)i * plane + col;
 #pragma unroll
     for (int d = 0; d < BW; ++d) {
       const int jj = j - KH + d;
-      vy[d] = u[idx + (long)((jj >= 0 && jj < ny ? jj : j) - j) * nz];
-      vz[d] = u[idx + oz[d]];
+      vy[d] = v[idx + (long)((jj >= 0 && jj < ny ? jj : j) - j) * nz];
+      vz[d] = v[idx + oz[d]];
     }
     const int inext = i + KH + 1;
-    wn = u[(size_t)(inext < nx ? inext : nx - 1) * plane + col];
-    fv = f[idx];
+    wn = v[(size_t)(inext < nx ? inext : nx - 1) * plane + col];
+    fv = has_f ? f[idx] : 0.0;
+    dv = has_d ? dg[idx] : 0.0;
   };
   if (i0 < i1) load_plane(i0);
   for (int i = i0; i < i1; ++i) {
@@ -149,10 +159,11 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* _
     }
     const double wnext = i + KH + 1 < nx ? wn : 0.0;
     const double fcur = fv;
+    const double dcur = has_d ? dv : w[KH];
     load_plane(i + 1 < i1 ? i + 1 : i);  // unconditional (the last step reloads a valid plane)
     __builtin_amdgcn_sched_barrier(0);    // keep the prefetch ahead of the reduction
     const double* __restrict__ hxr = hx + (size_t)i * BW;
-    double s = alpha * w[KH];
+    double s = 0.0;
 #pragma unroll
     for (int d = 0; d < BW; ++d) {
       s += hxr[d] * w[d];
@@ -160,7 +171,7 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* _
       s += cz[d] * cz_vz[d];
     }
     const size_t row0 = ((size_t)i * ny + j) * ldr;
-    put(r, row0 + l, fcur - s, rplane);
+    put(r, row0 + l, c.cf * fcur - c.cd * dcur - c.ch * s, rplane);
     if (l == nz - 1) zero_pad(r, row0, nz, ldr, rplane);
 #pragma unroll
     for (int d = 0; d + 1 < BW; ++d) w[d] = w[d + 1];
@@ -169,58 +180,65 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* _
 }
 
 template <int KH, class TR>
-static void launch_march(const double* u, const double* f, TR* r, int ldr, long rplane, const double* const hb[3],
-                         const int dims[3], double alpha, hipStream_t stream) {
+void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], const int dims[3], Coef c,
+                  hipStream_t stream) {
   // split x into chunks so that the grid fills the chip even for thin (y, z) planes
   const long cols = (long)((dims[2] + RZ - 1) / RZ) * ((dims[1] + RY - 1) / RY);
   int nchunks = (int)std::min<long>(dims[0], std::max<long>(1, (16384 + cols - 1) / cols));
   const int xchunk = (dims[0] + nchunks - 1) / nchunks;
   nchunks = (dims[0] + xchunk - 1) / xchunk;
   dim3 grid((unsigned)((dims[2] + RZ - 1) / RZ), (unsigned)((dims[1] + RY - 1) / RY), (unsigned)nchunks);
-  residual_march_kernel<KH, TR><<<grid, dim3(RY * RZ), 0, stream>>>(u, f, r, ldr, rplane, hb[0], hb[1], hb[2], dims[0],
-                                                                     dims[1], dims[2], xchunk, alpha);
+  residual_march_kernel<KH, TR><<<grid, dim3(RY * RZ), 0, stream>>>(ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0],
+                                                                     hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
+                                                                     c);
 }
 
 template <class TR>
-static hipError_t launch_res(const double* u, const double* f, TR* r, int ldr, long rplane, const double* const hb[3],
-                             int k,
-                             const int dims[3], double alpha, hipStream_t stream) {
-  const long plane = (long)dims[1] * dims[2];
-  if (dims[0] <= 0 || plane <= 0) return hipSuccess;
-  if ((dims[1] + RY - 1) / RY > 65535 || dims[0] > 65535) return hipErrorInvalidValue;
+hipError_t launch_typed(const ResidualArgs& ra, TR* r, const double* const hb[3], int k, const int dims[3],
+                        hipStream_t stream) {
+  const Coef c{ra.cf, ra.cd, ra.ch};
   switch (k) {
-    case 1: launch_march<1, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
-    case 2: launch_march<2, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
-    case 3: launch_march<3, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
-    case 4: launch_march<4, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
-    case 5: launch_march<5, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
-    case 6: launch_march<6, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
-    case 7: launch_march<7, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
-    case 8: launch_march<8, TR>(u, f, r, ldr, rplane, hb, dims, alpha, stream); break;
+    case 1: launch_march<1, TR>(ra, r, hb, dims, c, stream); break;
+    case 2: launch_march<2, TR>(ra, r, hb, dims, c, stream); break;
+    case 3: launch_march<3, TR>(ra, r, hb, dims, c, stream); break;
+    case 4: launch_march<4, TR>(ra, r, hb, dims, c, stream); break;
+    case 5: launch_march<5, TR>(ra, r, hb, dims, c, stream); break;
+    case 6: launch_march<6, TR>(ra, r, hb, dims, c, stream); break;
+    case 7: launch_march<7, TR>(ra, r, hb, dims, c, stream); break;
+    case 8: launch_march<8, TR>(ra, r, hb, dims, c, stream); break;
     default: {
+      const long plane = (long)dims[1] * dims[2];
       dim3 block(256), grid((unsigned)((plane + 255) / 256), (unsigned)dims[0]);
-      residual_f64_kernel<0, TR><<<grid, block, 0, stream>>>(u, f, r, ldr, rplane, hb[0], hb[1], hb[2], k, dims[0], dims[1],
-                                                            dims[2], alpha);
+      residual_any_kernel<TR><<<grid, block, 0, stream>>>(ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2],
+                                                          k, dims[0], dims[1], dims[2], c);
     }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_residual_f64(const double* u, const double* f, double* r, const double* const hb[3], int k,
-                               const int dims[3], double alpha, hipStream_t stream) {
-  return launch_res<double>(u, f, r, dims[2], 0, hb, k, dims, alpha, stream);
-}
+}  // namespace
 
-hipError_t launch_residual_lp(const double* u, const double* f, void* r, int r_kind, int ldr, long rplane,
-                              const double* const hb[3], int k, const int dims[3], double alpha, hipStream_t stream) {
-  if (ldr < dims[2]) return hipErrorInvalidValue;
-  if (r_kind == 1) return launch_res<float>(u, f, (float*)r, ldr, 0, hb, k, dims, alpha, stream);
-  if (r_kind == 2) return launch_res<unsigned short>(u, f, (unsigned short*)r, ldr, 0, hb, k, dims, alpha, stream);
-  if (r_kind == 3) {
-    if (rplane <= 0) return hipErrorInvalidValue;
-    return launch_res<unsigned short>(u, f, (unsigned short*)r, ldr, rplane, hb, k, dims, alpha, stream);
+hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], int k, const int dims[3],
+                           hipStream_t stream) {
+  const long plane = (long)dims[1] * dims[2];
+  if (dims[0] <= 0 || plane <= 0) return hipSuccess;
+  if (!ra.v || !ra.r || ra.ldr < dims[2] || k < 1) return hipErrorInvalidValue;
+  if ((dims[1] + RY - 1) / RY > 65535 || dims[0] > 65535 || (plane + 255) / 256 > 0x7fffffffL)
+    return hipErrorInvalidValue;
+  switch (ra.r_kind) {
+    case 0: return launch_typed<double>(ra, (double*)ra.r, hb, k, dims, stream);
+    case 1: return launch_typed<float>(ra, (float*)ra.r, hb, k, dims, stream);
+    case 2: {
+      ResidualArgs rb = ra;
+      rb.rplane = 0;
+      return launch_typed<unsigned short>(rb, (unsigned short*)ra.r, hb, k, dims, stream);
+    }
+    case 3:
+      if (ra.rplane <= 0) return hipErrorInvalidValue;
+      return launch_typed<unsigned short>(ra, (unsigned short*)ra.r, hb, k, dims, stream);
+    default:
+      return hipErrorInvalidValue;
   }
-  return launch_res<double>(u, f, (double*)r, ldr, 0, hb, k, dims, alpha, stream);
 }
 
 }  // namespace semfd

@@ -263,22 +263,8 @@ sem_status sem_solve(sem_plan* p, const double* f, double* u) {
   void* ws = nullptr;
   sem_status st = plan_workspace(p, workspace_need(p, SEM_F64), &ws);
   if (st != SEM_OK) return st;
-  double* tmp = (double*)ws;
-  EpiArgs none;
-  EpiArgs div;
-  div.lx = p->d_lam[0];
-  div.ly = p->d_lam[1];
-  div.lz = p->d_lam[2];
-  div.alpha = p->alpha;
-  div.nz = p->dims[2];
-  hipError_t e;
-  if ((e = launch_mode_f64(f, tmp, p->d_gf[2], p->ld[2], p->dims, 2, EPI_STORE, none, p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(tmp, u, p->d_gf[1], p->ld[1], p->dims, 1, EPI_STORE, none, p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(u, tmp, p->d_gf[0], p->ld[0], p->dims, 0, EPI_DIVIDE, div, p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(tmp, u, p->d_gb[2], p->ld[2], p->dims, 2, EPI_STORE, none, p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(u, tmp, p->d_gb[1], p->ld[1], p->dims, 1, EPI_STORE, none, p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(tmp, u, p->d_gb[0], p->ld[0], p->dims, 0, EPI_STORE, none, p->stream)) != hipSuccess)
-    return hip_fail(e, "sem_solve");
+  hipError_t e = fd64(p, Spectral{p->alpha, 1.0, 0.0}, f, u, (double*)ws);
+  if (e != hipSuccess) return hip_fail(e, "sem_solve");
   return SEM_OK;
 }
 
@@ -286,7 +272,16 @@ sem_status sem_residual(sem_plan* p, const double* u, const double* f, double* r
   if (!p || !u || !f || !r) return fail(SEM_EINVAL, "sem_residual: null argument");
   if (r == u) return fail(SEM_EINVAL, "sem_residual: r must not alias u");
   const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
-  hipError_t e = launch_residual_f64(u, f, r, hb, p->k, p->dims, p->alpha, p->stream);
+  ResidualArgs ra;
+  ra.v = u;
+  ra.f = f;
+  ra.r = r;
+  ra.r_kind = 0;
+  ra.ldr = p->dims[2];
+  ra.cf = 1.0;
+  ra.cd = p->alpha;
+  ra.ch = 1.0;
+  hipError_t e = launch_residual(ra, hb, p->k, p->dims, p->stream);
   if (e != hipSuccess) return hip_fail(e, "sem_residual");
   return SEM_OK;
 }

@@ -82,3 +82,20 @@ def test_plan_lowest_eigenvalues_match_continuous_spectrum_n999(P, bc):
     j = np.arange(1, 6) if bc == "dirichlet" else np.arange(0, 5)
     err = np.abs(d["lam"][:5] - (j * np.pi / 2) ** 2)
     assert np.all(err <= 5e-14 * (1 + j ** 2)), err
+
+
+@pytest.mark.parametrize("eps,mob,dt,prec,sweeps", [
+    (0.0, 0.02, 1e-4, 1, 2),            # eps must be > 0
+    (0.05, -1.0, 1e-4, 1, 2),           # mobility must be > 0
+    (0.05, 0.02, float("nan"), 1, 2),   # dt must be finite
+    (0.05, 0.02, 1e-4, 7, 2),           # unknown precision
+    (0.05, 0.02, 1e-4, 1, -1),          # negative sweep count
+])
+def test_ch_create_rejects_invalid(P, eps, mob, dt, prec, sweeps):
+    # argument checks come before any device work, so this runs without a GPU
+    import ctypes
+    ne = (ctypes.c_int * 3)(4, 4, 4)
+    box = (ctypes.c_double * 6)(0, 1, 0, 1, 0, 1)
+    out = ctypes.c_void_p(None)
+    st = P.lib.sem_ch_create(4, ne, box, eps, mob, dt, prec, sweeps, ctypes.byref(out))
+    assert st == 1 and not out.value  # SEM_EINVAL, nothing created
