@@ -119,6 +119,37 @@ sem_status sem_residual(sem_plan *p, const double *u, const double *f, double *r
 sem_status sem_solve_refined(sem_plan *p, sem_prec prec, double tol, int max_iter, const double *f, double *u,
                              int *iters, double *last_update_rel);
 
+/* ---- batched solves ---------------------------------------------------------- */
+
+typedef struct sem_batch sem_batch;
+
+/* A batch of `count` independent problems, one plan each (any mix of k <= 8,
+ * element counts, boxes, alpha and BC; all on one device).  The plans are not
+ * owned and must outlive the batch; the batch uses their workspaces.  Creation
+ * prepares the FP32 factors and workspaces of every plan, then times the
+ * candidate tile shapes of the FP32 mode-product kernel on the batch's own passes
+ * and keeps the fastest per contraction-length bucket.
+ * Synchronous.  SEM_EINVAL: count < 1, a null or repeated plan, k > 8, plans on
+ * different devices. */
+sem_status sem_batch_create(int count, sem_plan *const *plans, sem_batch **out);
+void sem_batch_destroy(sem_batch *b);
+sem_status sem_batch_set_stream(sem_batch *b, void *hip_stream);
+/* Block-tile rows chosen per contraction-length bucket n <= 16, 32, 64, 128, 256,
+ * > 256 (0 = no such length in the batch). */
+sem_status sem_batch_tile_rows(const sem_batch *b, int rows[6]);
+/* Solve all problems: f[i], u[i] are device arrays of plan i's N_i doubles (host
+ * arrays of count device pointers; u[i] must not alias f[i]).
+ *  SEM_F32: the refinement of sem_solve_refined for every problem at once; each
+ *           of the six mode products of an iteration is one persistent launch per
+ *           tile shape over all still-unconverged problems, each residual one
+ *           launch per k.  One synchronisation per iteration (norm read-back).
+ *  SEM_F64: one FP64 sem_solve per problem on the batch stream.
+ * iters (host array of count, may be NULL) receives the iterations per problem.
+ * Returns SEM_ENONFINITE if a problem produced a non-finite update, else
+ * SEM_ENOCONV if a problem stopped without meeting tol (diverging, or max_iter). */
+sem_status sem_batch_solve(sem_batch *b, sem_prec prec, double tol, int max_iter, const double *const *f,
+                           double *const *u, int *iters);
+
 /* ---- Cahn-Hilliard IMEX time stepping (Sec. 3.6) ---------------------------- */
 
 typedef struct sem_ch sem_ch;

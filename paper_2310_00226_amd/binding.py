@@ -46,6 +46,12 @@ def _load():
         "sem_solve_refined": (c_int, [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, POINTER(c_int),
                                       POINTER(c_double)]),
         "sem_axis_host": (c_int, [c_int, c_int, c_double, c_double, c_int, POINTER(c_int), dp, dp, dp, dp, dp]),
+        "sem_batch_create": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p)]),
+        "sem_batch_destroy": (None, [c_void_p]),
+        "sem_batch_set_stream": (c_int, [c_void_p, c_void_p]),
+        "sem_batch_tile_rows": (c_int, [c_void_p, POINTER(c_int)]),
+        "sem_batch_solve": (c_int, [c_void_p, c_int, c_double, c_int, POINTER(c_void_p), POINTER(c_void_p),
+                                    POINTER(c_int)]),
         "sem_ch_create": (c_int, [c_int, POINTER(c_int), dp, c_double, c_double, c_double, c_int, c_int,
                                   POINTER(c_void_p)]),
         "sem_ch_destroy": (None, [c_void_p]),
@@ -245,3 +251,48 @@ class CahnHilliard:
         b = _dev_ptr(phi_nm1, "phi_nm1", self.numel, torch.float64)
         check(lib.sem_ch_set_stream(self._c, c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
         check(lib.sem_ch_step(self._c, a, b, int(nsteps)))
+
+
+class Batch:
+    """Batched solves over several plans (sem_batch_create / sem_batch_solve)."""
+
+    def __init__(self, plans):
+        import torch
+        self.plans = list(plans)  # keep the plans alive
+        arr = (c_void_p * len(self.plans))(*[p._p.value for p in self.plans])
+        self._b = c_void_p(None)
+        with torch.cuda.device(self.plans[0].device):
+            check(lib.sem_batch_create(len(self.plans), arr, ctypes.byref(self._b)))
+
+    def __del__(self):
+        b = getattr(self, "_b", None)
+        if b is not None and b.value:
+            lib.sem_batch_destroy(b)
+            self._b = c_void_p(None)
+
+    def close(self):
+        self.__del__()
+
+    def tile_rows(self):
+        rows = (c_int * 6)()
+        check(lib.sem_batch_tile_rows(self._b, rows))
+        return list(rows)
+
+    def solve(self, fs, us, prec: str = "f32", tol: float = 1e-11, max_iter: int = 30,
+              raise_on_error: bool = True):
+        """Solve every problem; returns (per-problem iterations, status)."""
+        import torch
+        n = len(self.plans)
+        if len(fs) != n or len(us) != n:
+            raise ValueError("one right-hand side and one solution per plan")
+        fp = (c_void_p * n)(*[_dev_ptr(f, f"f[{i}]", p.numel, torch.float64).value
+                              for i, (f, p) in enumerate(zip(fs, self.plans))])
+        up = (c_void_p * n)(*[_dev_ptr(u, f"u[{i}]", p.numel, torch.float64).value
+                              for i, (u, p) in enumerate(zip(us, self.plans))])
+        pv = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        its = (c_int * n)()
+        check(lib.sem_batch_set_stream(self._b, c_void_p(torch.cuda.current_stream(self.plans[0].device).cuda_stream)))
+        st = lib.sem_batch_solve(self._b, pv, float(tol), int(max_iter), fp, up, its)
+        if raise_on_error:
+            check(st)
+        return list(its), st

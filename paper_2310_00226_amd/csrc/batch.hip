@@ -1,0 +1,442 @@
+// Batched mixed-precision solves: many independent problems of different sizes
+// solved together, each pass of the six-product FD solve of eq. 3D-Poisson and
+// each FP64 residual launched once for the whole batch.
+//
+// A solve call builds, for every pass, one descriptor per solve (operands,
+// geometry, epilogue, tile range in the launch's global tile numbering); the FP32
+// pass kernel runs persistently over all tiles of all solves, and the residual
+// kernel over all blocks of all solves with the same element degree k.  Solves
+// that meet the tolerance drop out through a per-solve active flag, so later
+// iterations only work on the rest.
+//
+// Tile shape: the FP32 kernel has 128 x 128, 64 x 128 and 32 x 128 block tiles
+// (factor rows x tensor rows).  Short contraction lengths waste most of a
+// 128-row factor tile, so the shape is chosen per length bucket (16, 32, 64, 128,
+// 256, 512 and above) by timing the candidates on the batch's own passes when the
+// batch is created (an autotuner).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+#include "plan_internal.h"
+
+namespace semfd {
+namespace {
+
+constexpr int NBUCKET = 6;
+constexpr int TILE_CANDIDATES[3] = {128, 64, 32};
+// pass variants: 0 = forward z from f (FP64 input), 1 = forward z from r,
+// 2..5 = passes 1..4 (2 ... 4 = forward y, forward x + divide, backward z, backward y),
+// 6 = backward x storing u (first iteration), 7 = backward x accumulating into u
+constexpr int NVAR = 8;
+
+int bucket_of(int L) {
+  int b = 0;
+  for (int cap = 16; b < NBUCKET - 1 && L > cap; cap *= 2) ++b;
+  return b;
+}
+
+inline int pad8(int n) { return (n + 7) / 8 * 8; }
+
+__global__ void zero_u64_n(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+struct Group {
+  int var, tile_rows;
+  int off, count;  // range in the descriptor array
+  long tiles;
+};
+
+}  // namespace
+}  // namespace semfd
+
+using namespace semfd;
+
+struct sem_batch {
+  int count = 0;
+  std::vector<sem_plan*> plans;
+  std::vector<LpWork> lw;
+  hipStream_t stream = nullptr;
+  int cus = 1;
+  int tile_rows[NBUCKET] = {0, 0, 0, 0, 0, 0};
+  LpDesc* d_desc = nullptr;
+  ResDesc* d_rdesc = nullptr;
+  int* d_active = nullptr;
+  unsigned long long* d_norms = nullptr;
+  std::vector<LpDesc> h_desc;
+  std::vector<ResDesc> h_rdesc;
+  std::vector<Group> groups;
+  std::vector<Group> rgroups;  // residual groups: var = k
+};
+
+namespace semfd {
+namespace {
+
+// Geometry of pass s (0..5) of plan p: contracted axis, input/output pitches and
+// rotated shapes, as in lp_fd.
+struct PassGeo {
+  int axis, dir, A, B, K, ldx, ldy;
+};
+PassGeo pass_geo(const sem_plan* p, int s) {
+  const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
+  switch (s) {
+    case 0: return {2, 0, nx, ny, nz, pad8(nz), pad8(ny)};
+    case 1: return {1, 0, nz, nx, ny, pad8(ny), pad8(nx)};
+    case 2: return {0, 0, ny, nz, nx, pad8(nx), pad8(nz)};
+    case 3: return {2, 1, nx, ny, nz, pad8(nz), pad8(ny)};
+    case 4: return {1, 1, nz, nx, ny, pad8(ny), pad8(nx)};
+    default: return {0, 1, ny, nz, nx, pad8(nx), nz};
+  }
+}
+
+// Descriptor of variant v for solve i (f, u may be null while tuning).
+LpDesc make_desc(sem_batch* b, int i, int v, const double* f, double* u) {
+  sem_plan* p = b->plans[i];
+  const LpWork& w = b->lw[i];
+  const int s = v <= 1 ? 0 : (v >= 6 ? 5 : v - 1);
+  const PassGeo g = pass_geo(p, s);
+  LpDesc d;
+  d.P = (long)g.A * g.B;
+  d.K = g.K;
+  d.L = g.K;
+  d.A = g.A;
+  d.B = g.B;
+  d.ldx = g.ldx;
+  d.ldy = g.ldy;
+  d.f = p->lp_f32[g.axis][g.dir];
+  d.ldf = p->lp_ld[g.axis];
+  d.sid = i;
+  // operands: r -> t0 -> t1 -> t0 -> t1 -> t0 -> u
+  const void* in[6] = {w.r, w.t0, w.t1, w.t0, w.t1, w.t0};
+  void* out[6] = {w.t0, w.t1, w.t0, w.t1, w.t0, (void*)u};
+  d.x = in[s];
+  d.y = out[s];
+  if (v == 0) {
+    d.x = f;
+    d.ldx = p->dims[2];
+  }
+  if (s == 2) {
+    d.epi.l0 = p->d_lam[0];
+    d.epi.l1 = p->d_lam[1];
+    d.epi.l2 = p->d_lam[2];
+    d.epi.alpha = p->alpha;
+    d.epi.b1 = 1.0;
+    d.epi.b2 = 0.0;
+  }
+  if (s == 5) {
+    d.epi.first = v == 6 ? 1 : 0;
+    d.epi.norms = b->d_norms + 2 * i;
+  }
+  return d;
+}
+
+int tile_for(const sem_batch* b, int L) {
+  const int t = b->tile_rows[bucket_of(L)];
+  return t ? t : 128;
+}
+
+// Build all pass descriptors (grouped by variant and tile shape) and the residual
+// descriptors (grouped by k) for one solve call.
+sem_status build_descs(sem_batch* b, const double* const* f, double* const* u) {
+  b->h_desc.clear();
+  b->groups.clear();
+  for (int v = 0; v < NVAR; ++v)
+    for (int tr : TILE_CANDIDATES) {
+      Group g{v, tr, (int)b->h_desc.size(), 0, 0};
+      for (int i = 0; i < b->count; ++i) {
+        LpDesc d = make_desc(b, i, v, f ? f[i] : nullptr, u ? u[i] : nullptr);
+        if (tile_for(b, d.L) != tr) continue;
+        d.tiles_l = (d.L + tr - 1) / tr;
+        d.tile0 = g.tiles;
+        g.tiles += (long)d.tiles_l * ((d.P + 127) / 128);
+        b->h_desc.push_back(d);
+        ++g.count;
+      }
+      if (g.count) b->groups.push_back(g);
+    }
+  b->h_rdesc.clear();
+  b->rgroups.clear();
+  for (int k = 1; k <= 8; ++k) {
+    Group g{k, 0, (int)b->h_rdesc.size(), 0, 0};
+    for (int i = 0; i < b->count; ++i) {
+      sem_plan* p = b->plans[i];
+      if (p->k != k) continue;
+      ResidualArgs ra;
+      ra.v = u ? u[i] : nullptr;
+      ra.f = f ? f[i] : nullptr;
+      ra.r = b->lw[i].r;
+      ra.r_kind = 1;
+      ra.ldr = b->lw[i].ldr;
+      ra.cf = 1.0;
+      ra.cd = p->alpha;
+      ra.ch = 1.0;
+      const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
+      ResDesc rd;
+      if (!residual_desc(ra, hb, k, p->dims, &rd)) return set_error(SEM_EINVAL, "sem_batch: residual descriptor");
+      rd.sid = i;
+      rd.block0 = g.tiles;
+      g.tiles += (long)rd.gx * rd.gy * rd.gz;
+      b->h_rdesc.push_back(rd);
+      ++g.count;
+    }
+    if (g.count) b->rgroups.push_back(g);
+  }
+  hipError_t e;
+  if ((e = hipMemcpy(b->d_desc, b->h_desc.data(), b->h_desc.size() * sizeof(LpDesc), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(b->d_rdesc, b->h_rdesc.data(), b->h_rdesc.size() * sizeof(ResDesc), hipMemcpyHostToDevice)) !=
+          hipSuccess)
+    return hip_fail(e, "sem_batch: descriptor upload");
+  return SEM_OK;
+}
+
+hipError_t launch_group(sem_batch* b, const Group& g) {
+  const int v = g.var;
+  const int in_kind = v == 0 ? 0 : 1;
+  const int out_kind = v >= 6 ? 0 : 1;
+  const int epi = v >= 6 ? EPI_ACCUM : (v == 3 ? EPI_DIVIDE : EPI_STORE);
+  const int grid = b->cus * lp_batch_blocks_per_cu(g.tile_rows);
+  return launch_mode_f32_batch(in_kind, out_kind, epi, g.tile_rows, b->d_desc + g.off, g.count, g.tiles, b->d_active,
+                               grid, b->stream);
+}
+
+hipError_t run_variant(sem_batch* b, int v) {
+  for (const Group& g : b->groups)
+    if (g.var == v) {
+      hipError_t e = launch_group(b, g);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
+// Time the candidate tile shapes on the batch's own forward-y passes, per bucket.
+sem_status autotune(sem_batch* b) {
+  // descriptors: a forward pass along every axis of every solve, FP32 in and out
+  // inside the solve's own workspace (contents irrelevant for timing)
+  std::vector<int> ones(b->count, 1);
+  hipError_t e = hipMemcpy(b->d_active, ones.data(), ones.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "sem_batch: autotune");
+  hipEvent_t t0, t1;
+  if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess)
+    return hip_fail(e, "sem_batch: autotune events");
+  sem_status st = SEM_OK;
+  for (int bk = 0; bk < NBUCKET && st == SEM_OK; ++bk) {
+    std::vector<LpDesc> base;
+    for (int i = 0; i < b->count; ++i)
+      for (int s : {1, 2, 3}) {  // variants 2, 3, 4 = passes along y, x, z
+        LpDesc d = make_desc(b, i, s + 1, nullptr, nullptr);
+        if (bucket_of(d.L) != bk) continue;
+        d.epi = EpiLP();
+        base.push_back(d);
+      }
+    if (base.empty()) continue;
+    float best = INFINITY;
+    int best_tr = 128;
+    for (int tr : TILE_CANDIDATES) {
+      std::vector<LpDesc> ds = base;
+      long tiles = 0;
+      for (LpDesc& d : ds) {
+        d.tiles_l = (d.L + tr - 1) / tr;
+        d.tile0 = tiles;
+        tiles += (long)d.tiles_l * ((d.P + 127) / 128);
+      }
+      if ((e = hipMemcpy(b->d_desc, ds.data(), ds.size() * sizeof(LpDesc), hipMemcpyHostToDevice)) != hipSuccess) {
+        st = hip_fail(e, "sem_batch: autotune upload");
+        break;
+      }
+      const int grid = b->cus * lp_batch_blocks_per_cu(tr);
+      float ms = 0.f;
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        if (rep == 1) e = hipEventRecord(t0, b->stream);
+        if (e == hipSuccess)
+          e = launch_mode_f32_batch(1, 1, EPI_STORE, tr, b->d_desc, (int)ds.size(), tiles, b->d_active, grid,
+                                    b->stream);
+      }
+      if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "sem_batch: autotune run");
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_tr = tr;
+      }
+    }
+    b->tile_rows[bk] = best_tr;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  return st;
+}
+
+}  // namespace
+}  // namespace semfd
+
+extern "C" {
+
+void sem_batch_destroy(sem_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  (void)hipFree(b->d_desc);
+  (void)hipFree(b->d_rdesc);
+  (void)hipFree(b->d_active);
+  (void)hipFree(b->d_norms);
+  delete b;
+}
+
+sem_status sem_batch_create(int count, sem_plan* const* plans, sem_batch** out) {
+  if (!out) return set_error(SEM_EINVAL, "sem_batch_create: null output");
+  *out = nullptr;
+  if (count < 1 || !plans) return set_error(SEM_EINVAL, "sem_batch_create: need count >= 1 plans");
+  int dev = -1;
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return set_error(SEM_EINVAL, "sem_batch_create: null plan");
+    if (plans[i]->k > 8) return set_error(SEM_EINVAL, "sem_batch_create: batched residual supports k <= 8");
+    if (i == 0) dev = plans[i]->device;
+    if (plans[i]->device != dev) return set_error(SEM_EINVAL, "sem_batch_create: plans on different devices");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return set_error(SEM_EINVAL, "sem_batch_create: a plan appears twice");
+  }
+  sem_batch* b = new (std::nothrow) sem_batch;
+  if (!b) return set_error(SEM_ENOMEM, "sem_batch_create: host allocation");
+  b->count = count;
+  b->plans.assign(plans, plans + count);
+  b->lw.resize(count);
+  for (int i = 0; i < count; ++i) {
+    sem_status st = lp_prepare(plans[i], SEM_F32, &b->lw[i]);
+    if (st != SEM_OK) {
+      sem_batch_destroy(b);
+      return st;
+    }
+  }
+  hipError_t e;
+  int cus = 0;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
+    sem_batch_destroy(b);
+    return hip_fail(e, "sem_batch_create: device query");
+  }
+  b->cus = cus > 0 ? cus : 1;
+  if ((e = hipMalloc(&b->d_desc, sizeof(LpDesc) * (size_t)std::max(NVAR * count, 3 * count))) != hipSuccess ||
+      (e = hipMalloc(&b->d_rdesc, sizeof(ResDesc) * (size_t)count)) != hipSuccess ||
+      (e = hipMalloc(&b->d_active, sizeof(int) * (size_t)count)) != hipSuccess ||
+      (e = hipMalloc(&b->d_norms, 2 * sizeof(unsigned long long) * (size_t)count)) != hipSuccess) {
+    sem_batch_destroy(b);
+    return hip_fail(e, "sem_batch_create: device allocation");
+  }
+  sem_status st = autotune(b);
+  if (st != SEM_OK) {
+    sem_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return SEM_OK;
+}
+
+sem_status sem_batch_set_stream(sem_batch* b, void* s) {
+  if (!b) return set_error(SEM_EINVAL, "sem_batch_set_stream: null handle");
+  b->stream = (hipStream_t)s;
+  return SEM_OK;
+}
+
+sem_status sem_batch_tile_rows(const sem_batch* b, int rows[6]) {
+  if (!b || !rows) return set_error(SEM_EINVAL, "sem_batch_tile_rows: null argument");
+  for (int k = 0; k < NBUCKET; ++k) rows[k] = b->tile_rows[k];
+  return SEM_OK;
+}
+
+sem_status sem_batch_solve(sem_batch* b, sem_prec prec, double tol, int max_iter, const double* const* f,
+                           double* const* u, int* iters) {
+  if (!b || !f || !u || max_iter < 1 || !(tol >= 0.0) || !std::isfinite(tol))
+    return set_error(SEM_EINVAL, "sem_batch_solve: invalid argument");
+  for (int i = 0; i < b->count; ++i) {
+    if (!f[i] || !u[i]) return set_error(SEM_EINVAL, "sem_batch_solve: null array");
+    if (f[i] == u[i]) return set_error(SEM_EINVAL, "sem_batch_solve: u must not alias f");
+    if (iters) iters[i] = 0;
+  }
+  if (prec == SEM_F64) {  // FP64 solves one after another on the batch stream
+    for (int i = 0; i < b->count; ++i) {
+      sem_plan* p = b->plans[i];
+      hipStream_t keep = p->stream;
+      p->stream = b->stream;
+      sem_status st = sem_solve(p, f[i], u[i]);
+      p->stream = keep;
+      if (st != SEM_OK) return st;
+      if (iters) iters[i] = 1;
+    }
+    return SEM_OK;
+  }
+  if (prec != SEM_F32) return set_error(SEM_EINVAL, "sem_batch_solve: batched solves run in SEM_F32 or SEM_F64");
+  sem_status st = build_descs(b, f, u);
+  if (st != SEM_OK) return st;
+  const int n = b->count;
+  std::vector<int> active(n, 1), done_it(n, 0);
+  std::vector<double> prev(n, INFINITY), prev2(n, INFINITY);
+  std::vector<unsigned long long> hn(2 * n);
+  sem_status result = SEM_OK;
+  hipError_t e;
+  for (int it = 0; it < max_iter; ++it) {
+    if ((e = hipMemcpyAsync(b->d_active, active.data(), n * sizeof(int), hipMemcpyHostToDevice, b->stream)) !=
+        hipSuccess)
+      return hip_fail(e, "sem_batch_solve: active flags");
+    if (it > 0)
+      for (const Group& g : b->rgroups)
+        if ((e = launch_residual_batch(g.var, 1, b->d_rdesc + g.off, g.count, g.tiles, b->d_active, b->stream)) !=
+            hipSuccess)
+          return hip_fail(e, "sem_batch_solve: residual");
+    zero_u64_n<<<(2 * n + 255) / 256, 256, 0, b->stream>>>(b->d_norms, 2 * n);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sem_batch_solve: norm reset");
+    const int seq[6] = {it == 0 ? 0 : 1, 2, 3, 4, 5, it == 0 ? 6 : 7};
+    for (int v : seq)
+      if ((e = run_variant(b, v)) != hipSuccess) return hip_fail(e, "sem_batch_solve: mode products");
+    if ((e = hipMemcpyAsync(hn.data(), b->d_norms, hn.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            b->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(b->stream)) != hipSuccess)
+      return hip_fail(e, "sem_batch_solve: norm readback");
+    int left = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!active[i]) continue;
+      double dmax, umax;
+      std::memcpy(&dmax, &hn[2 * i], 8);
+      std::memcpy(&umax, &hn[2 * i + 1], 8);
+      done_it[i] = it + 1;
+      if (!std::isfinite(dmax) || !std::isfinite(umax)) {
+        active[i] = 0;
+        result = SEM_ENONFINITE;
+        continue;
+      }
+      const double rel = umax > 0 ? dmax / umax : (dmax > 0 ? INFINITY : 0.0);
+      if (tol > 0 && rel <= tol) {
+        active[i] = 0;
+        continue;
+      }
+      if (it >= 2 && rel > prev[i] && prev[i] > prev2[i]) {  // diverging at this precision
+        active[i] = 0;
+        if (result == SEM_OK) result = SEM_ENOCONV;
+        continue;
+      }
+      prev2[i] = prev[i];
+      prev[i] = rel;
+      ++left;
+    }
+    if (!left) break;
+  }
+  if (iters)
+    for (int i = 0; i < n; ++i) iters[i] = done_it[i];
+  if (tol > 0)
+    for (int i = 0; i < n; ++i)
+      if (active[i] && result == SEM_OK) result = SEM_ENOCONV;
+  if (result == SEM_ENONFINITE) return set_error(result, "sem_batch_solve: a solve produced a non-finite update");
+  if (result == SEM_ENOCONV) return set_error(result, "sem_batch_solve: a solve did not meet the tolerance");
+  return SEM_OK;
+}
+
+}  // extern "C"

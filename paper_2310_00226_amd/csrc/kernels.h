@@ -75,7 +75,30 @@ struct LpPass {
   long xplane = 0, yplane = 0, fplane = 0;
   EpiLP epi;
 };
+// FP32 passes (mode_lp.hip): mode LP_F32, in_kind 0 or 1, out_kind 1 or 0 (accumulate).
 hipError_t launch_mode_lp(const LpPass& ps, hipStream_t stream);
+
+// One FP32 pass of one solve inside a batched (persistent) launch: the fields of
+// LpPass plus the tile bookkeeping.  Descriptor i owns tiles [tile0, tile0 +
+// tiles_l * ceil(P / 128)) of the launch's global tile numbering (ascending
+// tile0); sid indexes the launch's per-solve active flags.
+struct LpDesc {
+  const void* x = nullptr;
+  void* y = nullptr;
+  const void* f = nullptr;  // FP32 factor [l][k], pitch ldf
+  EpiLP epi;
+  long P = 0;
+  long tile0 = 0;
+  int ldx = 0, K = 0, ldy = 0, A = 0, B = 0, L = 0, ldf = 0;
+  int tiles_l = 0;
+  int sid = 0;
+};
+// Persistent FP32 launch over nd descriptors (device array) with tile_rows in
+// {128, 64, 32} (block tile tile_rows x 128), grid blocks striding over
+// total_tiles; active: device array of per-solve flags.
+hipError_t launch_mode_f32_batch(int in_kind, int out_kind, int epi, int tile_rows, const LpDesc* descs, int nd,
+                                 long total_tiles, const int* active, int grid, hipStream_t stream);
+int lp_batch_blocks_per_cu(int tile_rows);
 
 // ---- BF16 / split-BF16 passes with direct global -> LDS loads (mode_dma.hip) ----
 // Requirements: in_kind 2, ldx and ldf multiples of 8, ldx >= K, ldf >= L and K
@@ -107,5 +130,28 @@ struct ResidualArgs {
 };
 hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], int k, const int dims[3],
                            hipStream_t stream);
+
+// Residuals of many solves with the same k (1..8) in one launch.  Descriptor i
+// (device array, ascending block0) owns blocks [block0, block0 + gx*gy*gz);
+// active: device array of per-solve flags indexed by sid.
+struct ResDesc {
+  const double* v = nullptr;
+  const double* f = nullptr;
+  const double* d = nullptr;
+  void* r = nullptr;
+  const double* hx = nullptr;
+  const double* hy = nullptr;
+  const double* hz = nullptr;
+  long rplane = 0;
+  long block0 = 0;
+  int ldr = 0, nx = 0, ny = 0, nz = 0, xchunk = 0, gx = 0, gy = 0, gz = 0;
+  int sid = 0;
+  double cf = 1.0, cd = 0.0, ch = 1.0;
+};
+// Fill the geometry and operands of one descriptor (block0 and sid are the
+// caller's); false if k or the arguments are outside what the batch kernel takes.
+bool residual_desc(const ResidualArgs& ra, const double* const hb[3], int k, const int dims[3], ResDesc* d);
+hipError_t launch_residual_batch(int k, int r_kind, const ResDesc* descs, int nd, long total_blocks,
+                                 const int* active, hipStream_t stream);
 
 }  // namespace semfd

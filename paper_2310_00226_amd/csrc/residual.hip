@@ -92,20 +92,17 @@ __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restr
 constexpr int RY = 4, RZ = 64;
 
 template <int KH, class TR>
-__global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* __restrict__ v,
-                                                                  const double* __restrict__ f,
-                                                                  const double* __restrict__ dg, TR* __restrict__ r,
-                                                                  int ldr, long rplane,
-                                                                  const double* __restrict__ hx,
-                                                                  const double* __restrict__ hy,
-                                                                  const double* __restrict__ hz, int nx, int ny,
-                                                                  int nz, int xchunk, Coef c) {
+__device__ __forceinline__ void march_body(const double* __restrict__ v, const double* __restrict__ f,
+                                           const double* __restrict__ dg, TR* __restrict__ r, int ldr, long rplane,
+                                           const double* __restrict__ hx, const double* __restrict__ hy,
+                                           const double* __restrict__ hz, int nx, int ny, int nz, int xchunk,
+                                           const Coef& c, int bx, int by, int bz) {
   constexpr int BW = 2 * KH + 1;
   // one wave = one y row (RZ = 64 lanes along z): j and everything derived from it
   // is wave-uniform and lives in scalar registers
-  const int l = blockIdx.x * RZ + (threadIdx.x % RZ);
-  const int j = __builtin_amdgcn_readfirstlane(blockIdx.y * RY + (threadIdx.x / RZ));
-  const int i0 = blockIdx.z * xchunk;
+  const int l = bx * RZ + (threadIdx.x % RZ);
+  const int j = __builtin_amdgcn_readfirstlane(by * RY + (threadIdx.x / RZ));
+  const int i0 = bz * xchunk;
   const int i1 = min(nx, i0 + xchunk);
   if (l >= nz || j >= ny) return;  // no barriers below: early exit is safe
   const long plane = (long)ny * nz;
@@ -180,17 +177,71 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* _
 }
 
 template <int KH, class TR>
-void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], const int dims[3], Coef c,
-                  hipStream_t stream) {
-  // split x into chunks so that the grid fills the chip even for thin (y, z) planes
+__global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* __restrict__ v,
+                                                                  const double* __restrict__ f,
+                                                                  const double* __restrict__ dg, TR* __restrict__ r,
+                                                                  int ldr, long rplane,
+                                                                  const double* __restrict__ hx,
+                                                                  const double* __restrict__ hy,
+                                                                  const double* __restrict__ hz, int nx, int ny,
+                                                                  int nz, int xchunk, Coef c) {
+  march_body<KH, TR>(v, f, dg, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, c, blockIdx.x, blockIdx.y,
+                     blockIdx.z);
+}
+
+// Residuals of many solves (same k) in one launch: descriptor i owns blocks
+// [block0_i, block0_i + gx * gy * gz) of the grid; inactive solves are skipped.
+template <int KH, class TR>
+__global__ __launch_bounds__(RY * RZ) void residual_march_batch(const ResDesc* __restrict__ descs, int nd,
+                                                                 const int* __restrict__ active) {
+  const long i = blockIdx.x;
+  int lo = 0, hi = nd;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (descs[mid].block0 <= i) lo = mid;
+    else hi = mid;
+  }
+  const ResDesc& d = descs[lo];
+  if (!active[d.sid]) return;
+  const long rb = i - d.block0;
+  const int bx = (int)(rb % d.gx);
+  const int by = (int)((rb / d.gx) % d.gy);
+  const int bz = (int)(rb / ((long)d.gx * d.gy));
+  march_body<KH, TR>(d.v, d.f, d.d, (TR*)d.r, d.ldr, d.rplane, d.hx, d.hy, d.hz, d.nx, d.ny, d.nz, d.xchunk,
+                     Coef{d.cf, d.cd, d.ch}, bx, by, bz);
+}
+
+// x is split into chunks so that the grid fills the chip even for thin (y, z) planes
+void march_grid(const int dims[3], int* gx, int* gy, int* gz, int* xchunk) {
   const long cols = (long)((dims[2] + RZ - 1) / RZ) * ((dims[1] + RY - 1) / RY);
   int nchunks = (int)std::min<long>(dims[0], std::max<long>(1, (16384 + cols - 1) / cols));
-  const int xchunk = (dims[0] + nchunks - 1) / nchunks;
-  nchunks = (dims[0] + xchunk - 1) / xchunk;
-  dim3 grid((unsigned)((dims[2] + RZ - 1) / RZ), (unsigned)((dims[1] + RY - 1) / RY), (unsigned)nchunks);
-  residual_march_kernel<KH, TR><<<grid, dim3(RY * RZ), 0, stream>>>(ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0],
-                                                                     hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
-                                                                     c);
+  *xchunk = (dims[0] + nchunks - 1) / nchunks;
+  *gx = (dims[2] + RZ - 1) / RZ;
+  *gy = (dims[1] + RY - 1) / RY;
+  *gz = (dims[0] + *xchunk - 1) / *xchunk;
+}
+
+template <int KH, class TR>
+void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], const int dims[3], Coef c,
+                  hipStream_t stream) {
+  int gx, gy, gz, xchunk;
+  march_grid(dims, &gx, &gy, &gz, &xchunk);
+  residual_march_kernel<KH, TR><<<dim3(gx, gy, gz), dim3(RY * RZ), 0, stream>>>(
+      ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
+}
+
+template <int KH>
+hipError_t batch_typed(int r_kind, const ResDesc* descs, int nd, long total_blocks, const int* active,
+                       hipStream_t s) {
+  const dim3 grid((unsigned)total_blocks), block(RY * RZ);
+  switch (r_kind) {
+    case 0: residual_march_batch<KH, double><<<grid, block, 0, s>>>(descs, nd, active); break;
+    case 1: residual_march_batch<KH, float><<<grid, block, 0, s>>>(descs, nd, active); break;
+    case 2:
+    case 3: residual_march_batch<KH, unsigned short><<<grid, block, 0, s>>>(descs, nd, active); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <class TR>
@@ -238,6 +289,46 @@ hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], in
       return launch_typed<unsigned short>(ra, (unsigned short*)ra.r, hb, k, dims, stream);
     default:
       return hipErrorInvalidValue;
+  }
+}
+
+bool residual_desc(const ResidualArgs& ra, const double* const hb[3], int k, const int dims[3], ResDesc* d) {
+  if (k < 1 || k > 8 || !ra.v || !ra.r || ra.ldr < dims[2] || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0)
+    return false;
+  if (ra.r_kind == 3 && ra.rplane <= 0) return false;
+  d->v = ra.v;
+  d->f = ra.f;
+  d->d = ra.d;
+  d->r = ra.r;
+  d->hx = hb[0];
+  d->hy = hb[1];
+  d->hz = hb[2];
+  d->rplane = ra.r_kind == 3 ? ra.rplane : 0;
+  d->ldr = ra.ldr;
+  d->nx = dims[0];
+  d->ny = dims[1];
+  d->nz = dims[2];
+  march_grid(dims, &d->gx, &d->gy, &d->gz, &d->xchunk);
+  d->cf = ra.cf;
+  d->cd = ra.cd;
+  d->ch = ra.ch;
+  return true;
+}
+
+hipError_t launch_residual_batch(int k, int r_kind, const ResDesc* descs, int nd, long total_blocks,
+                                 const int* active, hipStream_t stream) {
+  if (nd <= 0 || total_blocks <= 0) return hipSuccess;
+  if (total_blocks > 0x7fffffffL) return hipErrorInvalidValue;
+  switch (k) {
+    case 1: return batch_typed<1>(r_kind, descs, nd, total_blocks, active, stream);
+    case 2: return batch_typed<2>(r_kind, descs, nd, total_blocks, active, stream);
+    case 3: return batch_typed<3>(r_kind, descs, nd, total_blocks, active, stream);
+    case 4: return batch_typed<4>(r_kind, descs, nd, total_blocks, active, stream);
+    case 5: return batch_typed<5>(r_kind, descs, nd, total_blocks, active, stream);
+    case 6: return batch_typed<6>(r_kind, descs, nd, total_blocks, active, stream);
+    case 7: return batch_typed<7>(r_kind, descs, nd, total_blocks, active, stream);
+    case 8: return batch_typed<8>(r_kind, descs, nd, total_blocks, active, stream);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -1,0 +1,127 @@
+"""GPU parity of batched solves (persistent FP32 launches over many problems of
+different sizes, FP64 refinement) against the FP64 oracle, per problem.
+
+Bar: ||u_i - u_oracle,i||_inf <= 1e-10 ||u_oracle,i||_inf + 10 x the oracle's own
+rounding floor, for every problem of the batch.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import batch_draws, batch_rhs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+BOX = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0)
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2310_00226_amd as P
+    return P
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _check(prob, f, u):
+    ref = O.fd_solve(prob, f)
+    floor = np.max(np.abs(ref - O.fd_solve(prob, f, order=(0, 1, 2))))
+    err = np.max(np.abs(u - ref))
+    return err <= TOL * np.max(np.abs(ref)) + 10 * floor, err / max(np.max(np.abs(ref)), 1e-300)
+
+
+def _run(torch, P, specs, seed, prec="f32", tol=1e-12, repeat=1):
+    plans = [P.Plan(s["k"], s["ne"], s.get("box", BOX), s["alpha"], s.get("bc", "dirichlet")) for s in specs]
+    batch = P.Batch(plans)
+    rows = batch.tile_rows()
+    assert all(r in (0, 32, 64, 128) for r in rows), rows
+    worst = 0.0
+    for rep in range(repeat):
+        fs = [batch_rhs(p.shape, seed + rep, i) for i, p in enumerate(plans)]
+        fd = [_dev(torch, f) for f in fs]
+        ud = [torch.empty_like(f) for f in fd]
+        its, st = batch.solve(fd, ud, prec=prec, tol=tol, max_iter=40)
+        assert st == 0
+        for i, (s, p) in enumerate(zip(specs, plans)):
+            prob = O.Problem(s["k"], s["ne"], s.get("box", BOX), s["alpha"], s.get("bc", "dirichlet"))
+            ok, rel = _check(prob, fs[i], ud[i].cpu().numpy())
+            worst = max(worst, rel)
+            assert ok, (rep, i, s, rel, its[i])
+    return rows, its, worst
+
+
+def test_batch_mixed_small(torch, P):
+    specs = [
+        {"k": 2, "ne": (1, 1, 1), "alpha": 0.0},
+        {"k": 8, "ne": (2, 1, 3), "alpha": 3.0},
+        {"k": 3, "ne": (5, 7, 2), "alpha": 0.5, "bc": "neumann", "box": (0, 2, -1, 1, 0, 3)},
+        {"k": 5, "ne": (9, 4, 6), "alpha": 9.0},
+        {"k": 4, "ne": (33, 3, 5), "alpha": 1.0},
+        {"k": 6, "ne": (3, 25, 2), "alpha": 0.0},
+        {"k": 7, "ne": (4, 4, 40), "alpha": 2.5, "bc": "neumann"},
+        {"k": 2, "ne": (64, 2, 1), "alpha": 1.0},
+    ]
+    _log("[batch] 8 mixed problems, two right-hand sides")
+    rows, its, worst = _run(torch, P, specs, 5, repeat=2)
+    _log(f"[batch]   tile rows {rows}, iterations {its}, worst rel err {worst:.2e}")
+
+
+def test_batch_matches_single_refined_solves(torch, P):
+    specs = [{"k": 4, "ne": (6, 5, 7), "alpha": 1.0}, {"k": 3, "ne": (11, 9, 10), "alpha": 0.2}]
+    plans = [P.Plan(s["k"], s["ne"], BOX, s["alpha"]) for s in specs]
+    batch = P.Batch(plans)
+    fs = [_dev(torch, batch_rhs(p.shape, 3, i)) for i, p in enumerate(plans)]
+    ub = [torch.empty_like(f) for f in fs]
+    its, st = batch.solve(fs, ub, prec="f32", tol=1e-12)
+    assert st == 0
+    for i, p in enumerate(plans):
+        us, it1, _, st1 = p.solve_refined(fs[i], prec="f32", tol=1e-12)
+        assert st1 == 0 and abs(it1 - its[i]) <= 1
+        d = (ub[i] - us).abs().max().item() / us.abs().max().item()
+        assert d <= 2e-12, (i, d)
+
+
+def test_batch_f64_path(torch, P):
+    specs = [{"k": 4, "ne": (3, 4, 5), "alpha": 1.0}, {"k": 2, "ne": (7, 2, 3), "alpha": 0.0}]
+    _run(torch, P, specs, 9, prec="f64")
+
+
+def test_batch_c4_recipe_reduced_elements(torch, P):
+    """The batched workload's recipe (256 problems, k in {2..8}, alpha in [0, 10],
+    N(0,1) right-hand sides) with 8..16 elements per axis, every problem checked."""
+    specs = batch_draws(256, 2311, ne_range=(8, 16))
+    _log("[batch] 256 problems, ne in 8..16")
+    rows, its, worst = _run(torch, P, specs, 2311)
+    _log(f"[batch]   tile rows {rows}, max iterations {max(its)}, worst rel err {worst:.2e}")
+
+
+def test_batch_rejects_invalid(torch, P):
+    plan = P.Plan(4, (2, 2, 2), BOX, 1.0)
+    with pytest.raises(P.SemError):
+        P.Batch([plan, plan])  # the same plan twice
+    big = P.Plan(9, (1, 1, 1), BOX, 1.0)
+    with pytest.raises(P.SemError):
+        P.Batch([big])  # k > 8
+    b = P.Batch([plan])
+    f = _dev(torch, np.ones(plan.shape))
+    with pytest.raises(P.SemError):
+        b.solve([f], [f])  # u aliases f
+    u = torch.empty_like(f)
+    its, st = b.solve([f], [u], prec="bf16", raise_on_error=False)
+    assert st == 1  # SEM_EINVAL: batched solves run in FP32 or FP64

@@ -101,14 +101,15 @@ def helmholtz_rhs(x, y, z, alpha: float, noise_scale: float = 1e-3, seed: int = 
     return f
 
 
-def batch_draws(count: int = 256, seed: int = BATCH_SEED):
-    """Per-solve parameters of the batched workload: k in {2..8}, Ne per axis in
-    {8..64}, alpha ~ U[0, 10]; Dirichlet on [-1, 1]^3."""
+def batch_draws(count: int = 256, seed: int = BATCH_SEED, k_range=(2, 8), ne_range=(8, 64)):
+    """Per-solve parameters of the batched workload: k uniform in {2..8}, Ne per
+    axis uniform in {8..64} (both inclusive ranges), alpha ~ U[0, 10]; Dirichlet
+    on [-1, 1]^3."""
     g = np.random.Generator(np.random.PCG64(seed))
     out = []
     for _ in range(count):
-        k = int(g.integers(2, 9))
-        ne = tuple(int(v) for v in g.integers(8, 65, size=3))
+        k = int(g.integers(k_range[0], k_range[1] + 1))
+        ne = tuple(int(v) for v in g.integers(ne_range[0], ne_range[1] + 1, size=3))
         alpha = float(g.uniform(0.0, 10.0))
         out.append({"k": k, "ne": ne, "alpha": alpha})
     return out
