@@ -1,20 +1,24 @@
 // BF16 rotating mode products with direct global -> LDS loads.
 //
-// Same contraction as mode_lp.hip (Y[l][a][b] = sum_k F[l][k] X[a][b][k], the
-// axes rotating from pass to pass) for the two BF16 modes, restructured for the
-// memory system of CDNA4:
+// Same contraction as the FP32 passes (Y[l][a][b] = sum_k F[l][k] X[a][b][k],
+// the axes rotating from pass to pass) for the two BF16 modes, organised for
+// CDNA4:
 //  * operand tiles move from HBM / L2 straight into LDS with
-//    global_load_lds_dwordx4 (no VGPR staging), through a ring of STAGES
-//    buffers; the loads of chunk c + STAGES - 1 are in flight while chunk c is
-//    multiplied, and a wave waits (vmcnt) only for the chunk it is about to read;
-//  * the ring stages are addressed with compile-time indices (the chunk loop is
-//    unrolled by STAGES); the kernel orders DMA and LDS reads itself (vmcnt wait
-//    + barrier per chunk), so the loads of later stages stay in flight;
+//    global_load_lds_dwordx4 (no VGPR staging), through a ring of STAGES buffers
+//    addressed with compile-time indices (the chunk loop is unrolled by STAGES);
+//    the kernel orders DMA and LDS reads itself (vmcnt waits + barriers);
 //  * LDS rows are 64 bytes (32 BF16 = one 16x16x32 MFMA step) made of four
 //    16-byte chunks placed at slot chunk ^ g(row), g(row) = ((row>>1)^(row>>2))&3,
 //    which makes the fragment reads (16 rows x one chunk per 16 lanes)
 //    bank-conflict-free for 32 and 64 four-byte banks;
-//  * block tile 256 (l) x 256 (p), eight waves of 128 x 64.
+//  * ping-pong wave groups: the 8 waves of a block form two groups of 4, one
+//    wave of each per SIMD.  While one group issues MFMAs the other issues the
+//    DMA and reads its next fragments from LDS; block barriers switch the roles
+//    twice per chunk, so every SIMD's MFMA unit is fed by one wave while its
+//    partner waits on memory;
+//  * block tile BML (l) x 256 (p): BF16 256 x 256 with waves of 128 x 64;
+//    split BF16 (three MFMAs per step, twice the operands) 128 x 256 with waves
+//    of 64 x 64 to stay within the register file.
 // Split BF16 (LP_BF16X3) keeps every operand as two BF16 planes (hi, lo) in
 // HBM, so its intermediates load without conversion too.
 //
@@ -23,8 +27,8 @@
 //    elements between K and ldx hold finite values (they meet zero factor
 //    columns), and the second plane (split mode) starts xplane elements after
 //    the first;
-//  * the factor is [l][k] with pitch ldf (multiple of 128, >= 256-rounded L and
-//    K), zero outside L x K, second plane fplane elements after the first.
+//  * the factor is [l][k] with pitch ldf (multiple of 8, >= 256-rounded L and
+//    32-rounded K), zero outside L x K, second plane fplane elements after the first.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -40,13 +44,12 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-constexpr int BM = 256, BN = 256, WL = 2, WP = 4;
-constexpr int NTHREADS = 64 * WL * WP;  // 512
-constexpr int TL = BM / WL, TP = BN / WP;  // 128 x 64 per wave
-constexpr int FL = TL / 16, FP = TP / 16;  // 8 x 4 MFMA tiles
-constexpr int BK = 32;                      // BF16 elements per chunk (64-byte LDS rows)
-constexpr int ROWB = BK * 2;                // bytes per LDS row
-constexpr int TILEB = BM * ROWB;            // bytes per operand tile (16 KB)
+constexpr int NTHREADS = 512;  // 8 waves
+constexpr int BN = 256;        // tensor rows per block tile
+constexpr int TP = 64;         // tensor rows per wave
+constexpr int FP = TP / 16;    // 4 MFMA tiles along p
+constexpr int BK = 32;         // BF16 elements per chunk (64-byte LDS rows)
+constexpr int ROWB = BK * 2;   // bytes per LDS row
 
 __device__ __forceinline__ int swz(int row) { return ((row >> 1) ^ (row >> 2)) & 3; }
 
@@ -62,14 +65,21 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (0 << 8) | ((N >> 4) << 14));
 }
 
-template <int MODE, class TOut, int EPI>
+template <int MODE>
 struct KCfg {
-  static constexpr int NS = MODE == LP_BF16X3 ? 2 : 1;
-  static constexpr int STAGES = NS == 2 ? 2 : 4;
-  static constexpr int STAGEB = NS * 2 * TILEB;  // factor + tensor tiles, all planes
-  // DMA instructions per chunk per wave: each 1 KB instruction fills 16 rows
-  static constexpr int DMA_PER_TILE = BM / 16 / (WL * WP);  // 2
-  static constexpr int D = NS * 2 * DMA_PER_TILE;
+  static constexpr int NS = MODE == LP_BF16X3 ? 2 : 1;  // operand planes
+  static constexpr int BML = NS == 2 ? 128 : 256;      // factor rows per block tile
+  static constexpr int TL = BML / 2;                   // factor rows per wave (two groups)
+  static constexpr int FL = TL / 16;
+  static constexpr int TILEF = BML * ROWB;             // bytes of one factor tile plane
+  static constexpr int TILEX = BN * ROWB;              // bytes of one tensor tile plane
+  static constexpr int PLANEB = TILEF + TILEX;
+  static constexpr int STAGEB = NS * PLANEB;
+  static constexpr int STAGES = NS == 2 ? 3 : 4;       // 144 KB / 128 KB of LDS
+  // DMA instructions per chunk per wave of group 0 (16 rows of 64 bytes each)
+  static constexpr int FQ = BML / 16 / 4, XQ = BN / 16 / 4;
+  static constexpr int D = NS * (FQ + XQ);
+  static_assert((STAGES - 2) * D < 64, "vmcnt range");
 };
 
 template <int MODE, class TOut, int EPI>
@@ -78,58 +88,64 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
                                                          int A, int B, int L, const unsigned short* __restrict__ f,
                                                          int ldf, long fplane, long tiles_l, long ntiles,
                                                          long nblocks_padded, EpiLP epi) {
-  typedef KCfg<MODE, TOut, EPI> C;
-  constexpr int NS = C::NS, S = C::STAGES;
+  typedef KCfg<MODE> C;
+  constexpr int NS = C::NS, S = C::STAGES, FL = C::FL;
   __shared__ __attribute__((aligned(1024))) unsigned char ring[S][C::STAGEB];
-  unsigned char* const st0 = ring[0];
-  unsigned char* const st1 = ring[1];
-  unsigned char* const st2 = ring[S > 2 ? 2 : 0];
-  unsigned char* const st3 = ring[S > 3 ? 3 : 0];
 
   const long t = xcd_tile(nblocks_padded);
   if (t >= ntiles) return;  // whole block leaves together, before any barrier
   const long lt = t % tiles_l;
   const long pt = t / tiles_l;
-  const int l0 = (int)(lt * BM);
+  const int l0 = (int)(lt * C::BML);
   const long p0 = pt * BN;
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = (wave / WP) * TL;
-  const int wn = (wave % WP) * TP;
+  // Waves w and w + 4 share SIMD w % 4.  Group 0 (waves 0-3) owns factor rows
+  // 0 .. TL-1 of the tile, group 1 (waves 4-7) rows TL .. 2 TL-1; within a group
+  // wave w % 4 owns tensor rows 64 (w % 4) .. + 63.
+  const bool g0 = wave < 4;
+  const int gw = wave & 3;
+  const int wm = g0 ? 0 : C::TL;
+  const int wn = gw * TP;
   const int nchunk = (K + BK - 1) / BK;
 
-  // ---- DMA source addresses --------------------------------------------------
-  // Instruction q (0, 1) of this wave fills tile rows 16*(2*wave + q) .. +15;
-  // lane i writes LDS slot i % 4 of row 16*(2*wave + q) + i / 4 and therefore
-  // fetches chunk (i % 4) ^ g(row) of that row.
-  const unsigned short* fsrc[2];
-  const unsigned short* xsrc[2];
-  int fchunk[2];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int row = 16 * (2 * wave + q) + lane / 4;
-    fchunk[q] = ((lane & 3) ^ swz(row)) * 8;  // element offset of the chunk
-    fsrc[q] = f + (size_t)(l0 + row) * ldf;
-    const long pr = p0 + row < P ? p0 + row : P - 1;  // rows past P: any valid row
-    xsrc[q] = x + (size_t)pr * ldx;
-  }
+  // ---- DMA (group 0 only) ----------------------------------------------------
+  // One instruction fills 16 LDS rows: lane i writes slot i % 4 of row
+  // row0 + i / 4 and therefore fetches chunk (i % 4) ^ g(row) of that row.  Wave
+  // gw fills factor rows [FQ*16*gw, +FQ*16) and tensor rows [XQ*16*gw, +XQ*16).
+  // Addresses are a wave-uniform base plus a 32-bit per-lane offset.
   auto issue = [&](unsigned char* stage, int c) {
     const int k0 = c * BK;
 #pragma unroll
-    for (int pl = 0; pl < NS; ++pl)
+    for (int q = 0; q < C::FQ; ++q) {  // factor: padded to whole tiles, always in bounds
+      const int rowq = 16 * (C::FQ * gw + q);
+      const int row = rowq + lane / 4;
+      const int kc = ((lane & 3) ^ swz(row)) * 8;
+      const unsigned short* fb = f + (size_t)(l0 + rowq) * ldf + k0;
+      const unsigned foff = (unsigned)((lane / 4) * ldf + kc);
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int ldsrow = 16 * (2 * wave + q);
-        unsigned char* fdst = stage + pl * 2 * TILEB + ldsrow * ROWB;
-        unsigned char* xdst = stage + pl * 2 * TILEB + TILEB + ldsrow * ROWB;
-        // factor: padded, always in bounds; tensor: chunks past the row pitch
-        // are redirected to the row start (finite data times zero factor columns)
-        const int kf = k0 + fchunk[q];
-        const int kx = kf < ldx ? kf : 0;
-        __builtin_amdgcn_global_load_lds((const void*)(fsrc[q] + pl * fplane + kf), (lds_void*)fdst, 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((const void*)(xsrc[q] + pl * xplane + kx), (lds_void*)xdst, 16, 0, 0);
-      }
+      for (int pl = 0; pl < NS; ++pl)
+        __builtin_amdgcn_global_load_lds((const void*)(fb + pl * fplane + foff),
+                                         (lds_void*)(stage + pl * C::PLANEB + rowq * ROWB), 16, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < C::XQ; ++q) {
+      // tensor: rows past P read row P - 1; chunks past the row pitch read the
+      // row start (finite data times zero factor columns)
+      const int rowq = 16 * (C::XQ * gw + q);
+      const int row = rowq + lane / 4;
+      const int kc = ((lane & 3) ^ swz(row)) * 8;
+      const long rq = p0 + rowq < P ? p0 + rowq : P - 1;
+      const long rl = p0 + row < P ? p0 + row : P - 1;
+      const unsigned short* xb = x + (size_t)rq * ldx;
+      const int kx = k0 + kc < ldx ? k0 + kc : 0;
+      const unsigned xoff = (unsigned)((rl - rq) * ldx + kx);
+#pragma unroll
+      for (int pl = 0; pl < NS; ++pl)
+        __builtin_amdgcn_global_load_lds((const void*)(xb + pl * xplane + xoff),
+                                         (lds_void*)(stage + pl * C::PLANEB + C::TILEF + rowq * ROWB), 16, 0, 0);
+    }
   };
 
   f4_t acc[FL][FP];
@@ -139,7 +155,7 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
     for (int j = 0; j < FP; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
   const int fr = lane & 15, fg = lane >> 4;
-  // fragment byte offsets within a tile (row-dependent swizzle)
+  // fragment byte offsets within a stage (row-dependent swizzle)
   int aoff[FL], boff[FP];
 #pragma unroll
   for (int i = 0; i < FL; ++i) {
@@ -149,70 +165,93 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
 #pragma unroll
   for (int j = 0; j < FP; ++j) {
     const int row = wn + 16 * j + fr;
-    boff[j] = row * ROWB + ((fg ^ swz(row)) << 4);
+    boff[j] = C::TILEF + row * ROWB + ((fg ^ swz(row)) << 4);
   }
-  auto compute = [&](const unsigned char* stage) {
-    bf8_t a[FL], b[FP];
+  bf8_t a[FL], b[FP], alo[NS == 2 ? FL : 1], blo[NS == 2 ? FP : 1];
+  auto read_frags = [&](const unsigned char* stage) {
 #pragma unroll
     for (int i = 0; i < FL; ++i) a[i] = *reinterpret_cast<const bf8_t*>(stage + aoff[i]);
 #pragma unroll
-    for (int j = 0; j < FP; ++j) b[j] = *reinterpret_cast<const bf8_t*>(stage + TILEB + boff[j]);
+    for (int j = 0; j < FP; ++j) b[j] = *reinterpret_cast<const bf8_t*>(stage + boff[j]);
     if constexpr (NS == 2) {
-      bf8_t alo[FL], blo[FP];
 #pragma unroll
-      for (int i = 0; i < FL; ++i) alo[i] = *reinterpret_cast<const bf8_t*>(stage + 2 * TILEB + aoff[i]);
+      for (int i = 0; i < FL; ++i) alo[i] = *reinterpret_cast<const bf8_t*>(stage + C::PLANEB + aoff[i]);
 #pragma unroll
-      for (int j = 0; j < FP; ++j) blo[j] = *reinterpret_cast<const bf8_t*>(stage + 3 * TILEB + boff[j]);
-      __builtin_amdgcn_sched_barrier(0);  // all fragment reads in flight before the first MFMA
+      for (int j = 0; j < FP; ++j) blo[j] = *reinterpret_cast<const bf8_t*>(stage + C::PLANEB + boff[j]);
+    }
+  };
+  // products outermost: consecutive MFMAs write different accumulators
+  auto mfmas = [&]() {
+    if constexpr (NS == 2) {
 #pragma unroll
       for (int i = 0; i < FL; ++i)
 #pragma unroll
-        for (int j = 0; j < FP; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], b[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], blo[j], acc[i][j], 0, 0, 0);
-        }
-    } else {
-      __builtin_amdgcn_sched_barrier(0);  // all fragment reads in flight before the first MFMA
+        for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], b[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < FL; ++i)
+#pragma unroll
+        for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], blo[j], acc[i][j], 0, 0, 0);
     }
 #pragma unroll
     for (int i = 0; i < FL; ++i)
 #pragma unroll
       for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   };
-
-  // ---- pipeline -----------------------------------------------------------------
-  // Every step issues exactly D DMA instructions per wave (past the last chunk it
-  // reloads the last chunk into the free stage, never read), so the number of
-  // instructions in flight behind chunk c is always (S - 2) * D and one constant
-  // vmcnt wait covers every step.
-  const int clast = nchunk - 1;
-  issue(st0, 0);
-  if constexpr (S > 2) {
-    issue(st1, 1 < clast ? 1 : clast);
-    issue(st2, 2 < clast ? 2 : clast);
-  }
-  // One step: wait until this wave's DMAs of chunk c landed, barrier (every wave's
-  // part landed, and every wave is done reading the stage about to be refilled),
-  // refill that stage with chunk c + S - 1, multiply chunk c.
-  auto step = [&](int c, unsigned char* cur, unsigned char* refill) {
-    wait_vm<(S - 2) * C::D>();
+  // a phase boundary: nothing moves across it
+  auto phase_end = [&]() {
+    __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_barrier();
-    issue(refill, c + S - 1 < clast ? c + S - 1 : clast);
-    compute(cur);
+    __builtin_amdgcn_sched_barrier(0);
   };
-  for (int c = 0; c < nchunk; c += S) {
-    if constexpr (S == 4) {
-      step(c, st0, st3);
-      if (c + 1 < nchunk) step(c + 1, st1, st0);
-      if (c + 2 < nchunk) step(c + 2, st2, st1);
-      if (c + 3 < nchunk) step(c + 3, st3, st2);
-    } else {
-      step(c, st0, st1);
-      if (c + 1 < nchunk) step(c + 1, st1, st0);
+
+  // ---- ping-pong pipeline ---------------------------------------------------------
+  // Chunk c is handled in two phases separated by block barriers:
+  //   phase 2c   : group 0 issues the DMA of chunk c + S - 1 and reads its chunk-c
+  //                fragments; group 1 multiplies chunk c - 1;
+  //   phase 2c+1 : group 0 multiplies chunk c; group 1 reads its chunk-c fragments.
+  // Only group 0 issues DMA, exactly D instructions per chunk (past the last
+  // chunk it reloads the last chunk into the free stage, never read), so one
+  // constant vmcnt wait at the end of phase 2c+1 guarantees its part of chunk
+  // c + 1; the following barrier publishes every wave's part.  The stage refilled
+  // in phase 2c held chunk c - 1, read by group 1 in phase 2c - 1 (which waits for
+  // its reads before that phase ends).  Both groups pass 1 + 2 nchunk barriers.
+  const int clast = nchunk - 1;
+  if (g0) {
+#pragma unroll
+    for (int s = 0; s + 1 < S; ++s) issue(ring[s], s < clast ? s : clast);
+    wait_vm<(S - 2) * C::D>();
+    phase_end();
+    for (int c = 0; c < nchunk; c += S) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (c + s < nchunk) {
+          const int cn = c + s + S - 1;
+          issue(ring[(s + S - 1) % S], cn < clast ? cn : clast);
+          read_frags(ring[s]);
+          phase_end();
+          mfmas();
+          wait_vm<(S - 2) * C::D>();  // this wave's DMA of chunk c + s + 1 landed
+          phase_end();
+        }
+      }
     }
+    wait_vm<0>();  // drain the trailing reloads before the LDS is released
+  } else {
+    phase_end();
+    for (int c = 0; c < nchunk; c += S) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (c + s < nchunk) {
+          if (c + s > 0) mfmas();
+          phase_end();
+          read_frags(ring[s]);
+          wait_vm<63>();  // lgkmcnt(0): fragments in registers before the stage can be refilled
+          phase_end();
+        }
+      }
+    }
+    mfmas();  // the last chunk (group 0 is already in its epilogue)
   }
-  // drain the trailing reloads before the LDS is released
-  wait_vm<0>();
 
   // ---- epilogue: f32 16x16 layout: lane, reg r -> row 4*(lane/16) + r, col lane%16
   int aidx[FP], bidx[FP];
@@ -251,7 +290,8 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
           umax = fabs(un) <= DBL_MAX ? fmax(umax, fabs(un)) : INFINITY;
         } else {
           float w = v;
-          if constexpr (EPI == EPI_DIVIDE) w = __fdividef(v, (float)spectral_den(dl + dab[j], epi.alpha, epi.b1, epi.b2));
+          if constexpr (EPI == EPI_DIVIDE)
+            w = __fdividef(v, (float)spectral_den(dl + dab[j], epi.alpha, epi.b1, epi.b2));
           const __bf16 h = (__bf16)w;
           y[off] = __builtin_bit_cast(unsigned short, h);
           if constexpr (NS == 2) y[off + yplane] = __builtin_bit_cast(unsigned short, (__bf16)(w - (float)h));
@@ -310,7 +350,8 @@ bool dma_supported(const LpPass& ps) {
 template <int MODE, class TOut, int EPI>
 static hipError_t launch_dma_t(const LpPass& ps, hipStream_t stream) {
   using namespace dmak;
-  const long tiles_l = (ps.L + BM - 1) / BM;
+  constexpr int BML = KCfg<MODE>::BML;
+  const long tiles_l = (ps.L + BML - 1) / BML;
   const long tiles_p = (ps.P + BN - 1) / BN;
   const long ntiles = tiles_l * tiles_p;
   const long nbp = ((ntiles + 7) / 8) * 8;

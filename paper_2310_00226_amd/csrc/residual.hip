@@ -89,95 +89,147 @@ __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restr
   if (l == nz - 1) zero_pad(r, row0, nz, ldr, rplane);
 }
 
-constexpr int RY = 4, RZ = 64;
+// Tiled march: a block owns a TY (y) x TZ (z) column of nodes and marches along x.
+constexpr int TY = 16, TZ = 64, RW = TY / 4;  // 4 waves, RW rows of y per wave
+constexpr int RY = TY, RZ = TZ;               // grid granularity
 
+template <int KH>
+struct TileGeo {
+  static constexpr int ROWS = TY + 2 * KH, COLS = TZ + 2 * KH, PLANE = ROWS * COLS;
+  // halo cells of a plane tile: KH rows above and below (full width), KH columns
+  // left and right of the core rows
+  static constexpr int HALO = 2 * KH * COLS + TY * 2 * KH;
+  static constexpr int NH = (HALO + 255) / 256;  // per thread
+};
+
+// One block's march.  Per x-plane i the tile (core + halo of KH nodes in y and z)
+// of v is staged in LDS (double-buffered, one barrier per plane): the core from
+// the x-window registers, the halo from global memory (neighbouring blocks' cores,
+// mostly cached).  The y and z neighbour sums read the tile, the x sum reads the
+// thread's register window of 2 KH + 1 planes, whose front is loaded from global
+// memory one plane ahead.  Out-of-domain values are zero in the tile and the
+// window (their band coefficients are zero as well).
 template <int KH, class TR>
 __device__ __forceinline__ void march_body(const double* __restrict__ v, const double* __restrict__ f,
                                            const double* __restrict__ dg, TR* __restrict__ r, int ldr, long rplane,
                                            const double* __restrict__ hx, const double* __restrict__ hy,
                                            const double* __restrict__ hz, int nx, int ny, int nz, int xchunk,
-                                           const Coef& c, int bx, int by, int bz) {
+                                           const Coef& c, int bx, int by, int bz, double* __restrict__ lds) {
   constexpr int BW = 2 * KH + 1;
-  // one wave = one y row (RZ = 64 lanes along z): j and everything derived from it
-  // is wave-uniform and lives in scalar registers
-  const int l = bx * RZ + (threadIdx.x % RZ);
-  const int j = __builtin_amdgcn_readfirstlane(by * RY + (threadIdx.x / RZ));
+  typedef TileGeo<KH> G;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int z0 = bx * TZ, y0 = by * TY;
+  const int l = z0 + lane;
+  const bool lok = l < nz;
   const int i0 = bz * xchunk;
   const int i1 = min(nx, i0 + xchunk);
-  if (l >= nz || j >= ny) return;  // no barriers below: early exit is safe
   const long plane = (long)ny * nz;
-  const long col = (long)j * nz + l;
   const bool has_f = f != nullptr, has_d = dg != nullptr;  // uniform
+  int jr[RW];
+  bool ok[RW];
+#pragma unroll
+  for (int q = 0; q < RW; ++q) {
+    jr[q] = y0 + RW * wave + q;  // wave-uniform
+    ok[q] = lok && jr[q] < ny;
+  }
   double cz[BW];
-  int oz[BW];
-  bool okz[BW];
-  // Neighbour offsets clamped into range (fixed for the march).  Out-of-range
-  // neighbours are loaded from a valid address and selected away (their band
-  // coefficients are zero too), so every load is unconditional.
 #pragma unroll
-  for (int d = 0; d < BW; ++d) {
-    cz[d] = hz[(size_t)l * BW + d];
-    const int ll = l - KH + d;
-    okz[d] = ll >= 0 && ll < nz;
-    oz[d] = (okz[d] ? ll : l) - l;
-  }
-  const double* __restrict__ cyr = hy + (size_t)j * BW;  // uniform
-  // x window: w[d] = v[i - KH + d], zero outside [0, nx)
-  double w[BW];
+  for (int d = 0; d < BW; ++d) cz[d] = lok ? hz[(size_t)l * BW + d] : 0.0;
+  // halo cells of this thread: LDS index and in-plane global offset (-1: outside)
+  int hl[G::NH], hg[G::NH];
 #pragma unroll
-  for (int d = 0; d < BW; ++d) {
-    const int ii = i0 - KH + d;
-    const double x = v[(size_t)(ii < 0 ? 0 : (ii >= nx ? nx - 1 : ii)) * plane + col];
-    w[d] = (ii >= 0 && ii < nx) ? x : 0.0;
+  for (int h = 0; h < G::NH; ++h) {
+    const int idx = tid + 256 * h;
+    int row = 0, col = 0;
+    if (idx < 2 * KH * G::COLS) {
+      const int rb = idx / G::COLS;
+      row = rb < KH ? rb : rb + TY;
+      col = idx % G::COLS;
+    } else {
+      const int sdx = idx - 2 * KH * G::COLS;
+      row = KH + sdx / (2 * KH);
+      const int cs = sdx % (2 * KH);
+      col = cs < KH ? cs : cs + TZ;
+    }
+    const int gy = y0 - KH + row, gz = z0 - KH + col;
+    const bool in = idx < G::HALO;
+    hl[h] = in ? row * G::COLS + col : -1;
+    hg[h] = (in && gy >= 0 && gy < ny && gz >= 0 && gz < nz) ? gy * nz + gz : -1;
   }
-  // software pipeline: the loads of plane i+1 are issued before plane i is reduced
-  double vy[BW], vz[BW], wn, fv, dv;
-  auto load_plane = [&](int i) {
-    const size_t idx = (size_t)i * plane + col;
+  auto at = [&](int i, int q) -> size_t { return (size_t)i * plane + (size_t)jr[q] * nz + (lok ? l : 0); };
+  // x windows: w[q][d] = v[i - KH + d] at (jr[q], l), zero outside the domain
+  double w[RW][BW];
+#pragma unroll
+  for (int q = 0; q < RW; ++q)
 #pragma unroll
     for (int d = 0; d < BW; ++d) {
-      const int jj = j - KH + d;
-      vy[d] = v[idx + (long)((jj >= 0 && jj < ny ? jj : j) - j) * nz];
-      vz[d] = v[idx + oz[d]];
+      const int ii = i0 - KH + d;
+      const bool in = ok[q] && ii >= 0 && ii < nx;
+      const double x = v[in ? at(ii, q) : 0];
+      w[q][d] = in ? x : 0.0;
     }
-    const int inext = i + KH + 1;
-    wn = v[(size_t)(inext < nx ? inext : nx - 1) * plane + col];
-    fv = has_f ? f[idx] : 0.0;
-    dv = has_d ? dg[idx] : 0.0;
+  // prefetched operands of the current plane
+  double hv[G::NH], fv[RW], dv[RW], wn[RW];
+  auto prefetch = [&](int i) {  // halo and f/d of plane i, window front v[i + KH]
+    const int ic = i < nx ? i : nx - 1;
+#pragma unroll
+    for (int h = 0; h < G::NH; ++h) {
+      const double x = v[(size_t)ic * plane + (hg[h] >= 0 ? hg[h] : 0)];
+      hv[h] = hg[h] >= 0 ? x : 0.0;
+    }
+    const int inext = i + KH;  // enters the window when plane i - 1 is done
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      const bool in = ok[q] && inext < nx;
+      const double x = v[in ? at(inext, q) : 0];
+      wn[q] = in ? x : 0.0;
+      fv[q] = (has_f && ok[q]) ? f[at(ic, q)] : 0.0;
+      dv[q] = (has_d && ok[q]) ? dg[at(ic, q)] : 0.0;
+    }
   };
-  if (i0 < i1) load_plane(i0);
+  if (i0 < i1) prefetch(i0);
   for (int i = i0; i < i1; ++i) {
-    double cy_vy[BW], cz_vz[BW];
+    double* __restrict__ T = lds + ((i - i0) & 1) * G::PLANE;
 #pragma unroll
-    for (int d = 0; d < BW; ++d) {
-      const int jj = j - KH + d;
-      cy_vy[d] = (jj >= 0 && jj < ny) ? vy[d] : 0.0;
-      cz_vz[d] = okz[d] ? vz[d] : 0.0;
+    for (int q = 0; q < RW; ++q) T[(KH + RW * wave + q) * G::COLS + KH + lane] = w[q][KH];
+#pragma unroll
+    for (int h = 0; h < G::NH; ++h)
+      if (hl[h] >= 0) T[hl[h]] = hv[h];
+    double fc[RW], dc[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      fc[q] = fv[q];
+      dc[q] = has_d ? dv[q] : w[q][KH];
     }
-    const double wnext = i + KH + 1 < nx ? wn : 0.0;
-    const double fcur = fv;
-    const double dcur = has_d ? dv : w[KH];
-    load_plane(i + 1 < i1 ? i + 1 : i);  // unconditional (the last step reloads a valid plane)
-    __builtin_amdgcn_sched_barrier(0);    // keep the prefetch ahead of the reduction
+    __syncthreads();  // the plane-i tile is complete (and plane i-2's readers are done)
+    prefetch(i + 1);  // halo, f, d of plane i + 1 and the window front v[i + 1 + KH]
     const double* __restrict__ hxr = hx + (size_t)i * BW;
-    double s = 0.0;
 #pragma unroll
-    for (int d = 0; d < BW; ++d) {
-      s += hxr[d] * w[d];
-      s += cyr[d] * cy_vy[d];
-      s += cz[d] * cz_vz[d];
+    for (int q = 0; q < RW; ++q) {
+      const int rc = KH + RW * wave + q;
+      const double* __restrict__ hyr = hy + (size_t)(jr[q] < ny ? jr[q] : 0) * BW;
+      double s = 0.0;
+#pragma unroll
+      for (int d = 0; d < BW; ++d) {
+        s += hxr[d] * w[q][d];
+        s += hyr[d] * T[(rc - KH + d) * G::COLS + KH + lane];
+        s += cz[d] * T[rc * G::COLS + lane + d];
+      }
+      if (ok[q]) {
+        const size_t row0 = ((size_t)i * ny + jr[q]) * ldr;
+        put(r, row0 + l, c.cf * fc[q] - c.cd * dc[q] - c.ch * s, rplane);
+        if (l == nz - 1) zero_pad(r, row0, nz, ldr, rplane);
+      }
+#pragma unroll
+      for (int d = 0; d + 1 < BW; ++d) w[q][d] = w[q][d + 1];
+      w[q][BW - 1] = wn[q];
     }
-    const size_t row0 = ((size_t)i * ny + j) * ldr;
-    put(r, row0 + l, c.cf * fcur - c.cd * dcur - c.ch * s, rplane);
-    if (l == nz - 1) zero_pad(r, row0, nz, ldr, rplane);
-#pragma unroll
-    for (int d = 0; d + 1 < BW; ++d) w[d] = w[d + 1];
-    w[BW - 1] = wnext;
   }
 }
 
 template <int KH, class TR>
-__global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* __restrict__ v,
+__global__ __launch_bounds__(256) void residual_march_kernel(const double* __restrict__ v,
                                                                   const double* __restrict__ f,
                                                                   const double* __restrict__ dg, TR* __restrict__ r,
                                                                   int ldr, long rplane,
@@ -185,15 +237,17 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_kernel(const double* _
                                                                   const double* __restrict__ hy,
                                                                   const double* __restrict__ hz, int nx, int ny,
                                                                   int nz, int xchunk, Coef c) {
+  __shared__ double lds[2 * TileGeo<KH>::PLANE];
   march_body<KH, TR>(v, f, dg, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, c, blockIdx.x, blockIdx.y,
-                     blockIdx.z);
+                     blockIdx.z, lds);
 }
 
 // Residuals of many solves (same k) in one launch: descriptor i owns blocks
 // [block0_i, block0_i + gx * gy * gz) of the grid; inactive solves are skipped.
 template <int KH, class TR>
-__global__ __launch_bounds__(RY * RZ) void residual_march_batch(const ResDesc* __restrict__ descs, int nd,
-                                                                 const int* __restrict__ active) {
+__global__ __launch_bounds__(256) void residual_march_batch(const ResDesc* __restrict__ descs, int nd,
+                                                             const int* __restrict__ active) {
+  __shared__ double lds[2 * TileGeo<KH>::PLANE];
   const long i = blockIdx.x;
   int lo = 0, hi = nd;
   while (hi - lo > 1) {
@@ -208,13 +262,13 @@ __global__ __launch_bounds__(RY * RZ) void residual_march_batch(const ResDesc* _
   const int by = (int)((rb / d.gx) % d.gy);
   const int bz = (int)(rb / ((long)d.gx * d.gy));
   march_body<KH, TR>(d.v, d.f, d.d, (TR*)d.r, d.ldr, d.rplane, d.hx, d.hy, d.hz, d.nx, d.ny, d.nz, d.xchunk,
-                     Coef{d.cf, d.cd, d.ch}, bx, by, bz);
+                     Coef{d.cf, d.cd, d.ch}, bx, by, bz, lds);
 }
 
 // x is split into chunks so that the grid fills the chip even for thin (y, z) planes
 void march_grid(const int dims[3], int* gx, int* gy, int* gz, int* xchunk) {
   const long cols = (long)((dims[2] + RZ - 1) / RZ) * ((dims[1] + RY - 1) / RY);
-  int nchunks = (int)std::min<long>(dims[0], std::max<long>(1, (16384 + cols - 1) / cols));
+  int nchunks = (int)std::min<long>(dims[0], std::max<long>(1, (8192 + cols - 1) / cols));
   *xchunk = (dims[0] + nchunks - 1) / nchunks;
   *gx = (dims[2] + RZ - 1) / RZ;
   *gy = (dims[1] + RY - 1) / RY;
@@ -226,14 +280,14 @@ void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], cons
                   hipStream_t stream) {
   int gx, gy, gz, xchunk;
   march_grid(dims, &gx, &gy, &gz, &xchunk);
-  residual_march_kernel<KH, TR><<<dim3(gx, gy, gz), dim3(RY * RZ), 0, stream>>>(
+  residual_march_kernel<KH, TR><<<dim3(gx, gy, gz), dim3(256), 0, stream>>>(
       ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
 }
 
 template <int KH>
 hipError_t batch_typed(int r_kind, const ResDesc* descs, int nd, long total_blocks, const int* active,
                        hipStream_t s) {
-  const dim3 grid((unsigned)total_blocks), block(RY * RZ);
+  const dim3 grid((unsigned)total_blocks), block(256);
   switch (r_kind) {
     case 0: residual_march_batch<KH, double><<<grid, block, 0, s>>>(descs, nd, active); break;
     case 1: residual_march_batch<KH, float><<<grid, block, 0, s>>>(descs, nd, active); break;
@@ -274,8 +328,8 @@ hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], in
   const long plane = (long)dims[1] * dims[2];
   if (dims[0] <= 0 || plane <= 0) return hipSuccess;
   if (!ra.v || !ra.r || ra.ldr < dims[2] || k < 1) return hipErrorInvalidValue;
-  if ((dims[1] + RY - 1) / RY > 65535 || dims[0] > 65535 || (plane + 255) / 256 > 0x7fffffffL)
-    return hipErrorInvalidValue;
+  // in-plane offsets are 32-bit; the grid's y and z extents are limited to 65535
+  if ((dims[1] + RY - 1) / RY > 65535 || dims[0] > 65535 || plane > 0x7fffffffL) return hipErrorInvalidValue;
   switch (ra.r_kind) {
     case 0: return launch_typed<double>(ra, (double*)ra.r, hb, k, dims, stream);
     case 1: return launch_typed<float>(ra, (float*)ra.r, hb, k, dims, stream);
@@ -295,6 +349,7 @@ hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], in
 bool residual_desc(const ResidualArgs& ra, const double* const hb[3], int k, const int dims[3], ResDesc* d) {
   if (k < 1 || k > 8 || !ra.v || !ra.r || ra.ldr < dims[2] || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0)
     return false;
+  if ((long)dims[1] * dims[2] > 0x7fffffffL) return false;
   if (ra.r_kind == 3 && ra.rplane <= 0) return false;
   d->v = ra.v;
   d->f = ra.f;
