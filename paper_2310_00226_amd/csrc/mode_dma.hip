@@ -4,21 +4,23 @@
 // the axes rotating from pass to pass) for the two BF16 modes, organised for
 // CDNA4:
 //  * operand tiles move from HBM / L2 straight into LDS with
-//    global_load_lds_dwordx4 (no VGPR staging), through a ring of STAGES buffers
-//    addressed with compile-time indices (the chunk loop is unrolled by STAGES);
-//    the kernel orders DMA and LDS reads itself (vmcnt waits + barriers);
+//    global_load_lds_dwordx4 (no VGPR staging), through a ring of STAGES
+//    buffers; the loads of chunk c + STAGES - 1 are in flight while chunk c is
+//    multiplied, and a wave waits (vmcnt) only for the chunk it is about to read;
+//  * the ring stages are addressed with compile-time indices (the chunk loop is
+//    unrolled by STAGES); the kernel orders DMA and LDS reads itself (vmcnt wait
+//    + barrier per chunk), so the loads of later stages stay in flight;
 //  * LDS rows are 64 bytes (32 BF16 = one 16x16x32 MFMA step) made of four
 //    16-byte chunks placed at slot chunk ^ g(row), g(row) = ((row>>1)^(row>>2))&3,
 //    which makes the fragment reads (16 rows x one chunk per 16 lanes)
 //    bank-conflict-free for 32 and 64 four-byte banks;
-//  * ping-pong wave groups: the 8 waves of a block form two groups of 4, one
-//    wave of each per SIMD.  While one group issues MFMAs the other issues the
-//    DMA and reads its next fragments from LDS; block barriers switch the roles
-//    twice per chunk, so every SIMD's MFMA unit is fed by one wave while its
-//    partner waits on memory;
-//  * block tile BML (l) x 256 (p): BF16 256 x 256 with waves of 128 x 64;
-//    split BF16 (three MFMAs per step, twice the operands) 128 x 256 with waves
-//    of 64 x 64 to stay within the register file.
+//  * block tile 256 (l) x 256 (p), eight waves of 128 x 64;
+//  * the output columns run over the padded output layout, p = a * ldy + b with
+//    b < ldy, so that an output row (fixed l) of the tile is one contiguous
+//    segment y[l * A * ldy + p]: the epilogue stages the tile in LDS and writes
+//    it with 16-byte stores (padding columns b >= B receive finite values
+//    computed from a repeated input row, which the next pass multiplies by zero
+//    factor columns).
 // Split BF16 (LP_BF16X3) keeps every operand as two BF16 planes (hi, lo) in
 // HBM, so its intermediates load without conversion too.
 //
@@ -28,7 +30,9 @@
 //    columns), and the second plane (split mode) starts xplane elements after
 //    the first;
 //  * the factor is [l][k] with pitch ldf (multiple of 8, >= 256-rounded L and
-//    32-rounded K), zero outside L x K, second plane fplane elements after the first.
+//    32-rounded K), 256-rounded L rows, zero outside L x K, second plane fplane
+//    elements after the first;
+//  * BF16 outputs have a pitch ldy that is a multiple of 8.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -42,14 +46,22 @@ namespace dmak {
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef unsigned u4_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-constexpr int NTHREADS = 512;  // 8 waves
-constexpr int BN = 256;        // tensor rows per block tile
-constexpr int TP = 64;         // tensor rows per wave
-constexpr int FP = TP / 16;    // 4 MFMA tiles along p
-constexpr int BK = 32;         // BF16 elements per chunk (64-byte LDS rows)
-constexpr int ROWB = BK * 2;   // bytes per LDS row
+constexpr int BM = 256, BN = 256, WL = 2, WP = 4;
+constexpr int NTHREADS = 64 * WL * WP;  // 512
+constexpr int TL = BM / WL, TP = BN / WP;  // 128 x 64 per wave
+constexpr int FL = TL / 16, FP = TP / 16;  // 8 x 4 MFMA tiles
+constexpr int BK = 32;                      // BF16 elements per chunk (64-byte LDS rows)
+constexpr int ROWB = BK * 2;                // bytes per LDS row
+constexpr int TILEB = BM * ROWB;            // bytes per operand tile (16 KB)
+// epilogue staging: BF16 rows of 264 elements (16-byte aligned row starts) and
+// FP32 rows of 260; in both, rows 4 apart start on different banks, so the
+// MFMA output layout writes without conflicts
+constexpr int EROW_H = 264, EROW_F = 260;
+constexpr int EPIB = 256 * EROW_H * 2;  // 256 BF16 rows (>= 128 FP32 rows)
+static_assert(128 * EROW_F * 4 <= EPIB, "FP32 staging fits");
 
 __device__ __forceinline__ int swz(int row) { return ((row >> 1) ^ (row >> 2)) & 3; }
 
@@ -67,19 +79,13 @@ __device__ __forceinline__ void wait_vm() {
 
 template <int MODE>
 struct KCfg {
-  static constexpr int NS = MODE == LP_BF16X3 ? 2 : 1;  // operand planes
-  static constexpr int BML = NS == 2 ? 128 : 256;      // factor rows per block tile
-  static constexpr int TL = BML / 2;                   // factor rows per wave (two groups)
-  static constexpr int FL = TL / 16;
-  static constexpr int TILEF = BML * ROWB;             // bytes of one factor tile plane
-  static constexpr int TILEX = BN * ROWB;              // bytes of one tensor tile plane
-  static constexpr int PLANEB = TILEF + TILEX;
-  static constexpr int STAGEB = NS * PLANEB;
-  static constexpr int STAGES = NS == 2 ? 3 : 4;       // 144 KB / 128 KB of LDS
-  // DMA instructions per chunk per wave of group 0 (16 rows of 64 bytes each)
-  static constexpr int FQ = BML / 16 / 4, XQ = BN / 16 / 4;
-  static constexpr int D = NS * (FQ + XQ);
-  static_assert((STAGES - 2) * D < 64, "vmcnt range");
+  static constexpr int NS = MODE == LP_BF16X3 ? 2 : 1;
+  static constexpr int STAGES = NS == 2 ? 2 : 4;
+  static constexpr int STAGEB = NS * 2 * TILEB;  // factor + tensor tiles, all planes
+  // DMA instructions per chunk per wave: each 1 KB instruction fills 16 rows
+  static constexpr int DMA_PER_TILE = BM / 16 / (WL * WP);  // 2
+  static constexpr int D = NS * 2 * DMA_PER_TILE;
+  static constexpr int SMEM = STAGES * STAGEB > EPIB ? STAGES * STAGEB : EPIB;
 };
 
 template <int MODE, class TOut, int EPI>
@@ -89,63 +95,66 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
                                                          int ldf, long fplane, long tiles_l, long ntiles,
                                                          long nblocks_padded, EpiLP epi) {
   typedef KCfg<MODE> C;
-  constexpr int NS = C::NS, S = C::STAGES, FL = C::FL;
-  __shared__ __attribute__((aligned(1024))) unsigned char ring[S][C::STAGEB];
+  constexpr int NS = C::NS, S = C::STAGES;
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[C::SMEM];
+  unsigned char* const st0 = smem;
+  unsigned char* const st1 = smem + C::STAGEB;
+  unsigned char* const st2 = smem + (S > 2 ? 2 : 0) * C::STAGEB;
+  unsigned char* const st3 = smem + (S > 3 ? 3 : 0) * C::STAGEB;
 
   const long t = xcd_tile(nblocks_padded);
   if (t >= ntiles) return;  // whole block leaves together, before any barrier
   const long lt = t % tiles_l;
   const long pt = t / tiles_l;
-  const int l0 = (int)(lt * C::BML);
+  const int l0 = (int)(lt * BM);
   const long p0 = pt * BN;
+  const long Pp = (long)A * ldy;  // padded output columns
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // Waves w and w + 4 share SIMD w % 4.  Group 0 (waves 0-3) owns factor rows
-  // 0 .. TL-1 of the tile, group 1 (waves 4-7) rows TL .. 2 TL-1; within a group
-  // wave w % 4 owns tensor rows 64 (w % 4) .. + 63.
-  const bool g0 = wave < 4;
-  const int gw = wave & 3;
-  const int wm = g0 ? 0 : C::TL;
-  const int wn = gw * TP;
+  const int wm = (wave / WP) * TL;
+  const int wn = (wave % WP) * TP;
   const int nchunk = (K + BK - 1) / BK;
 
-  // ---- DMA (group 0 only) ----------------------------------------------------
-  // One instruction fills 16 LDS rows: lane i writes slot i % 4 of row
-  // row0 + i / 4 and therefore fetches chunk (i % 4) ^ g(row) of that row.  Wave
-  // gw fills factor rows [FQ*16*gw, +FQ*16) and tensor rows [XQ*16*gw, +XQ*16).
-  // Addresses are a wave-uniform base plus a 32-bit per-lane offset.
+  // ---- DMA source addresses --------------------------------------------------
+  // Instruction q (0, 1) of this wave fills tile rows 16*(2*wave + q) .. +15;
+  // lane i writes LDS slot i % 4 of row 16*(2*wave + q) + i / 4 and therefore
+  // fetches chunk (i % 4) ^ g(row) of that row.  Output column p = a * ldy + b
+  // reads input row a * B + b; padding columns (b >= B) and columns past the end
+  // read a valid row instead.
+  const unsigned short* fsrc[2];
+  const unsigned short* xsrc[2];
+  int fchunk[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int row = 16 * (2 * wave + q) + lane / 4;
+    fchunk[q] = ((lane & 3) ^ swz(row)) * 8;  // element offset of the chunk
+    fsrc[q] = f + (size_t)(l0 + row) * ldf;
+    const long pc = p0 + row;
+    long pr = P - 1;
+    if (pc < Pp) {
+      const long a = pc / ldy;
+      const long b = pc - a * ldy;
+      pr = a * B + (b < B ? b : B - 1);
+    }
+    xsrc[q] = x + (size_t)pr * ldx;
+  }
   auto issue = [&](unsigned char* stage, int c) {
     const int k0 = c * BK;
 #pragma unroll
-    for (int q = 0; q < C::FQ; ++q) {  // factor: padded to whole tiles, always in bounds
-      const int rowq = 16 * (C::FQ * gw + q);
-      const int row = rowq + lane / 4;
-      const int kc = ((lane & 3) ^ swz(row)) * 8;
-      const unsigned short* fb = f + (size_t)(l0 + rowq) * ldf + k0;
-      const unsigned foff = (unsigned)((lane / 4) * ldf + kc);
+    for (int pl = 0; pl < NS; ++pl)
 #pragma unroll
-      for (int pl = 0; pl < NS; ++pl)
-        __builtin_amdgcn_global_load_lds((const void*)(fb + pl * fplane + foff),
-                                         (lds_void*)(stage + pl * C::PLANEB + rowq * ROWB), 16, 0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < C::XQ; ++q) {
-      // tensor: rows past P read row P - 1; chunks past the row pitch read the
-      // row start (finite data times zero factor columns)
-      const int rowq = 16 * (C::XQ * gw + q);
-      const int row = rowq + lane / 4;
-      const int kc = ((lane & 3) ^ swz(row)) * 8;
-      const long rq = p0 + rowq < P ? p0 + rowq : P - 1;
-      const long rl = p0 + row < P ? p0 + row : P - 1;
-      const unsigned short* xb = x + (size_t)rq * ldx;
-      const int kx = k0 + kc < ldx ? k0 + kc : 0;
-      const unsigned xoff = (unsigned)((rl - rq) * ldx + kx);
-#pragma unroll
-      for (int pl = 0; pl < NS; ++pl)
-        __builtin_amdgcn_global_load_lds((const void*)(xb + pl * xplane + xoff),
-                                         (lds_void*)(stage + pl * C::PLANEB + C::TILEF + rowq * ROWB), 16, 0, 0);
-    }
+      for (int q = 0; q < 2; ++q) {
+        const int ldsrow = 16 * (2 * wave + q);
+        unsigned char* fdst = stage + pl * 2 * TILEB + ldsrow * ROWB;
+        unsigned char* xdst = stage + pl * 2 * TILEB + TILEB + ldsrow * ROWB;
+        // factor: padded, always in bounds; tensor: chunks past the row pitch
+        // are redirected to the row start (finite data times zero factor columns)
+        const int kf = k0 + fchunk[q];
+        const int kx = kf < ldx ? kf : 0;
+        __builtin_amdgcn_global_load_lds((const void*)(fsrc[q] + pl * fplane + kf), (lds_void*)fdst, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void*)(xsrc[q] + pl * xplane + kx), (lds_void*)xdst, 16, 0, 0);
+      }
   };
 
   f4_t acc[FL][FP];
@@ -155,7 +164,7 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
     for (int j = 0; j < FP; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
   const int fr = lane & 15, fg = lane >> 4;
-  // fragment byte offsets within a stage (row-dependent swizzle)
+  // fragment byte offsets within a tile (row-dependent swizzle)
   int aoff[FL], boff[FP];
 #pragma unroll
   for (int i = 0; i < FL; ++i) {
@@ -165,24 +174,22 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
 #pragma unroll
   for (int j = 0; j < FP; ++j) {
     const int row = wn + 16 * j + fr;
-    boff[j] = C::TILEF + row * ROWB + ((fg ^ swz(row)) << 4);
+    boff[j] = row * ROWB + ((fg ^ swz(row)) << 4);
   }
-  bf8_t a[FL], b[FP], alo[NS == 2 ? FL : 1], blo[NS == 2 ? FP : 1];
-  auto read_frags = [&](const unsigned char* stage) {
+  auto compute = [&](const unsigned char* stage) {
+    bf8_t a[FL], b[FP];
 #pragma unroll
     for (int i = 0; i < FL; ++i) a[i] = *reinterpret_cast<const bf8_t*>(stage + aoff[i]);
 #pragma unroll
-    for (int j = 0; j < FP; ++j) b[j] = *reinterpret_cast<const bf8_t*>(stage + boff[j]);
+    for (int j = 0; j < FP; ++j) b[j] = *reinterpret_cast<const bf8_t*>(stage + TILEB + boff[j]);
     if constexpr (NS == 2) {
+      bf8_t alo[FL], blo[FP];
 #pragma unroll
-      for (int i = 0; i < FL; ++i) alo[i] = *reinterpret_cast<const bf8_t*>(stage + C::PLANEB + aoff[i]);
+      for (int i = 0; i < FL; ++i) alo[i] = *reinterpret_cast<const bf8_t*>(stage + 2 * TILEB + aoff[i]);
 #pragma unroll
-      for (int j = 0; j < FP; ++j) blo[j] = *reinterpret_cast<const bf8_t*>(stage + C::PLANEB + boff[j]);
-    }
-  };
-  // products outermost: consecutive MFMAs write different accumulators
-  auto mfmas = [&]() {
-    if constexpr (NS == 2) {
+      for (int j = 0; j < FP; ++j) blo[j] = *reinterpret_cast<const bf8_t*>(stage + 3 * TILEB + boff[j]);
+      __builtin_amdgcn_sched_barrier(0);  // all fragment reads in flight before the first MFMA
+      // products outermost: consecutive MFMAs write different accumulators
 #pragma unroll
       for (int i = 0; i < FL; ++i)
 #pragma unroll
@@ -191,122 +198,97 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
       for (int i = 0; i < FL; ++i)
 #pragma unroll
         for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], blo[j], acc[i][j], 0, 0, 0);
+    } else {
+      __builtin_amdgcn_sched_barrier(0);  // all fragment reads in flight before the first MFMA
     }
 #pragma unroll
     for (int i = 0; i < FL; ++i)
 #pragma unroll
       for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   };
-  // a phase boundary: nothing moves across it
-  auto phase_end = [&]() {
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_sched_barrier(0);
-  };
 
-  // ---- ping-pong pipeline ---------------------------------------------------------
-  // Chunk c is handled in two phases separated by block barriers:
-  //   phase 2c   : group 0 issues the DMA of chunk c + S - 1 and reads its chunk-c
-  //                fragments; group 1 multiplies chunk c - 1;
-  //   phase 2c+1 : group 0 multiplies chunk c; group 1 reads its chunk-c fragments.
-  // Only group 0 issues DMA, exactly D instructions per chunk (past the last
-  // chunk it reloads the last chunk into the free stage, never read), so one
-  // constant vmcnt wait at the end of phase 2c+1 guarantees its part of chunk
-  // c + 1; the following barrier publishes every wave's part.  The stage refilled
-  // in phase 2c held chunk c - 1, read by group 1 in phase 2c - 1 (which waits for
-  // its reads before that phase ends).  Both groups pass 1 + 2 nchunk barriers.
+  // ---- pipeline -----------------------------------------------------------------
+  // Every step issues exactly D DMA instructions per wave (past the last chunk it
+  // reloads the last chunk into the free stage, never read), so the number of
+  // instructions in flight behind chunk c is always (S - 2) * D and one constant
+  // vmcnt wait covers every step.
   const int clast = nchunk - 1;
-  if (g0) {
-#pragma unroll
-    for (int s = 0; s + 1 < S; ++s) issue(ring[s], s < clast ? s : clast);
-    wait_vm<(S - 2) * C::D>();
-    phase_end();
-    for (int c = 0; c < nchunk; c += S) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        if (c + s < nchunk) {
-          const int cn = c + s + S - 1;
-          issue(ring[(s + S - 1) % S], cn < clast ? cn : clast);
-          read_frags(ring[s]);
-          phase_end();
-          mfmas();
-          wait_vm<(S - 2) * C::D>();  // this wave's DMA of chunk c + s + 1 landed
-          phase_end();
-        }
-      }
-    }
-    wait_vm<0>();  // drain the trailing reloads before the LDS is released
-  } else {
-    phase_end();
-    for (int c = 0; c < nchunk; c += S) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        if (c + s < nchunk) {
-          if (c + s > 0) mfmas();
-          phase_end();
-          read_frags(ring[s]);
-          wait_vm<63>();  // lgkmcnt(0): fragments in registers before the stage can be refilled
-          phase_end();
-        }
-      }
-    }
-    mfmas();  // the last chunk (group 0 is already in its epilogue)
+  issue(st0, 0);
+  if constexpr (S > 2) {
+    issue(st1, 1 < clast ? 1 : clast);
+    issue(st2, 2 < clast ? 2 : clast);
   }
+  // One step: wait until this wave's DMAs of chunk c landed, barrier (every wave's
+  // part landed, and every wave is done reading the stage about to be refilled),
+  // refill that stage with chunk c + S - 1, multiply chunk c.
+  auto step = [&](int c, unsigned char* cur, unsigned char* refill) {
+    wait_vm<(S - 2) * C::D>();
+    __builtin_amdgcn_s_barrier();
+    issue(refill, c + S - 1 < clast ? c + S - 1 : clast);
+    compute(cur);
+  };
+  for (int c = 0; c < nchunk; c += S) {
+    if constexpr (S == 4) {
+      step(c, st0, st3);
+      if (c + 1 < nchunk) step(c + 1, st1, st0);
+      if (c + 2 < nchunk) step(c + 2, st2, st1);
+      if (c + 3 < nchunk) step(c + 3, st3, st2);
+    } else {
+      step(c, st0, st1);
+      if (c + 1 < nchunk) step(c + 1, st1, st0);
+    }
+  }
+  // drain the trailing reloads, then every wave is done with the ring
+  wait_vm<0>();
+  __syncthreads();
 
   // ---- epilogue: f32 16x16 layout: lane, reg r -> row 4*(lane/16) + r, col lane%16
-  int aidx[FP], bidx[FP];
-  bool pok[FP];
+  // The tile goes through LDS so that global stores are whole row segments.
+  if constexpr (EPI == EPI_ACCUM) {
+    // u += delta in FP64; two rounds of 128 rows staged as FP32
+    float* sf = reinterpret_cast<float*>(smem);
+    double dmax = 0.0, umax = 0.0;
 #pragma unroll
-  for (int j = 0; j < FP; ++j) {
-    const long p = p0 + wn + 16 * j + fr;
-    pok[j] = p < P;
-    const int pi = (int)(pok[j] ? p : 0);
-    aidx[j] = pi / B;
-    bidx[j] = pi - aidx[j] * B;
-  }
-  double dab[FP];
+    for (int half = 0; half < 2; ++half) {
+      if (half) __syncthreads();  // the previous round's readers are done
+      if (wm == half * TL) {
 #pragma unroll
-  for (int j = 0; j < FP; ++j) dab[j] = EPI == EPI_DIVIDE ? epi.l1[aidx[j]] + epi.l2[bidx[j]] : 0.0;
-  double dmax = 0.0, umax = 0.0;
+        for (int i = 0; i < FL; ++i)
 #pragma unroll
-  for (int i = 0; i < FL; ++i)
+          for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int l = l0 + wm + 16 * i + 4 * fg + r;
-      if (l >= L) continue;
-      const double dl = EPI == EPI_DIVIDE ? epi.l0[l] : 0.0;
+            for (int j = 0; j < FP; ++j) sf[(16 * i + 4 * fg + r) * EROW_F + wn + 16 * j + fr] = acc[i][j][r];
+      }
+      __syncthreads();
+      // batches of UB elements per thread: all their loads of u in flight at once
+      constexpr int UB = 16;
+      const int col = tid % BN;  // consecutive threads: consecutive columns
+      const long pc = p0 + col;
+#pragma unroll 1
+      for (int it0 = 0; it0 < TL * BN / NTHREADS; it0 += UB) {
+        double uo[UB];
 #pragma unroll
-      for (int j = 0; j < FP; ++j) {
-        if (!pok[j]) continue;
-        const size_t rowb = ((size_t)l * A + aidx[j]) * ldy;
-        const size_t off = rowb + bidx[j];
-        const float v = acc[i][j][r];
-        if constexpr (EPI == EPI_ACCUM) {
-          const double dv = (double)v;
-          const double un = epi.first ? dv : (double)y[off] + dv;
-          y[off] = (TOut)un;
-          // a NaN / Inf turns the norm into +Inf (fmax alone would drop NaN)
-          dmax = fabs(dv) <= DBL_MAX ? fmax(dmax, fabs(dv)) : INFINITY;
-          umax = fabs(un) <= DBL_MAX ? fmax(umax, fabs(un)) : INFINITY;
-        } else {
-          float w = v;
-          if constexpr (EPI == EPI_DIVIDE)
-            w = __fdividef(v, (float)spectral_den(dl + dab[j], epi.alpha, epi.b1, epi.b2));
-          const __bf16 h = (__bf16)w;
-          y[off] = __builtin_bit_cast(unsigned short, h);
-          if constexpr (NS == 2) y[off + yplane] = __builtin_bit_cast(unsigned short, (__bf16)(w - (float)h));
-          // the row's last element also clears the pitch padding that the next
-          // pass reads (against zero factor columns)
-          if (bidx[j] == B - 1) {
-            for (int e = B; e < ldy; ++e) {
-              y[rowb + e] = 0;
-              if constexpr (NS == 2) y[rowb + e + yplane] = 0;
-            }
+        for (int u = 0; u < UB; ++u) {
+          const int row = (it0 + u) * (NTHREADS / BN) + tid / BN;
+          const long l = l0 + half * TL + row;
+          const bool in = l < L && pc < Pp;
+          uo[u] = (in && !epi.first) ? (double)y[(size_t)l * Pp + pc] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          const int row = (it0 + u) * (NTHREADS / BN) + tid / BN;
+          const long l = l0 + half * TL + row;
+          if (l < L && pc < Pp) {
+            const double dv = (double)sf[row * EROW_F + col];
+            const double un = uo[u] + dv;
+            y[(size_t)l * Pp + pc] = (TOut)un;
+            // a NaN / Inf turns the norm into +Inf (fmax alone would drop NaN)
+            dmax = fabs(dv) <= DBL_MAX ? fmax(dmax, fabs(dv)) : INFINITY;
+            umax = fabs(un) <= DBL_MAX ? fmax(umax, fabs(un)) : INFINITY;
           }
         }
       }
     }
-  if constexpr (EPI == EPI_ACCUM) {
     if (epi.norms) {
 #pragma unroll
       for (int s = 32; s >= 1; s >>= 1) {
@@ -317,6 +299,60 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(const unsigned short* _
         atomicMax(reinterpret_cast<unsigned long long*>(epi.norms), (unsigned long long)__double_as_longlong(dmax));
         atomicMax(reinterpret_cast<unsigned long long*>(epi.norms) + 1,
                   (unsigned long long)__double_as_longlong(umax));
+      }
+    }
+  } else {
+    // BF16 planes (hi, then lo for split), optional spectral divide
+    if constexpr (EPI == EPI_DIVIDE) {
+      double dab[FP];
+#pragma unroll
+      for (int j = 0; j < FP; ++j) {
+        const long pc = p0 + wn + 16 * j + fr;
+        long a = 0, b = 0;
+        if (pc < Pp) {
+          a = pc / ldy;
+          b = pc - a * ldy;
+          if (b >= B) b = B - 1;  // padding column: any finite value
+        }
+        dab[j] = epi.l1[a] + epi.l2[b];
+      }
+#pragma unroll
+      for (int i = 0; i < FL; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = l0 + wm + 16 * i + 4 * fg + r;
+          const double dl = epi.l0[l < L ? l : L - 1];
+#pragma unroll
+          for (int j = 0; j < FP; ++j)
+            acc[i][j][r] = __fdividef(acc[i][j][r], (float)spectral_den(dl + dab[j], epi.alpha, epi.b1, epi.b2));
+        }
+    }
+    unsigned short* sh = reinterpret_cast<unsigned short*>(smem);
+#pragma unroll
+    for (int pl = 0; pl < NS; ++pl) {
+      if (pl) __syncthreads();  // the previous round's readers are done
+#pragma unroll
+      for (int i = 0; i < FL; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int j = 0; j < FP; ++j) {
+            const float w = acc[i][j][r];
+            const __bf16 h = (__bf16)w;
+            const __bf16 o = pl == 0 ? h : (__bf16)(w - (float)h);
+            sh[(wm + 16 * i + 4 * fg + r) * EROW_H + wn + 16 * j + fr] = __builtin_bit_cast(unsigned short, o);
+          }
+      __syncthreads();
+      TOut* __restrict__ yp = y + pl * yplane;
+#pragma unroll 4
+      for (int it = 0; it < BM * BN / 8 / NTHREADS; ++it) {
+        const int idx = it * NTHREADS + tid;
+        const int row = idx / (BN / 8), ch = idx % (BN / 8);
+        const long l = l0 + row;
+        const long pc = p0 + 8 * ch;
+        if (l < L && pc < Pp)  // Pp is a multiple of 8: a chunk is wholly in or out
+          *reinterpret_cast<u4_t*>(yp + (size_t)l * Pp + pc) =
+              *reinterpret_cast<const u4_t*>(sh + row * EROW_H + 8 * ch);
       }
     }
   }
@@ -341,18 +377,19 @@ __global__ __launch_bounds__(256) void to_lowp_kernel(const double* __restrict__
 
 bool dma_supported(const LpPass& ps) {
   // whole 256-row factor tiles must exist in the padded factor; the tensor pitch
-  // must keep 16-byte chunks aligned
+  // must keep 16-byte chunks aligned, BF16 outputs 16-byte row segments
   const long pad256 = (ps.L + 255) / 256 * 256;
+  const bool out_ok = ps.out_kind == 0 ? ps.ldy == ps.B : (ps.ldy % 8 == 0 && ps.ldy >= ps.B);
   return (ps.mode == LP_BF16 || ps.mode == LP_BF16X3) && ps.in_kind == 2 && ps.ldf >= pad256 &&
-         ps.ldf % 8 == 0 && ps.ldx % 8 == 0 && ps.ldx >= ps.K && ps.ldf >= (ps.K + 31) / 32 * 32;
+         ps.ldf % 8 == 0 && ps.ldx % 8 == 0 && ps.ldx >= ps.K && ps.ldf >= (ps.K + 31) / 32 * 32 && out_ok &&
+         ps.P == (long)ps.A * ps.B;
 }
 
 template <int MODE, class TOut, int EPI>
 static hipError_t launch_dma_t(const LpPass& ps, hipStream_t stream) {
   using namespace dmak;
-  constexpr int BML = KCfg<MODE>::BML;
-  const long tiles_l = (ps.L + BML - 1) / BML;
-  const long tiles_p = (ps.P + BN - 1) / BN;
+  const long tiles_l = (ps.L + BM - 1) / BM;
+  const long tiles_p = ((long)ps.A * ps.ldy + BN - 1) / BN;
   const long ntiles = tiles_l * tiles_p;
   const long nbp = ((ntiles + 7) / 8) * 8;
   if (ntiles == 0) return hipSuccess;

@@ -89,8 +89,10 @@ __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restr
   if (l == nz - 1) zero_pad(r, row0, nz, ldr, rplane);
 }
 
-// Tiled march: a block owns a TY (y) x TZ (z) column of nodes and marches along x.
-constexpr int TY = 16, TZ = 64, RW = TY / 4;  // 4 waves, RW rows of y per wave
+// Tiled march: a block (8 waves) owns a TY (y) x TZ (z) column of nodes and marches
+// along x; each wave owns RW rows of y.
+constexpr int RT = 512;                       // threads per block (8 waves)
+constexpr int TY = 16, TZ = 64, RW = TY / 8;  // RW rows of y per wave
 constexpr int RY = TY, RZ = TZ;               // grid granularity
 
 template <int KH>
@@ -99,7 +101,7 @@ struct TileGeo {
   // halo cells of a plane tile: KH rows above and below (full width), KH columns
   // left and right of the core rows
   static constexpr int HALO = 2 * KH * COLS + TY * 2 * KH;
-  static constexpr int NH = (HALO + 255) / 256;  // per thread
+  static constexpr int NH = (HALO + RT - 1) / RT;  // per thread
 };
 
 // One block's march.  Per x-plane i the tile (core + halo of KH nodes in y and z)
@@ -140,7 +142,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
   int hl[G::NH], hg[G::NH];
 #pragma unroll
   for (int h = 0; h < G::NH; ++h) {
-    const int idx = tid + 256 * h;
+    const int idx = tid + RT * h;
     int row = 0, col = 0;
     if (idx < 2 * KH * G::COLS) {
       const int rb = idx / G::COLS;
@@ -229,7 +231,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
 }
 
 template <int KH, class TR>
-__global__ __launch_bounds__(256) void residual_march_kernel(const double* __restrict__ v,
+__global__ __launch_bounds__(RT) void residual_march_kernel(const double* __restrict__ v,
                                                                   const double* __restrict__ f,
                                                                   const double* __restrict__ dg, TR* __restrict__ r,
                                                                   int ldr, long rplane,
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(256) void residual_march_kernel(const double* __res
 // Residuals of many solves (same k) in one launch: descriptor i owns blocks
 // [block0_i, block0_i + gx * gy * gz) of the grid; inactive solves are skipped.
 template <int KH, class TR>
-__global__ __launch_bounds__(256) void residual_march_batch(const ResDesc* __restrict__ descs, int nd,
+__global__ __launch_bounds__(RT) void residual_march_batch(const ResDesc* __restrict__ descs, int nd,
                                                              const int* __restrict__ active) {
   __shared__ double lds[2 * TileGeo<KH>::PLANE];
   const long i = blockIdx.x;
@@ -280,14 +282,14 @@ void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], cons
                   hipStream_t stream) {
   int gx, gy, gz, xchunk;
   march_grid(dims, &gx, &gy, &gz, &xchunk);
-  residual_march_kernel<KH, TR><<<dim3(gx, gy, gz), dim3(256), 0, stream>>>(
+  residual_march_kernel<KH, TR><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
       ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
 }
 
 template <int KH>
 hipError_t batch_typed(int r_kind, const ResDesc* descs, int nd, long total_blocks, const int* active,
                        hipStream_t s) {
-  const dim3 grid((unsigned)total_blocks), block(256);
+  const dim3 grid((unsigned)total_blocks), block(RT);
   switch (r_kind) {
     case 0: residual_march_batch<KH, double><<<grid, block, 0, s>>>(descs, nd, active); break;
     case 1: residual_march_batch<KH, float><<<grid, block, 0, s>>>(descs, nd, active); break;
