@@ -119,6 +119,13 @@ sem_status sem_residual(sem_plan *p, const double *u, const double *f, double *r
 sem_status sem_solve_refined(sem_plan *p, sem_prec prec, double tol, int max_iter, const double *f, double *u,
                              int *iters, double *last_update_rel);
 
+/* One fast-diagonalisation solve (eq. 3D-Poisson) with its six mode products in
+ * precision prec (SEM_F32, SEM_BF16, SEM_BF16X3; SEM_F64 = sem_solve) and no
+ * refinement: the single-precision solve of Sec. 3.7 (Table 10), accurate to
+ * about the working precision times the conditioning.  u is FP64 (u = delta of
+ * the first refinement iteration); u must not alias f.  Asynchronous. */
+sem_status sem_solve_lowp(sem_plan *p, sem_prec prec, const double *f, double *u);
+
 /* ---- batched solves ---------------------------------------------------------- */
 
 typedef struct sem_batch sem_batch;

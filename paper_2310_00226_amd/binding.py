@@ -45,6 +45,7 @@ def _load():
         "sem_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "sem_solve_refined": (c_int, [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, POINTER(c_int),
                                       POINTER(c_double)]),
+        "sem_solve_lowp": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
         "sem_axis_host": (c_int, [c_int, c_int, c_double, c_double, c_int, POINTER(c_int), dp, dp, dp, dp, dp]),
         "sem_batch_create": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p)]),
         "sem_batch_destroy": (None, [c_void_p]),
@@ -189,6 +190,18 @@ class Plan:
         if raise_on_error:
             check(st)
         return u, it.value, rel.value, st
+
+    def solve_lowp(self, f, u=None, prec: str = "bf16x3"):
+        """One unrefined solve with low-precision mode products (sem_solve_lowp)."""
+        import torch
+        if u is None:
+            u = torch.empty_like(f)
+        pv = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        fp = _dev_ptr(f, "f", self.numel, torch.float64)
+        up = _dev_ptr(u, "u", self.numel, torch.float64)
+        self._prepare(pv)
+        check(lib.sem_solve_lowp(self._p, pv, fp, up))
+        return u
 
     def mode_product(self, axis: int, inverse: bool, x, out=None):
         import torch

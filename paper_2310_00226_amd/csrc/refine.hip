@@ -341,3 +341,17 @@ extern "C" sem_status sem_solve_refined(sem_plan* p, sem_prec prec, double tol, 
   if (tol > 0) return set_error(SEM_ENOCONV, "sem_solve_refined: tolerance not met within max_iter");
   return SEM_OK;
 }
+
+extern "C" sem_status sem_solve_lowp(sem_plan* p, sem_prec prec, const double* f, double* u) {
+  if (!p || !f || !u) return set_error(SEM_EINVAL, "sem_solve_lowp: null argument");
+  if (f == u) return set_error(SEM_EINVAL, "sem_solve_lowp: u must not alias f");
+  if (prec == SEM_F64) return sem_solve(p, f, u);
+  if (prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3)
+    return set_error(SEM_EINVAL, "sem_solve_lowp: unknown precision");
+  LpWork w;
+  sem_status st = lp_prepare(p, prec, &w);
+  if (st != SEM_OK) return st;
+  const hipError_t e = lp_fd(p, w, Spectral{p->alpha, 1.0, 0.0}, f, u, 1, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "sem_solve_lowp");
+  return SEM_OK;
+}

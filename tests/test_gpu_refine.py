@@ -107,3 +107,21 @@ def test_refined_full_size_n999(torch, P):
         err = float((ud.cpu() - torch.from_numpy(u_ref)).abs().max()) / scale
         _log(f"    iters={iters} last_rel={rel:.2e} rel err vs oracle {err:.2e}")
         assert err <= TOL_REFINED
+
+
+# accuracy of one unrefined solve: about the precision's unit roundoff times the
+# growth through six mode products and the divide (bounds measured with margin)
+LOWP_BOUND = {"f32": 1e-5, "bf16x3": 1e-4, "bf16": 5e-2}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_unrefined_lowp_solve(torch, P, prec):
+    k, ne, box, alpha = 4, (12, 9, 10), (-1, 1, -1, 1, -1, 1), 1.0
+    prob = O.Problem(k, ne, box, alpha, "dirichlet")
+    f = helmholtz_rhs(*(o.x for o in prob.axes), alpha)
+    plan = P.Plan(k, ne, box, alpha, "dirichlet")
+    u = plan.solve_lowp(_dev(torch, f), prec=prec).cpu().numpy()
+    err = O.rel_max_err(u, O.fd_solve(prob, f))
+    _log(f"[lowp] {prec}: unrefined rel err {err:.2e}")
+    assert err <= LOWP_BOUND[prec], err
+    assert err > 1e-13  # an FP64 solve would be at ~1e-15: low precision really was used
