@@ -106,7 +106,12 @@ sem_status sem_residual(sem_plan *p, const double *u, const double *f, double *r
 
 /* Mixed-precision solve with FP64 iterative refinement:
  *   u = 0, r = f;  repeat  delta = FD_prec(r),  u += delta,  r = f - M_3^{-1} A u
- *   until ||delta||_inf <= tol * ||u||_inf  (iterations <= max_iter).
+ *   until ||delta||_inf <= tol * ||u||_inf, or until the updates contract fast
+ *   enough that the remaining error is predicted below that: with
+ *   r_k = ||delta_k|| / ||u_k|| and, from the third iteration on, q = the larger
+ *   of r_k / r_{k-1} and r_{k-1} / r_{k-2}, stop when q < 1/2 and
+ *   q r_k / (1 - q) <= tol (the next update and all later ones are at most that
+ *   for a contraction that stays at q)  (iterations <= max_iter).
  * FD_prec is eq. 3D-Poisson with its six mode products in precision `prec`
  * (SEM_F32, SEM_BF16, SEM_BF16X3; SEM_F64 performs one FP64 solve); the update
  * of u and the residual are FP64.  tol = 0 runs exactly max_iter iterations.

@@ -414,7 +414,7 @@ sem_status sem_batch_solve(sem_batch* b, sem_prec prec, double tol, int max_iter
         continue;
       }
       const double rel = umax > 0 ? dmax / umax : (dmax > 0 ? INFINITY : 0.0);
-      if (tol > 0 && rel <= tol) {
+      if (refine_converged(rel, prev[i], prev2[i], tol)) {
         active[i] = 0;
         continue;
       }

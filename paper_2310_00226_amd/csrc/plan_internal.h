@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 
 #include "../../include/sem.h"
@@ -58,6 +59,23 @@ hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double*
                  unsigned long long* norms);
 hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp);
 hipError_t zero_norms(unsigned long long* norms, hipStream_t stream);
+
+// Refinement stop test on the relative updates r_k = ||delta_k|| / ||u_k||: met
+// when r_k <= tol, or when the observed contraction, q = the larger of the last
+// two ratios r_k / r_{k-1} and r_{k-1} / r_{k-2} (from the third iteration on;
+// the convergence of the coarsest precisions alternates between fast and slow
+// steps), is below 1/2 and makes the predicted remaining error q r_k / (1 - q)
+// (a bound on the next update and all later ones for contraction q) <= tol.
+// prev = r_{k-1}, prev2 = r_{k-2}; infinite when not yet available.
+inline bool refine_converged(double rel, double prev, double prev2, double tol) {
+  if (!(tol > 0)) return false;
+  if (rel <= tol) return true;
+  if (prev > 0 && prev < 1e300 && prev2 > 0 && prev2 < 1e300) {
+    const double q = fmax(rel / prev, prev / prev2);
+    if (q < 0.5 && rel * q / (1.0 - q) <= tol) return true;
+  }
+  return false;
+}
 
 sem_status hip_fail(hipError_t e, const char* what);
 sem_status set_error(sem_status st, const char* msg);

@@ -4,7 +4,8 @@
 //   repeat: delta = S_3 [ (F_3 r) ./ (Lambda3D + alpha) ]   (mode products in low precision)
 //           u += delta                                      (FP64, fused into the last pass)
 //           r  = f - M_3^{-1} A u                           (FP64 matrix-free residual)
-//   until ||delta||_inf <= tol ||u||_inf.
+//   until ||delta||_inf <= tol ||u||_inf, or the observed contraction of the
+//   updates predicts that the remaining error is below that (refine_converged).
 // The low-precision solve is eq. 3D-Poisson of the paper (Sec. 2.4) with its
 // mode products rounded to FP32 / BF16; the refinement around it is not in the
 // paper (its single-precision runs plateau without it, Table 10).
@@ -332,7 +333,7 @@ extern "C" sem_status sem_solve_refined(sem_plan* p, sem_prec prec, double tol, 
       return set_error(SEM_ENONFINITE, "sem_solve_refined: non-finite update");
     const double rel = umax > 0 ? dmax / umax : (dmax > 0 ? INFINITY : 0.0);
     if (last_update_rel) *last_update_rel = rel;
-    if (tol > 0 && rel <= tol) return SEM_OK;
+    if (refine_converged(rel, prev, prev2, tol)) return SEM_OK;
     if (it >= 2 && rel > prev && prev > prev2)
       return set_error(SEM_ENOCONV, "sem_solve_refined: updates grow; refinement diverges at this precision");
     prev2 = prev;

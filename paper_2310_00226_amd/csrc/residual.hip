@@ -267,11 +267,13 @@ __global__ __launch_bounds__(RT) void residual_march_batch(const ResDesc* __rest
                      Coef{d.cf, d.cd, d.ch}, bx, by, bz, lds);
 }
 
-// x is split into chunks so that the grid fills the chip even for thin (y, z) planes
-void march_grid(const int dims[3], int* gx, int* gy, int* gz, int* xchunk) {
+// x is split into chunks so that the grid fills the chip even for thin (y, z)
+// planes; a chunk spans at least 8 k planes, since each chunk first loads the 2k
+// planes of its window
+void march_grid(const int dims[3], int k, int* gx, int* gy, int* gz, int* xchunk) {
   const long cols = (long)((dims[2] + RZ - 1) / RZ) * ((dims[1] + RY - 1) / RY);
   int nchunks = (int)std::min<long>(dims[0], std::max<long>(1, (8192 + cols - 1) / cols));
-  *xchunk = (dims[0] + nchunks - 1) / nchunks;
+  *xchunk = std::max((dims[0] + nchunks - 1) / nchunks, std::min(dims[0], 8 * k));
   *gx = (dims[2] + RZ - 1) / RZ;
   *gy = (dims[1] + RY - 1) / RY;
   *gz = (dims[0] + *xchunk - 1) / *xchunk;
@@ -281,7 +283,7 @@ template <int KH, class TR>
 void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], const int dims[3], Coef c,
                   hipStream_t stream) {
   int gx, gy, gz, xchunk;
-  march_grid(dims, &gx, &gy, &gz, &xchunk);
+  march_grid(dims, KH, &gx, &gy, &gz, &xchunk);
   residual_march_kernel<KH, TR><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
       ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
 }
@@ -365,7 +367,7 @@ bool residual_desc(const ResidualArgs& ra, const double* const hb[3], int k, con
   d->nx = dims[0];
   d->ny = dims[1];
   d->nz = dims[2];
-  march_grid(dims, &d->gx, &d->gy, &d->gz, &d->xchunk);
+  march_grid(dims, k, &d->gx, &d->gy, &d->gz, &d->xchunk);
   d->cf = ra.cf;
   d->cd = ra.cd;
   d->ch = ra.ch;
