@@ -198,16 +198,22 @@ class Problem:
     """-Lap u + alpha u = f on a box with homogeneous Dirichlet or Neumann BCs,
     Q^k SEM with ne[a] elements on axis a (Sec. 2, eq. pde / matvec3D)."""
 
-    def __init__(self, k: int, ne, box, alpha: float, bc: str):
+    def __init__(self, k: int, ne, box, alpha: float, bc: str, eigen: bool = True):
+        """eigen=False builds only the 1D operators (enough for residuals)."""
         self.k = int(k)
         self.ne = tuple(int(v) for v in ne)
         self.box = tuple(float(v) for v in box)
         self.alpha = float(alpha)
         self.bc = bc
-        pairs = [_axis_eigen_cached(self.k, self.ne[a], self.box[2 * a], self.box[2 * a + 1], bc)
-                 for a in range(3)]
-        self.axes = [p[0] for p in pairs]
-        self.eig = [p[1] for p in pairs]
+        if eigen:
+            pairs = [_axis_eigen_cached(self.k, self.ne[a], self.box[2 * a], self.box[2 * a + 1], bc)
+                     for a in range(3)]
+            self.axes = [p[0] for p in pairs]
+            self.eig = [p[1] for p in pairs]
+        else:
+            self.axes = [axis_operators(self.k, self.ne[a], self.box[2 * a], self.box[2 * a + 1], bc)
+                         for a in range(3)]
+            self.eig = None
 
     @property
     def shape(self):
