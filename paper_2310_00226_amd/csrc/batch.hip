@@ -9,7 +9,7 @@
 // that meet the tolerance drop out through a per-solve active flag, so later
 // iterations only work on the rest.
 //
-// Tile shape: the FP32 kernel has 128 x 128, 64 x 128 and 32 x 128 block tiles
+// Tile shape: the FP32 kernel has 128 x 128, 96 x 128, 64 x 128 and 32 x 128 block tiles
 // (factor rows x tensor rows).  Short contraction lengths waste most of a
 // 128-row factor tile, so the shape is chosen per length bucket (16, 32, 64, 128,
 // 256, 512 and above) by timing the candidates on the batch's own passes when the
@@ -29,7 +29,7 @@ namespace semfd {
 namespace {
 
 constexpr int NBUCKET = 6;
-constexpr int TILE_CANDIDATES[3] = {128, 64, 32};
+constexpr int TILE_CANDIDATES[4] = {128, 96, 64, 32};
 // pass variants: 0 = forward z from f (FP64 input), 1 = forward z from r,
 // 2..5 = passes 1..4 (2 ... 4 = forward y, forward x + divide, backward z, backward y),
 // 6 = backward x storing u (first iteration), 7 = backward x accumulating into u

@@ -94,7 +94,7 @@ struct LpDesc {
   int sid = 0;
 };
 // Persistent FP32 launch over nd descriptors (device array) with tile_rows in
-// {128, 64, 32} (block tile tile_rows x 128), grid blocks striding over
+// {128, 96, 64, 32} (block tile tile_rows x 128), grid blocks striding over
 // total_tiles; active: device array of per-solve flags.
 hipError_t launch_mode_f32_batch(int in_kind, int out_kind, int epi, int tile_rows, const LpDesc* descs, int nd,
                                  long total_tiles, const int* active, int grid, hipStream_t stream);

@@ -12,8 +12,9 @@
 // GEMM view:  C[l][p] = sum_k F[l][k] X[p][k],  p = a*B + b, output address
 // (l*A + a)*ldy + b.  Block tile BM (l) x BN (p) of v_mfma_f32_16x16x4_f32
 // tiles, register-staged loads into a double-buffered LDS tile.  The tile
-// shapes (128 x 128, 64 x 128, 32 x 128) cover large and small contraction
-// lengths; the batched launcher picks one per length bucket by timing them.
+// shapes (128 x 128, 96 x 128, 64 x 128, 32 x 128) cover large and small
+// contraction lengths; the batched launcher picks one per length bucket by
+// timing them, the single launcher the one with the fewest padded rows.
 // Epilogues: store (FP32 intermediates), spectral divide (third forward pass),
 // or accumulate into the FP64 solution (u += delta) while recording max|delta|
 // and max|u| for the refinement stop test.
@@ -40,6 +41,7 @@ struct Tile {
   static constexpr int FL = TL / 16, FP = TP / 16;  // MFMA tiles per wave
 };
 typedef Tile<128, 128, 2, 2> T128;  // 4 waves of 64 x 64
+typedef Tile<96, 128, 2, 2> T96;    // 4 waves of 48 x 64
 typedef Tile<64, 128, 2, 2> T64;    // 4 waves of 32 x 64
 typedef Tile<32, 128, 1, 4> T32;    // 4 waves of 32 x 32
 
@@ -316,6 +318,7 @@ hipError_t batch_by_tile(int tile_rows, const LpDesc* descs, int nd, long total_
                          hipStream_t s) {
   switch (tile_rows) {
     case 128: return launch_batch_t<TIn, TOut, EPI, T128>(descs, nd, total_tiles, active, grid, s);
+    case 96: return launch_batch_t<TIn, TOut, EPI, T96>(descs, nd, total_tiles, active, grid, s);
     case 64: return launch_batch_t<TIn, TOut, EPI, T64>(descs, nd, total_tiles, active, grid, s);
     case 32: return launch_batch_t<TIn, TOut, EPI, T32>(descs, nd, total_tiles, active, grid, s);
     default: return hipErrorInvalidValue;
@@ -325,6 +328,19 @@ hipError_t batch_by_tile(int tile_rows, const LpDesc* descs, int nd, long total_
 }  // namespace f32k
 
 // ---------------------------------------------------------------------------
+template <class TT>
+static hipError_t launch_single_tile(const LpDesc& d, const LpPass& ps, hipStream_t stream) {
+  using namespace f32k;
+  if (ps.out_kind == 0)
+    return ps.in_kind == 0 ? launch_single<double, double, EPI_ACCUM, TT>(d, stream)
+                           : launch_single<float, double, EPI_ACCUM, TT>(d, stream);
+  if (ps.epi_kind == EPI_DIVIDE)
+    return ps.in_kind == 0 ? launch_single<double, float, EPI_DIVIDE, TT>(d, stream)
+                           : launch_single<float, float, EPI_DIVIDE, TT>(d, stream);
+  return ps.in_kind == 0 ? launch_single<double, float, EPI_STORE, TT>(d, stream)
+                         : launch_single<float, float, EPI_STORE, TT>(d, stream);
+}
+
 bool lp_kind_ok(int in_kind, int out_kind, int epi) {
   if (out_kind == 0) return epi == EPI_ACCUM && (in_kind == 0 || in_kind == 1);
   return out_kind == 1 && epi != EPI_ACCUM && (in_kind == 0 || in_kind == 1);
@@ -346,14 +362,11 @@ hipError_t launch_mode_lp(const LpPass& ps, hipStream_t stream) {
   d.L = ps.L;
   d.ldf = ps.ldf;
   using namespace f32k;
-  if (ps.out_kind == 0)
-    return ps.in_kind == 0 ? launch_single<double, double, EPI_ACCUM, T128>(d, stream)
-                           : launch_single<float, double, EPI_ACCUM, T128>(d, stream);
-  if (ps.epi_kind == EPI_DIVIDE)
-    return ps.in_kind == 0 ? launch_single<double, float, EPI_DIVIDE, T128>(d, stream)
-                           : launch_single<float, float, EPI_DIVIDE, T128>(d, stream);
-  return ps.in_kind == 0 ? launch_single<double, float, EPI_STORE, T128>(d, stream)
-                         : launch_single<float, float, EPI_STORE, T128>(d, stream);
+  // 96-row factor tiles when they cover L with clearly fewer padded rows (e.g.
+  // L = 257: 288 rows instead of 384)
+  const long r128 = (ps.L + 127) / 128 * 128, r96 = (ps.L + 95) / 96 * 96;
+  if (r96 * 10 < r128 * 9) return launch_single_tile<T96>(d, ps, stream);
+  return launch_single_tile<T128>(d, ps, stream);
 }
 
 hipError_t launch_mode_f32_batch(int in_kind, int out_kind, int epi, int tile_rows, const LpDesc* descs, int nd,
@@ -383,6 +396,10 @@ int lp_batch_blocks_per_cu(int tile_rows) {
     case 128:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mode_rot_f32_batch<float, float, EPI_STORE, T128>,
                                                        T128::NTHREADS, 0);
+      break;
+    case 96:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mode_rot_f32_batch<float, float, EPI_STORE, T96>,
+                                                       T96::NTHREADS, 0);
       break;
     case 64:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mode_rot_f32_batch<float, float, EPI_STORE, T64>,

@@ -97,9 +97,10 @@ void release_lowp(sem_plan* p) {
 }
 
 // Low-precision copies of the factors, layout [l][k] (row l = output mode,
-// contraction k contiguous), zero-padded to pad256(n) x pad256(n): FP32, and
-// BF16 hi followed by BF16 lo = bf16(v - hi) in one allocation (lp_lo = lp_hi +
-// ld * ld elements).
+// contraction k contiguous), zero-padded to pitch ld = pad256(n): FP32 with
+// ld + 96 rows (whole tiles of 128, 96, 64 or 32 rows stay inside), and BF16 hi
+// followed by BF16 lo = bf16(v - hi) with ld rows each in one allocation
+// (lp_lo = lp_hi + ld * ld elements).
 static sem_status ensure_lowp(sem_plan* p) {
   if (p->lp_ready) return SEM_OK;
   for (int a = 0; a < 3; ++a) {
@@ -108,7 +109,7 @@ static sem_status ensure_lowp(sem_plan* p) {
     p->lp_ld[a] = ld;
     for (int d = 0; d < 2; ++d) {
       const std::vector<double>& M = d == 0 ? p->ax[a].F : p->ax[a].S;
-      std::vector<float> f32(plane, 0.0f);
+      std::vector<float> f32(plane + 96 * (size_t)ld, 0.0f);
       std::vector<unsigned short> hl(2 * plane, 0);
       for (int l = 0; l < n; ++l)
         for (int k = 0; k < n; ++k) {
