@@ -233,8 +233,13 @@ def main() -> int:
     # (its six mode-product launches, the right-hand side conversion included),
     # timed alone with HIP events on the stream the kernels run on
     lowp_roof = None
-    if best != "f64":
-        prec = best.split("_")[0]
+    for name, v in variants.items():
+        if name == "f64":
+            continue
+        # one low-precision FD application of this variant (right-hand-side
+        # conversion and six mode-product launches), timed alone with HIP events on
+        # the stream the kernels run on
+        prec = name.split("_")[0]
         ul = torch.empty_like(f)
         plan.solve_lowp(f, ul, prec=prec)
         torch.cuda.synchronize()
@@ -247,13 +252,16 @@ def main() -> int:
         del ul
         peak = PEAK_FP32_TFLOPS if prec == "f32" else PEAK_BF16_TFLOPS
         ach = fd_flops / (fd_ms * 1e-3) / 1e12
-        lowp_roof = {"bound": "mfma", "kernel": f"{prec} FD application: six mode_rot passes "
-                                                 f"({'mode_rot_dma' if prec != 'f32' else 'mode_rot_f32'})",
-                     "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
-                     "launch_ms": fd_ms, "flops_per_launch": fd_flops,
-                     "mfma_work_factor": 3 if prec == "bf16x3" else 1}
+        roof = {"bound": "mfma", "kernel": f"{prec} FD application: six mode_rot passes "
+                                           f"({'mode_rot_dma' if prec != 'f32' else 'mode_rot_f32'})",
+                "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                "launch_ms": fd_ms, "flops_per_launch": fd_flops,
+                "mfma_work_factor": 3 if prec == "bf16x3" else 1}
+        v["fd_application"] = roof
         log(f"{prec} FD application alone: {fd_ms:.2f} ms, {ach:.1f} TFLOP/s algorithmic "
             f"({ach / peak:.3f} of {peak} TFLOP/s)")
+        if name == best:
+            lowp_roof = roof
 
     # dominant kernel: the batched NN mode product (y axis), timed alone per launch
     tmp = torch.empty_like(f)
