@@ -37,10 +37,15 @@ __device__ __forceinline__ void put(unsigned short* r, size_t i, double v, long 
   r[i] = __builtin_bit_cast(unsigned short, h);
   if (plane) r[i + plane] = __builtin_bit_cast(unsigned short, (__bf16)(fv - (float)h));
 }
-// zero the pitch padding [nz, ldr) of one row (done by the row's last node)
+// zero the pitch padding [nz, ldr) of one row, spread over the row's nodes: node
+// l writes element l + (ldr - nz) when that lies in the padding; the last node
+// also writes the part of a padding wider than the row
 template <class TR>
-__device__ __forceinline__ void zero_pad(TR* r, size_t row0, int nz, int ldr, long plane) {
-  for (int e = nz; e < ldr; ++e) put(r, row0 + e, 0.0, plane);
+__device__ __forceinline__ void zero_pad(TR* r, size_t row0, int l, int nz, int ldr, long plane) {
+  const int npad = ldr - nz;
+  if (l + npad >= nz) put(r, row0 + l + npad, 0.0, plane);
+  if (l == nz - 1)
+    for (int e = nz; e < npad; ++e) put(r, row0 + e, 0.0, plane);
 }
 
 struct Coef {
@@ -86,7 +91,7 @@ __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restr
   const double fv = f ? f[idx] : 0.0;
   const size_t row0 = ((size_t)i * ny + j) * ldr;
   put(r, row0 + l, c.cf * fv - c.cd * dv - c.ch * s, rplane);
-  if (l == nz - 1) zero_pad(r, row0, nz, ldr, rplane);
+  zero_pad(r, row0, l, nz, ldr, rplane);
 }
 
 // Tiled march: a block (8 waves) owns a TY (y) x TZ (z) column of nodes and marches
@@ -221,7 +226,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       if (ok[q]) {
         const size_t row0 = ((size_t)i * ny + jr[q]) * ldr;
         put(r, row0 + l, c.cf * fc[q] - c.cd * dc[q] - c.ch * s, rplane);
-        if (l == nz - 1) zero_pad(r, row0, nz, ldr, rplane);
+        zero_pad(r, row0, l, nz, ldr, rplane);
       }
 #pragma unroll
       for (int d = 0; d + 1 < BW; ++d) w[q][d] = w[q][d + 1];
