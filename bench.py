@@ -96,6 +96,25 @@ def bench_batch(args, P, torch, dev, log):
     return res
 
 
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of the
+# current kernels at n = 999, scaled by a streaming kernel of known traffic
+# (FETCH x 1.970, WRITE x 1.000); recorded here because counters cannot be read
+# inside the timed run.  Variants without such runs report null.
+PROFILED_TRAFFIC = {
+    # one split-BF16 FD application (conversion + six passes, sem_solve_lowp)
+    "bf16x3": {"fetch_bytes": 49.21e9, "write_bytes": 36.23e9,
+               "algorithmic_bytes": 65.0e9, "source": "profiles/split_bf16_refined_n999.md"},
+    # one FP64 y-axis mode product (mode_nn_f64)
+    "f64": {"fetch_bytes": 38.6e9, "write_bytes": 8.23e9,
+            "algorithmic_bytes": 15.97e9, "source": "profiles/mode_f64_n999.md"},
+}
+
+
+def _traffic(name):
+    t = PROFILED_TRAFFIC.get(name)
+    return None if t is None else t["fetch_bytes"] + t["write_bytes"]
+
+
 def bench_ch(args, P, torch, dev, log):
     """Cahn-Hilliard IMEX stepping on [0, 2pi]^3, Neumann, Q^4, 64^3 elements
     (n = 257), eps = 0.05, m = 0.02, dt = 1e-4, phi_0 ~ U[-0.05, 0.05] (seed 2312);
@@ -255,7 +274,8 @@ def main() -> int:
         ach = fd_flops / (fd_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": f"{prec} FD application: six mode_rot passes "
                                            f"({'mode_rot_dma' if prec != 'f32' else 'mode_rot_f32'})",
-                "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": _traffic(prec), "traffic_detail": PROFILED_TRAFFIC.get(prec),
                 "launch_ms": fd_ms, "flops_per_launch": fd_flops,
                 "mfma_work_factor": 3 if prec == "bf16x3" else 1}
         v["fd_application"] = roof
@@ -306,7 +326,8 @@ def main() -> int:
         "plan_seconds": plan_s,
         "roofline_f64": {"bound": "mfma", "kernel": "mode_nn_f64 (y-axis mode product)",
                          "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                         "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                         "frac": achieved / PEAK_FP64_TFLOPS, "traffic": _traffic("f64"),
+                         "traffic_detail": PROFILED_TRAFFIC["f64"],
                          "launch_ms": launch_ms, "flops_per_launch": flops_launch},
     }
     out["roofline"] = lowp_roof if lowp_roof is not None else out["roofline_f64"]
