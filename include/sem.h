@@ -155,7 +155,15 @@ sem_status sem_batch_tile_rows(const sem_batch *b, int rows[6]);
  *           of the six mode products of an iteration is one persistent launch per
  *           tile shape over all still-unconverged problems, each residual one
  *           launch per k.  One synchronisation per iteration (norm read-back).
+ *  SEM_BF16X3: as SEM_F32, except that every problem whose three dimensions are
+ *           all >= 160 runs its iterations with the split-BF16 mode products of
+ *           sem_solve_refined (one launch per pass, on the batch stream, after
+ *           the persistent launches of the other problems); all problems refine
+ *           in FP64 to the same tol.
  *  SEM_F64: one FP64 sem_solve per problem on the batch stream.
+ * Every call (re)lays out each plan's low-precision workspace for the chosen
+ * precision, so plans may be used by other calls between batch solves; the call
+ * first waits for the batch stream.
  * iters (host array of count, may be NULL) receives the iterations per problem.
  * Returns SEM_ENONFINITE if a problem produced a non-finite update, else
  * SEM_ENOCONV if a problem stopped without meeting tol (diverging, or max_iter). */

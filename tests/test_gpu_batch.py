@@ -1,5 +1,6 @@
 """GPU parity of batched solves (persistent FP32 launches over many problems of
-different sizes, FP64 refinement) against the FP64 oracle, per problem.
+different sizes, FP64 refinement; split-BF16 passes for the problems whose every
+dimension is >= 160 in SEM_BF16X3 batches) against the FP64 oracle, per problem.
 
 Bar: ||u_i - u_oracle,i||_inf <= 1e-10 ||u_oracle,i||_inf + 10 x the oracle's own
 rounding floor, for every problem of the batch.
@@ -50,7 +51,7 @@ def _run(torch, P, specs, seed, prec="f32", tol=1e-12, repeat=1):
     plans = [P.Plan(s["k"], s["ne"], s.get("box", BOX), s["alpha"], s.get("bc", "dirichlet")) for s in specs]
     batch = P.Batch(plans)
     rows = batch.tile_rows()
-    assert all(r in (0, 32, 64, 128) for r in rows), rows
+    assert all(r in (0, 32, 64, 96, 128) for r in rows), rows
     worst = 0.0
     for rep in range(repeat):
         fs = [batch_rhs(p.shape, seed + rep, i) for i, p in enumerate(plans)]
@@ -111,6 +112,71 @@ def test_batch_c4_recipe_reduced_elements(torch, P):
     _log(f"[batch]   tile rows {rows}, max iterations {max(its)}, worst rel err {worst:.2e}")
 
 
+# three problems with every dimension >= 160 (split BF16 in a SEM_BF16X3 batch), one
+# just below (FP32), small ones (FP32)
+SPLIT_SPECS = [
+    {"k": 5, "ne": (33, 34, 35), "alpha": 1.0},                   # 164 x 169 x 174
+    {"k": 4, "ne": (40, 42, 40), "alpha": 0.5, "bc": "neumann"},  # 161 x 169 x 161
+    {"k": 8, "ne": (21, 20, 24), "alpha": 0.0},                   # 167 x 159 x 191: FP32
+    {"k": 3, "ne": (5, 7, 2), "alpha": 0.5},
+    {"k": 8, "ne": (2, 1, 3), "alpha": 3.0},
+    {"k": 2, "ne": (90, 81, 85), "alpha": 4.0},                   # 179 x 161 x 169
+]
+SPLIT_MASK = [True, True, False, False, False, True]
+
+
+def test_batch_split_bf16_mixed(torch, P):
+    _log("[batch] split-BF16 batch: 3 large problems + 3 FP32 ones, two right-hand sides")
+    rows, its, worst = _run(torch, P, SPLIT_SPECS, 17, prec="bf16x3", repeat=2)
+    _log(f"[batch]   iterations {its}, worst rel err {worst:.2e}")
+
+
+def test_batch_split_bf16_paths(torch, P):
+    """One iteration without refinement (tol 0): the FP32 problems of a SEM_BF16X3
+    batch give exactly the FP32 batch's result, the large ones a different
+    (split-BF16) result within the unrefined split-BF16 error."""
+    plans = [P.Plan(s["k"], s["ne"], BOX, s["alpha"], s.get("bc", "dirichlet")) for s in SPLIT_SPECS]
+    batch = P.Batch(plans)
+    fs = [batch_rhs(p.shape, 23, i) for i, p in enumerate(plans)]
+    fd = [_dev(torch, f) for f in fs]
+    u32 = [torch.empty_like(f) for f in fd]
+    usp = [torch.empty_like(f) for f in fd]
+    its, st = batch.solve(fd, u32, prec="f32", tol=0.0, max_iter=1)
+    assert st == 0 and its == [1] * len(plans)
+    its, st = batch.solve(fd, usp, prec="bf16x3", tol=0.0, max_iter=1)
+    assert st == 0 and its == [1] * len(plans)
+    for i, (s, split) in enumerate(zip(SPLIT_SPECS, SPLIT_MASK)):
+        same = torch.equal(u32[i], usp[i])
+        assert same != split, (i, s)
+        if split:
+            prob = O.Problem(s["k"], s["ne"], BOX, s["alpha"], s.get("bc", "dirichlet"))
+            ref = O.fd_solve(prob, fs[i])
+            rel = np.max(np.abs(usp[i].cpu().numpy() - ref)) / np.max(np.abs(ref))
+            _log(f"[batch]   problem {i}: one split-BF16 solve, rel err {rel:.2e}")
+            assert 1e-13 < rel <= 1e-4, (i, rel)
+
+
+def test_batch_after_other_uses_of_its_plans(torch, P):
+    """A plan's workspace may move between batch solves (here: a single split-BF16
+    solve of one of the plans needs a larger one); the next batch solve must use
+    the moved workspace."""
+    specs = [{"k": 3, "ne": (5, 4, 5), "alpha": 1.0}, {"k": 4, "ne": (3, 6, 2), "alpha": 0.3}]
+    plans = [P.Plan(s["k"], s["ne"], BOX, s["alpha"]) for s in specs]
+    batch = P.Batch(plans)
+    fs = [batch_rhs(p.shape, 29, i) for i, p in enumerate(plans)]
+    fd = [_dev(torch, f) for f in fs]
+    for rep in range(2):
+        ud = [torch.empty_like(f) for f in fd]
+        its, st = batch.solve(fd, ud, prec="f32", tol=1e-12)
+        assert st == 0
+        for i, s in enumerate(specs):
+            ok, rel = _check(O.Problem(s["k"], s["ne"], BOX, s["alpha"], "dirichlet"), fs[i], ud[i].cpu().numpy())
+            assert ok, (rep, i, rel)
+        if rep == 0:
+            u1, _, _, st1 = plans[0].solve_refined(fd[0], prec="bf16x3", tol=1e-12)
+            assert st1 == 0
+
+
 def test_batch_rejects_invalid(torch, P):
     plan = P.Plan(4, (2, 2, 2), BOX, 1.0)
     with pytest.raises(P.SemError):
@@ -140,10 +206,11 @@ class _Lines:
 
 def test_batch_full_size_sampled(torch, P):
     """The batched workload at its full size (256 problems, 8..64 elements per
-    axis, ~2.3e9 unknowns) in the launch configuration the benchmark times:
-    every problem's nodal residual at 8 seeded nodes, recomputed by the oracle, is
-    within a 1e-10 normwise backward error; the two smallest problems are compared
-    with full oracle solves."""
+    axis, ~2.3e9 unknowns) in the launch configurations the benchmark times (the
+    FP32 batch and the SEM_BF16X3 batch, whose problems with every dimension
+    >= 160 run split BF16): every problem's nodal residual at 8 seeded nodes,
+    recomputed by the oracle, is within a 1e-10 normwise backward error; the two
+    smallest problems are compared with full oracle solves."""
     from concurrent.futures import ThreadPoolExecutor
     specs = batch_draws(256, 2311)
     plans = [P.Plan(s["k"], s["ne"], BOX, s["alpha"], "dirichlet") for s in specs]
@@ -151,23 +218,25 @@ def test_batch_full_size_sampled(torch, P):
     with ThreadPoolExecutor(16) as ex:
         hosts = list(ex.map(lambda ip: batch_rhs(ip[1].shape, 2311, ip[0]), enumerate(plans)))
     fd = [_dev(torch, h) for h in hosts]
-    ud = [torch.empty_like(f) for f in fd]
-    its, st = batch.solve(fd, ud, prec="f32", tol=1e-10, max_iter=40)
-    assert st == 0 and max(its) <= 40
-    _log(f"[batch] full size: {sum(p.numel for p in plans)} unknowns, iterations {min(its)}..{max(its)}")
-    rng = np.random.default_rng(7)
-    worst = 0.0
-    for i, (s, p) in enumerate(zip(specs, plans)):
-        prob = O.Problem(s["k"], s["ne"], BOX, s["alpha"], "dirichlet", eigen=False)
-        idx = np.stack([rng.integers(0, n, size=8) for n in p.shape], axis=1)
-        r = O.residual_at(prob, _Lines(ud[i]), hosts[i], idx)
-        hnorm = s["alpha"] + sum(np.max(np.sum(np.abs(prob.h_dense(a)), axis=1)) for a in range(3))
-        scale = np.max(np.abs(hosts[i])) + hnorm * float(ud[i].abs().max())
-        worst = max(worst, float(np.max(np.abs(r))) / scale)
-    _log(f"[batch]   worst sampled backward error {worst:.2e}")
-    assert worst <= 1e-10
-    for i in sorted(range(len(plans)), key=lambda j: plans[j].numel)[:2]:
-        s = specs[i]
-        prob = O.Problem(s["k"], s["ne"], BOX, s["alpha"], "dirichlet")
-        ok, rel = _check(prob, hosts[i], ud[i].cpu().numpy())
-        assert ok, (i, rel)
+    for prec in ("f32", "bf16x3"):
+        ud = [torch.empty_like(f) for f in fd]
+        its, st = batch.solve(fd, ud, prec=prec, tol=1e-10, max_iter=40)
+        assert st == 0 and max(its) <= 40
+        _log(f"[batch] full size {prec}: {sum(p.numel for p in plans)} unknowns, iterations {min(its)}..{max(its)}")
+        rng = np.random.default_rng(7)
+        worst = 0.0
+        for i, (s, p) in enumerate(zip(specs, plans)):
+            prob = O.Problem(s["k"], s["ne"], BOX, s["alpha"], "dirichlet", eigen=False)
+            idx = np.stack([rng.integers(0, n, size=8) for n in p.shape], axis=1)
+            r = O.residual_at(prob, _Lines(ud[i]), hosts[i], idx)
+            hnorm = s["alpha"] + sum(np.max(np.sum(np.abs(prob.h_dense(a)), axis=1)) for a in range(3))
+            scale = np.max(np.abs(hosts[i])) + hnorm * float(ud[i].abs().max())
+            worst = max(worst, float(np.max(np.abs(r))) / scale)
+        _log(f"[batch]   worst sampled backward error {worst:.2e}")
+        assert worst <= 1e-10
+        for i in sorted(range(len(plans)), key=lambda j: plans[j].numel)[:2]:
+            s = specs[i]
+            prob = O.Problem(s["k"], s["ne"], BOX, s["alpha"], "dirichlet")
+            ok, rel = _check(prob, hosts[i], ud[i].cpu().numpy())
+            assert ok, (prec, i, rel)
+        del ud
