@@ -14,6 +14,7 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   gll, diff_matrix, element_matrices, axis_operators, axis_eigen   pinned
   fd_solve, apply_h3, residual, residual_at, dense_system          pinned
   ch_step                                                          pinned
+  schrodinger_apply, pcg_schrodinger                               pinned
 """
 from .sem_oracle import (  # noqa: F401
     gll,
@@ -32,5 +33,7 @@ from .sem_oracle import (  # noqa: F401
     dense_solve,
     ch_step,
     ch_operator_residual,
+    schrodinger_apply,
+    pcg_schrodinger,
     rel_max_err,
 )

@@ -250,7 +250,7 @@ def mode_product(x, mat, axis: int, out=None):
     raise ValueError(axis)
 
 
-def fd_solve(prob: Problem, f: np.ndarray, order=(2, 1, 0)) -> np.ndarray:
+def fd_solve(prob: Problem, f: np.ndarray, order=(2, 1, 0), alpha=None) -> np.ndarray:
     """Fast-diagonalisation solve of eq. (3D-Poisson) with the alpha shift.
 
     u = (S_x (x) S_y (x) S_z) [ (F_x (x) F_y (x) F_z) f ] ./ (Lambda3D + alpha),
@@ -258,7 +258,9 @@ def fd_solve(prob: Problem, f: np.ndarray, order=(2, 1, 0)) -> np.ndarray:
     forward, then the entrywise divide (Appendix Poisson3D adds alpha), then z, y,
     x backward.  The Kronecker factors act on different axes and commute, so any
     `order` gives the same result in exact arithmetic; a second order measures the
-    FP64 rounding floor of the solve itself.
+    FP64 rounding floor of the solve itself.  `alpha` (default prob.alpha)
+    replaces the shift, as the preconditioner of the variable-coefficient
+    problem needs.
     """
     f = np.ascontiguousarray(f, dtype=np.float64)
     lams = [e[0] for e in prob.eig]
@@ -268,7 +270,8 @@ def fd_solve(prob: Problem, f: np.ndarray, order=(2, 1, 0)) -> np.ndarray:
     for a in order:
         mode_product(src, prob.eig[a][2], a, out=dst)
         src, dst = dst, (buf2 if dst is buf1 else buf1)
-    src /= (lams[0][:, None, None] + lams[1][None, :, None] + lams[2][None, None, :] + prob.alpha)
+    shift = prob.alpha if alpha is None else float(alpha)
+    src /= (lams[0][:, None, None] + lams[1][None, :, None] + lams[2][None, None, :] + shift)
     for a in order:
         mode_product(src, prob.eig[a][1], a, out=dst)
         src, dst = dst, (buf2 if dst is buf1 else buf1)
@@ -362,6 +365,57 @@ def ch_operator_residual(prob: Problem, phi_np1, phi_n, phi_nm1, eps, mob, dt):
     lhs = a * phi_np1 + mob * dt * eps * apply_h3(prob, apply_h3(prob, phi_np1))
     rhs = phi_hat - (mob * dt / eps) * apply_h3(prob, g)
     return lhs - rhs
+
+
+# ---------------------------------------------------------------------------
+# Variable coefficients: alpha u - Lap u + V(x) u = f by PCG (the paper's
+# Schrodinger-equation section, eq. shrodinger)
+# ---------------------------------------------------------------------------
+
+
+def schrodinger_apply(prob: Problem, v: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """A u = alpha u + H_3 u + V u: the GLL-quadrature weak form
+    alpha M_3 u + K_3 u + M_3 V u = M_3 f divided by the diagonal M_3 (nodal form,
+    as eq. matvec3D in H-form), with the potential V given at the nodes."""
+    return prob.alpha * u + apply_h3(prob, u) + v * u
+
+
+def pcg_schrodinger(prob: Problem, v: np.ndarray, f: np.ndarray, shift: float, tol: float = 1e-12,
+                    max_iter: int = 500):
+    """Preconditioned conjugate gradients for A u = f (schrodinger_apply) with
+    the fast-diagonalisation solve of (shift I + H_3) as preconditioner; the
+    paper takes shift = alpha + beta/2 for 0 <= V <= beta.  A and the
+    preconditioner are self-adjoint and positive in the M_3-weighted inner
+    product <a, b> = sum M_3 a b, which the iteration uses throughout (the same
+    iterates as plain PCG on the symmetric weak form).  Starts from u = 0 and
+    stops when ||r||_M <= tol ||f||_M.  Returns (u, iterations, [||r_k||_M / ||f||_M])."""
+    m3 = prob.mass3()
+
+    def dot(a, b):
+        return float(np.sum(m3 * a * b))
+
+    u = np.zeros_like(f)
+    r = np.array(f, dtype=np.float64, copy=True)
+    fn = math.sqrt(dot(f, f))
+    hist = []
+    if fn == 0.0:
+        return u, 0, hist
+    z = fd_solve(prob, r, alpha=shift)
+    p = z.copy()
+    rz = dot(r, z)
+    for it in range(1, max_iter + 1):
+        q = schrodinger_apply(prob, v, p)
+        a = rz / dot(p, q)
+        u += a * p
+        r -= a * q
+        hist.append(math.sqrt(dot(r, r)) / fn)
+        if hist[-1] <= tol:
+            return u, it, hist
+        z = fd_solve(prob, r, alpha=shift)
+        rz_new = dot(r, z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return u, max_iter, hist
 
 
 def rel_max_err(a, b) -> float:

@@ -11,6 +11,11 @@ Workloads (paper: Liu, Shen & Zhang, arXiv 2310.00226):
   * "uD"      Dirichlet test solution of Sec. 3.1 (Table 1)
   * "uN"      Neumann test solution of Sec. 3.1 (Table 1) / Appendix script
 The right-hand side is f = alpha*u - Laplacian(u), evaluated exactly.
+  * Schrodinger-type problem of the paper's variable-coefficient section
+    (eq. beta): alpha u - Laplacian(u) + V u = f on [-16, 16]^3 with
+    V = beta sin^2(pi x/4) sin^2(pi y/4) sin^2(pi z/4) and exact solution
+    cos(pi x/16) cos(pi y/16) cos(pi z/16) (which satisfies homogeneous Neumann
+    conditions on that box).
 """
 from __future__ import annotations
 
@@ -65,6 +70,24 @@ def manufactured(kind: str, x, y, z, alpha: float):
         f = alpha * u + 14.0 * pi * pi * t1 - lap2
         return u, f
     raise ValueError(f"unknown manufactured solution {kind!r}")
+
+
+SCHRODINGER_BOX = (-16.0, 16.0, -16.0, 16.0, -16.0, 16.0)
+
+
+def schrodinger_data(x, y, z, alpha: float, beta: float):
+    """(V, u_exact, f) of the Schrodinger-type test problem on the tensor grid
+    x * y * z: V from eq. (beta), u = cos(pi x/16) cos(pi y/16) cos(pi z/16) and
+    f = (alpha + 3 (pi/16)^2 + V) u, since -Laplacian(u) = 3 (pi/16)^2 u."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    s2 = [np.sin(math.pi * t / 4.0) ** 2 for t in (x, y, z)]
+    c = [np.cos(math.pi * t / 16.0) for t in (x, y, z)]
+    v = beta * _outer3(*s2)
+    u = _outer3(*c)
+    f = (alpha + 3.0 * (math.pi / 16.0) ** 2 + v) * u
+    return v, u, f
 
 
 def normal_noise(shape, seed: int, scale: float = 1.0, chunks: int = 16) -> np.ndarray:
