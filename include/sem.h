@@ -131,6 +131,35 @@ sem_status sem_solve_refined(sem_plan *p, sem_prec prec, double tol, int max_ite
  * the first refinement iteration); u must not alias f.  Asynchronous. */
 sem_status sem_solve_lowp(sem_plan *p, sem_prec prec, const double *f, double *u);
 
+/* ---- variable coefficients (PCG) ---------------------------------------------- */
+
+/* Bytes of the caller-provided workspace of sem_pcg_solve: four FP64 arrays of N
+ * (r, z, p, q) and the partial sums of the inner products. */
+sem_status sem_pcg_workspace_bytes(const sem_plan *p, size_t *bytes);
+
+/* alpha u - Lap u + V u = f (the paper's Schrodinger-equation section, eq.
+ * shrodinger; alpha = the plan's alpha, V >= 0 given at the nodes) by
+ * preconditioned conjugate gradients with the fast-diagonalisation solve of
+ * (shift I - Lap) as the preconditioner (eq. 3D-Poisson with alpha := shift; the
+ * paper takes shift = alpha + beta/2 for 0 <= V <= beta).  The operator is the
+ * GLL-quadrature weak form divided by the lumped mass, A u = alpha u + H_3 u + V u,
+ * applied matrix-free in FP64; the inner products are M_3-weighted.  Starts from
+ * u = 0 and stops when ||f - A u||_M <= tol ||f||_M.
+ *  v, f, u: device FP64 arrays of N nodal values (u must not alias f or v);
+ *  prec: precision of the preconditioner's mode products (SEM_F64, or SEM_F32 /
+ *        SEM_BF16 / SEM_BF16X3, then with the flexible Polak-Ribiere update; the
+ *        operator, the update and the inner products stay FP64);
+ *  work: device buffer of sem_pcg_workspace_bytes bytes, 256-byte aligned.
+ *        The preconditioner also uses the plan workspace.
+ *  iters / relres (may be NULL): iterations and final ||r||_M / ||f||_M.
+ * Synchronises with the plan stream once per inner product (three per iteration).
+ * SEM_EINVAL: null pointers, aliasing, shift <= 0, tol < 0, max_iter < 1, small
+ * or misaligned workspace.  SEM_ENOCONV: tol not met within max_iter, or a
+ * non-positive curvature (V too negative: A not positive definite).
+ * SEM_ENONFINITE: NaN / Inf in f or in an iterate. */
+sem_status sem_pcg_solve(sem_plan *p, const double *v, double shift, sem_prec prec, double tol, int max_iter,
+                         const double *f, double *u, void *work, size_t work_bytes, int *iters, double *relres);
+
 /* ---- batched solves ---------------------------------------------------------- */
 
 typedef struct sem_batch sem_batch;

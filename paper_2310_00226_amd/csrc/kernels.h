@@ -122,6 +122,8 @@ struct ResidualArgs {
   const double* v = nullptr;
   const double* f = nullptr;
   const double* d = nullptr;
+  const double* wt = nullptr;  // optional per-node weight of the d term: cd * (wa + wt) * (d or v)
+  double wa = 0.0;
   void* r = nullptr;
   int r_kind = 0;
   int ldr = 0;
@@ -138,6 +140,8 @@ struct ResDesc {
   const double* v = nullptr;
   const double* f = nullptr;
   const double* d = nullptr;
+  const double* wt = nullptr;
+  double wa = 0.0;
   void* r = nullptr;
   const double* hx = nullptr;
   const double* hy = nullptr;

@@ -1,0 +1,282 @@
+// Variable coefficients: alpha u - Lap u + V(x) u = f (the paper's Schrodinger-
+// equation section, eq. shrodinger) by preconditioned conjugate gradients with
+// the fast-diagonalisation solve of (shift I - Lap) as the preconditioner; the
+// paper takes shift = alpha + beta/2 for 0 <= V <= beta.
+//
+// Discrete form (GLL quadrature, nodal): A u = alpha u + H_3 u + V u = f, with
+// H_3 = M_3^{-1} K_3.  A and P = shift I + H_3 are self-adjoint and positive in
+// the M_3-weighted inner product <a, b> = sum M_3 a b, which the iteration uses
+// throughout (the iterates of plain PCG on the symmetric weak form).
+//
+// One iteration on the GPU: q = A p (the matrix-free residual kernel with the
+// per-node weight alpha + V), <p, q>; u += a p and r -= a q fused with <r, r>;
+// z = P^{-1} r (an FP64 FD solve, or a low-precision one); <r, z> (and <z, q>);
+// p = z + b p.  The weighted inner products are two-stage block reductions
+// (fixed block count, partial sums added in a fixed order: deterministic); the
+// mass weight of node (i, j, l) is Mx_i My_j Mz_l from the three 1D masses.
+//
+// With a low-precision preconditioner the operator P^{-1} varies slightly from
+// one application to the next, so b uses the flexible (Polak-Ribiere) form
+// <z_new, r_new - r_old> / <z_old, r_old> = -a <z_new, q> / <z_old, r_old>,
+// which equals the classical <z_new, r_new> / <z_old, r_old> for a fixed
+// preconditioner; the FP64 preconditioner uses the classical form.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "kernels.h"
+#include "plan_internal.h"
+
+namespace semfd {
+namespace {
+
+constexpr int DOT_BLOCKS = 1024, DOT_THREADS = 256, MAXDOT = 2;
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < DOT_THREADS / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+// Partial sums of NDOT weighted products <a_d, b_d> per block, rows (i, j) strided
+// over the blocks, the z line of a row over the threads.
+template <int NDOT>
+__global__ __launch_bounds__(DOT_THREADS) void mdot_partial(const double* __restrict__ a0,
+                                                            const double* __restrict__ b0,
+                                                            const double* __restrict__ a1,
+                                                            const double* __restrict__ b1,
+                                                            const double* __restrict__ mx,
+                                                            const double* __restrict__ my,
+                                                            const double* __restrict__ mz, int nx, int ny, int nz,
+                                                            double* __restrict__ partial) {
+  __shared__ double sh[DOT_THREADS / 64];
+  double s0 = 0.0, s1 = 0.0;
+  const long rows = (long)nx * ny;
+  for (long row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int i = (int)(row / ny), j = (int)(row - (long)i * ny);
+    const double mr = mx[i] * my[j];
+    const size_t base = (size_t)row * nz;
+    for (int l = threadIdx.x; l < nz; l += DOT_THREADS) {
+      const double m = mr * mz[l];
+      s0 += m * a0[base + l] * b0[base + l];
+      if (NDOT > 1) s1 += m * a1[base + l] * b1[base + l];
+    }
+  }
+  const double t0 = block_sum(s0, sh);
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXDOT] = t0;
+  if (NDOT > 1) {
+    const double t1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXDOT + 1] = t1;
+  }
+}
+
+// u += a p, r -= a q, and the partial sums of <r, r> (new r).
+__global__ __launch_bounds__(DOT_THREADS) void pcg_update(double* __restrict__ u, double* __restrict__ r,
+                                                          const double* __restrict__ p,
+                                                          const double* __restrict__ q, double a,
+                                                          const double* __restrict__ mx,
+                                                          const double* __restrict__ my,
+                                                          const double* __restrict__ mz, int nx, int ny, int nz,
+                                                          double* __restrict__ partial) {
+  __shared__ double sh[DOT_THREADS / 64];
+  double s = 0.0;
+  const long rows = (long)nx * ny;
+  for (long row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int i = (int)(row / ny), j = (int)(row - (long)i * ny);
+    const double mr = mx[i] * my[j];
+    const size_t base = (size_t)row * nz;
+    for (int l = threadIdx.x; l < nz; l += DOT_THREADS) {
+      const size_t g = base + l;
+      u[g] += a * p[g];
+      const double rn = r[g] - a * q[g];
+      r[g] = rn;
+      s += mr * mz[l] * rn * rn;
+    }
+  }
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXDOT] = t;
+}
+
+// Fixed-order sum of the block partials: out[d] = sum_b partial[b][d].
+__global__ __launch_bounds__(DOT_THREADS) void mdot_final(const double* __restrict__ partial, int nblocks, int ndot,
+                                                          double* __restrict__ out) {
+  __shared__ double sh[DOT_THREADS / 64];
+  for (int d = 0; d < ndot; ++d) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += DOT_THREADS) s += partial[(size_t)b * MAXDOT + d];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) out[d] = t;
+  }
+}
+
+// p = z + b p
+__global__ __launch_bounds__(256) void pcg_direction(double* __restrict__ p, const double* __restrict__ z, double b,
+                                                     size_t n) {
+  for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (size_t)gridDim.x * blockDim.x)
+    p[g] = z[g] + b * p[g];
+}
+
+struct PcgWork {
+  double *r, *z, *p, *q, *partial, *out;
+};
+
+size_t pcg_need(const sem_plan* p) {
+  return 4 * align256(p->N * sizeof(double)) + align256(DOT_BLOCKS * MAXDOT * sizeof(double)) + 256;
+}
+
+int dot_blocks(const sem_plan* p) {
+  const long rows = (long)p->dims[0] * p->dims[1];
+  return (int)(rows < DOT_BLOCKS ? rows : DOT_BLOCKS);
+}
+
+// <a0, b0> (and <a1, b1>) into host h[0..ndot)
+hipError_t mdot(sem_plan* p, const PcgWork& w, int ndot, const double* a0, const double* b0, const double* a1,
+                const double* b1, double* h) {
+  const int nb = dot_blocks(p);
+  if (ndot == 1)
+    mdot_partial<1><<<nb, DOT_THREADS, 0, p->stream>>>(a0, b0, a0, b0, p->d_mass[0], p->d_mass[1], p->d_mass[2],
+                                                       p->dims[0], p->dims[1], p->dims[2], w.partial);
+  else
+    mdot_partial<2><<<nb, DOT_THREADS, 0, p->stream>>>(a0, b0, a1, b1, p->d_mass[0], p->d_mass[1], p->d_mass[2],
+                                                       p->dims[0], p->dims[1], p->dims[2], w.partial);
+  mdot_final<<<1, DOT_THREADS, 0, p->stream>>>(w.partial, nb, ndot, w.out);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h, w.out, ndot * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  return e;
+}
+
+}  // namespace
+}  // namespace semfd
+
+using namespace semfd;
+
+extern "C" {
+
+sem_status sem_pcg_workspace_bytes(const sem_plan* p, size_t* bytes) {
+  if (!p || !bytes) return set_error(SEM_EINVAL, "sem_pcg_workspace_bytes: null argument");
+  *bytes = pcg_need(p);
+  return SEM_OK;
+}
+
+sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec prec, double tol, int max_iter,
+                         const double* f, double* u, void* work, size_t work_bytes, int* iters, double* relres) {
+  if (iters) *iters = 0;
+  if (relres) *relres = NAN;
+  if (!p || !v || !f || !u || !work) return set_error(SEM_EINVAL, "sem_pcg_solve: null argument");
+  if (u == f || u == v) return set_error(SEM_EINVAL, "sem_pcg_solve: u must not alias f or V");
+  if (!(shift > 0.0) || !std::isfinite(shift)) return set_error(SEM_EINVAL, "sem_pcg_solve: shift must be > 0");
+  if (!(tol >= 0.0) || !std::isfinite(tol) || max_iter < 1)
+    return set_error(SEM_EINVAL, "sem_pcg_solve: invalid tol or max_iter");
+  if (prec != SEM_F64 && prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3)
+    return set_error(SEM_EINVAL, "sem_pcg_solve: unknown precision");
+  if (work_bytes < pcg_need(p) || ((uintptr_t)work & 255))
+    return set_error(SEM_EINVAL, "sem_pcg_solve: workspace too small or not 256-byte aligned");
+  const size_t n = p->N;
+  const size_t vb = align256(n * sizeof(double));
+  char* wb = (char*)work;
+  PcgWork w{(double*)wb, (double*)(wb + vb), (double*)(wb + 2 * vb), (double*)(wb + 3 * vb),
+            (double*)(wb + 4 * vb), (double*)(wb + 4 * vb + align256(DOT_BLOCKS * MAXDOT * sizeof(double)))};
+
+  // preconditioner z = (shift I + H_3)^{-1} r
+  const Spectral sp{shift, 1.0, 0.0};
+  LpWork lw;
+  double* tmp64 = nullptr;
+  if (prec == SEM_F64) {
+    void* ws = nullptr;
+    sem_status st = plan_workspace(p, workspace_need(p, SEM_F64), &ws);
+    if (st != SEM_OK) return st;
+    tmp64 = (double*)ws;
+  } else {
+    sem_status st = lp_prepare(p, prec, &lw);
+    if (st != SEM_OK) return st;
+  }
+  auto precondition = [&]() -> hipError_t {
+    return prec == SEM_F64 ? fd64(p, sp, w.r, w.z, tmp64) : lp_fd(p, lw, sp, w.r, w.z, 1, nullptr);
+  };
+  // q = A p = (alpha + V) p + H_3 p
+  ResidualArgs ra;
+  ra.v = w.p;
+  ra.f = nullptr;
+  ra.wt = v;
+  ra.wa = p->alpha;
+  ra.r = w.q;
+  ra.r_kind = 0;
+  ra.ldr = p->dims[2];
+  ra.cf = 0.0;
+  ra.cd = -1.0;
+  ra.ch = -1.0;
+  const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
+  const int nb = dot_blocks(p);
+  const unsigned gdir = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+
+  hipError_t e;
+  double h[2];
+  // u = 0, r = f
+  if ((e = hipMemsetAsync(u, 0, n * sizeof(double), p->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(w.r, f, n * sizeof(double), hipMemcpyDeviceToDevice, p->stream)) != hipSuccess ||
+      (e = mdot(p, w, 1, f, f, nullptr, nullptr, h)) != hipSuccess)
+    return hip_fail(e, "sem_pcg_solve: start");
+  const double fn2 = h[0];
+  if (!std::isfinite(fn2)) return set_error(SEM_ENONFINITE, "sem_pcg_solve: non-finite right-hand side");
+  if (fn2 == 0.0) {
+    if (relres) *relres = 0.0;
+    return SEM_OK;
+  }
+  if ((e = precondition()) != hipSuccess || (e = mdot(p, w, 1, w.r, w.z, nullptr, nullptr, h)) != hipSuccess ||
+      (e = hipMemcpyAsync(w.p, w.z, n * sizeof(double), hipMemcpyDeviceToDevice, p->stream)) != hipSuccess)
+    return hip_fail(e, "sem_pcg_solve: first preconditioner application");
+  double rz = h[0];
+  double rel = 1.0;
+  for (int it = 1; it <= max_iter; ++it) {
+    if ((e = launch_residual(ra, hb, p->k, p->dims, p->stream)) != hipSuccess ||
+        (e = mdot(p, w, 1, w.p, w.q, nullptr, nullptr, h)) != hipSuccess)
+      return hip_fail(e, "sem_pcg_solve: operator");
+    const double pq = h[0];
+    if (!std::isfinite(pq) || !std::isfinite(rz)) return set_error(SEM_ENONFINITE, "sem_pcg_solve: non-finite iterate");
+    if (!(pq > 0.0) || !(rz > 0.0))
+      return set_error(SEM_ENOCONV, "sem_pcg_solve: operator or preconditioner not positive definite");
+    const double a = rz / pq;
+    pcg_update<<<nb, DOT_THREADS, 0, p->stream>>>(u, w.r, w.p, w.q, a, p->d_mass[0], p->d_mass[1], p->d_mass[2],
+                                                   p->dims[0], p->dims[1], p->dims[2], w.partial);
+    mdot_final<<<1, DOT_THREADS, 0, p->stream>>>(w.partial, nb, 1, w.out);
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipMemcpyAsync(h, w.out, sizeof(double), hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(p->stream)) != hipSuccess)
+      return hip_fail(e, "sem_pcg_solve: update");
+    rel = std::sqrt(h[0] / fn2);
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    if (!std::isfinite(rel)) return set_error(SEM_ENONFINITE, "sem_pcg_solve: non-finite residual");
+    if (rel <= tol) return SEM_OK;
+    if (it == max_iter) break;
+    if ((e = precondition()) != hipSuccess) return hip_fail(e, "sem_pcg_solve: preconditioner");
+    double b;
+    if (prec == SEM_F64) {
+      if ((e = mdot(p, w, 1, w.r, w.z, nullptr, nullptr, h)) != hipSuccess) return hip_fail(e, "sem_pcg_solve: dot");
+      b = h[0] / rz;
+      rz = h[0];
+    } else {
+      if ((e = mdot(p, w, 2, w.r, w.z, w.z, w.q, h)) != hipSuccess) return hip_fail(e, "sem_pcg_solve: dot");
+      b = -a * h[1] / rz;
+      rz = h[0];
+    }
+    pcg_direction<<<gdir, 256, 0, p->stream>>>(w.p, w.z, b, n);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sem_pcg_solve: direction");
+  }
+  if (tol > 0) return set_error(SEM_ENOCONV, "sem_pcg_solve: tolerance not met within max_iter");
+  return SEM_OK;
+}
+
+}  // extern "C"

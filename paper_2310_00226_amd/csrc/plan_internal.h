@@ -24,6 +24,7 @@ struct sem_plan {
   double* d_gb[3] = {nullptr, nullptr, nullptr};  // backward factor S, stored G[m][l] = S[l][m]
   double* d_lam[3] = {nullptr, nullptr, nullptr};
   double* d_hb[3] = {nullptr, nullptr, nullptr};  // banded rows of H = M^{-1} K
+  double* d_mass[3] = {nullptr, nullptr, nullptr};  // lumped 1D masses (inner products of PCG)
   // low-precision factors (created on first use): [axis][0 = forward, 1 = backward],
   // layout [l][k], zero-padded to lp_ld x lp_ld
   void* lp_f32[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};

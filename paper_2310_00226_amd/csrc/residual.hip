@@ -48,14 +48,16 @@ __device__ __forceinline__ void zero_pad(TR* r, size_t row0, int l, int nz, int 
     for (int e = nz; e < npad; ++e) put(r, row0 + e, 0.0, plane);
 }
 
+// r = cf f - cd (wa + wt) (d or v) - ch H_3 v  (weight 1 without wt)
 struct Coef {
-  double cf, cd, ch;
+  double cf, cd, ch, wa;
 };
 
 // Generic kernel (any k): one thread per node.
 template <class TR>
 __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restrict__ v, const double* __restrict__ f,
-                                                           const double* __restrict__ dg, TR* __restrict__ r, int ldr,
+                                                           const double* __restrict__ dg,
+                                                           const double* __restrict__ wt, TR* __restrict__ r, int ldr,
                                                            long rplane, const double* __restrict__ hx,
                                                            const double* __restrict__ hy,
                                                            const double* __restrict__ hz, int k, int nx, int ny,
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restr
     const int d1 = i + k >= nx ? k + (nx - 1 - i) : 2 * k;
     for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (long)(d - k) * plane];
   }
-  const double dv = dg ? dg[idx] : v[idx];
+  const double dv = (dg ? dg[idx] : v[idx]) * (wt ? c.wa + wt[idx] : 1.0);
   const double fv = f ? f[idx] : 0.0;
   const size_t row0 = ((size_t)i * ny + j) * ldr;
   put(r, row0 + l, c.cf * fv - c.cd * dv - c.ch * s, rplane);
@@ -118,7 +120,8 @@ struct TileGeo {
 // window (their band coefficients are zero as well).
 template <int KH, class TR>
 __device__ __forceinline__ void march_body(const double* __restrict__ v, const double* __restrict__ f,
-                                           const double* __restrict__ dg, TR* __restrict__ r, int ldr, long rplane,
+                                           const double* __restrict__ dg, const double* __restrict__ wt,
+                                           TR* __restrict__ r, int ldr, long rplane,
                                            const double* __restrict__ hx, const double* __restrict__ hy,
                                            const double* __restrict__ hz, int nx, int ny, int nz, int xchunk,
                                            const Coef& c, int bx, int by, int bz, double* __restrict__ lds) {
@@ -132,7 +135,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
   const int i0 = bz * xchunk;
   const int i1 = min(nx, i0 + xchunk);
   const long plane = (long)ny * nz;
-  const bool has_f = f != nullptr, has_d = dg != nullptr;  // uniform
+  const bool has_f = f != nullptr, has_d = dg != nullptr, has_w = wt != nullptr;  // uniform
   int jr[RW];
   bool ok[RW];
 #pragma unroll
@@ -177,7 +180,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       w[q][d] = in ? x : 0.0;
     }
   // prefetched operands of the current plane
-  double hv[G::NH], fv[RW], dv[RW], wn[RW];
+  double hv[G::NH], fv[RW], dv[RW], wv[RW], wn[RW];
   auto prefetch = [&](int i) {  // halo and f/d of plane i, window front v[i + KH]
     const int ic = i < nx ? i : nx - 1;
 #pragma unroll
@@ -193,6 +196,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       wn[q] = in ? x : 0.0;
       fv[q] = (has_f && ok[q]) ? f[at(ic, q)] : 0.0;
       dv[q] = (has_d && ok[q]) ? dg[at(ic, q)] : 0.0;
+      wv[q] = (has_w && ok[q]) ? c.wa + wt[at(ic, q)] : 1.0;
     }
   };
   if (i0 < i1) prefetch(i0);
@@ -207,7 +211,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
       fc[q] = fv[q];
-      dc[q] = has_d ? dv[q] : w[q][KH];
+      dc[q] = (has_d ? dv[q] : w[q][KH]) * wv[q];
     }
     __syncthreads();  // the plane-i tile is complete (and plane i-2's readers are done)
     prefetch(i + 1);  // halo, f, d of plane i + 1 and the window front v[i + 1 + KH]
@@ -238,14 +242,15 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
 template <int KH, class TR>
 __global__ __launch_bounds__(RT) void residual_march_kernel(const double* __restrict__ v,
                                                                   const double* __restrict__ f,
-                                                                  const double* __restrict__ dg, TR* __restrict__ r,
+                                                                  const double* __restrict__ dg,
+                                                                  const double* __restrict__ wt, TR* __restrict__ r,
                                                                   int ldr, long rplane,
                                                                   const double* __restrict__ hx,
                                                                   const double* __restrict__ hy,
                                                                   const double* __restrict__ hz, int nx, int ny,
                                                                   int nz, int xchunk, Coef c) {
   __shared__ double lds[2 * TileGeo<KH>::PLANE];
-  march_body<KH, TR>(v, f, dg, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, c, blockIdx.x, blockIdx.y,
+  march_body<KH, TR>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, c, blockIdx.x, blockIdx.y,
                      blockIdx.z, lds);
 }
 
@@ -268,8 +273,8 @@ __global__ __launch_bounds__(RT) void residual_march_batch(const ResDesc* __rest
   const int bx = (int)(rb % d.gx);
   const int by = (int)((rb / d.gx) % d.gy);
   const int bz = (int)(rb / ((long)d.gx * d.gy));
-  march_body<KH, TR>(d.v, d.f, d.d, (TR*)d.r, d.ldr, d.rplane, d.hx, d.hy, d.hz, d.nx, d.ny, d.nz, d.xchunk,
-                     Coef{d.cf, d.cd, d.ch}, bx, by, bz, lds);
+  march_body<KH, TR>(d.v, d.f, d.d, d.wt, (TR*)d.r, d.ldr, d.rplane, d.hx, d.hy, d.hz, d.nx, d.ny, d.nz, d.xchunk,
+                     Coef{d.cf, d.cd, d.ch, d.wa}, bx, by, bz, lds);
 }
 
 // x is split into chunks so that the grid fills the chip even for thin (y, z)
@@ -290,7 +295,7 @@ void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], cons
   int gx, gy, gz, xchunk;
   march_grid(dims, KH, &gx, &gy, &gz, &xchunk);
   residual_march_kernel<KH, TR><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
-      ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
+      ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
 }
 
 template <int KH>
@@ -310,7 +315,7 @@ hipError_t batch_typed(int r_kind, const ResDesc* descs, int nd, long total_bloc
 template <class TR>
 hipError_t launch_typed(const ResidualArgs& ra, TR* r, const double* const hb[3], int k, const int dims[3],
                         hipStream_t stream) {
-  const Coef c{ra.cf, ra.cd, ra.ch};
+  const Coef c{ra.cf, ra.cd, ra.ch, ra.wa};
   switch (k) {
     case 1: launch_march<1, TR>(ra, r, hb, dims, c, stream); break;
     case 2: launch_march<2, TR>(ra, r, hb, dims, c, stream); break;
@@ -323,7 +328,8 @@ hipError_t launch_typed(const ResidualArgs& ra, TR* r, const double* const hb[3]
     default: {
       const long plane = (long)dims[1] * dims[2];
       dim3 block(256), grid((unsigned)((plane + 255) / 256), (unsigned)dims[0]);
-      residual_any_kernel<TR><<<grid, block, 0, stream>>>(ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2],
+      residual_any_kernel<TR><<<grid, block, 0, stream>>>(ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1],
+                                                          hb[2],
                                                           k, dims[0], dims[1], dims[2], c);
     }
   }
@@ -363,6 +369,8 @@ bool residual_desc(const ResidualArgs& ra, const double* const hb[3], int k, con
   d->v = ra.v;
   d->f = ra.f;
   d->d = ra.d;
+  d->wt = ra.wt;
+  d->wa = ra.wa;
   d->r = ra.r;
   d->hx = hb[0];
   d->hy = hb[1];

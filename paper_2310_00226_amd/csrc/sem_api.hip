@@ -177,7 +177,8 @@ sem_status sem_plan_create(int k, const int ne[3], const double box[6], double a
     if ((e = upload_factor(p->ax[a].F, n, p->ld[a], &p->d_gf[a])) != hipSuccess ||
         (e = upload_factor(p->ax[a].S, n, p->ld[a], &p->d_gb[a])) != hipSuccess ||
         (e = upload_vec(p->ax[a].lam, &p->d_lam[a])) != hipSuccess ||
-        (e = upload_vec(p->ax[a].hband, &p->d_hb[a])) != hipSuccess) {
+        (e = upload_vec(p->ax[a].hband, &p->d_hb[a])) != hipSuccess ||
+        (e = upload_vec(p->ax[a].mass, &p->d_mass[a])) != hipSuccess) {
       sem_plan_destroy(p);
       return hip_fail(e, "sem_plan_create: factor upload");
     }
@@ -197,6 +198,7 @@ void sem_plan_destroy(sem_plan* p) {
     (void)hipFree(p->d_gb[a]);
     (void)hipFree(p->d_lam[a]);
     (void)hipFree(p->d_hb[a]);
+    (void)hipFree(p->d_mass[a]);
   }
   release_lowp(p);
   if (p->ws_owned) (void)hipFree(p->ws);
