@@ -111,6 +111,55 @@ def bench_batch(args, P, torch, dev, log):
     return res
 
 
+def bench_schrodinger(args, P, torch, dev, log):
+    """Variable coefficients (the paper's Schrodinger-equation section): alpha u -
+    Lap u + V u = f on [-16, 16]^3, homogeneous Neumann, Q^5 with args.schrodinger_ne^3
+    elements (200 -> n = 1001, 1.003e9 unknowns), alpha = 1, V from eq. (beta)
+    with beta = 1, f from the exact solution cos(pi x/16) cos(pi y/16) cos(pi z/16);
+    PCG with the FD solve of ((alpha + beta/2) I - Lap) as preconditioner, in FP64
+    and in split BF16, to ||r||_M <= 1e-12 ||f||_M."""
+    from workloads import SCHRODINGER_BOX, schrodinger_data
+    ne, alpha, beta = args.schrodinger_ne, 1.0, 1.0
+    t0 = time.perf_counter()
+    plan = P.Plan(5, (ne, ne, ne), SCHRODINGER_BOX, alpha, "neumann")
+    plan_s = time.perf_counter() - t0
+    v, ue, f = schrodinger_data(*(plan.nodes(a) for a in range(3)), alpha, beta)
+    vd, fd, ued = (torch.from_numpy(a).to(dev) for a in (v, f, ue))
+    del v, f, ue
+    n = plan.numel
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {"workload": f"alpha u - Lap u + V u = f, V = beta sin^2(pi x/4) sin^2(pi y/4) sin^2(pi z/4), "
+                       f"beta = {beta:g}, alpha = {alpha:g}, [-16,16]^3 Neumann, Q^5, {ne}^3 elements "
+                       f"(n={plan.shape[0]}), PCG with the FD preconditioner (shift alpha + beta/2), "
+                       f"tol 1e-12",
+           "unknowns": n, "plan_seconds": plan_s,
+           "paper_context": "Table tab5: 20.4 s on one A100 (MATLAB, FP64, periodic Q^5, 1000^3 DoFs, 10 iterations)",
+           "by_preconditioner": {}}
+    u = torch.empty_like(fd)
+    for prec in ("f64", "bf16x3"):
+        plan.pcg_solve(vd, fd, u, shift=alpha + beta / 2, prec=prec, tol=1e-12)  # warm-up
+        torch.cuda.synchronize()
+        e0.record(stream)
+        _, it, rel, st = plan.pcg_solve(vd, fd, u, shift=alpha + beta / 2, prec=prec, tol=1e-12,
+                                        raise_on_error=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        err = float((u - ued).abs().max())
+        log(f"schrodinger {prec} preconditioner: {ms:.1f} ms per solve, {it} iterations, "
+            f"rel residual {rel:.1e}, max error vs exact {err:.2e}, {n / (ms * 1e-3):.3e} unknowns/s")
+        res["by_preconditioner"][prec] = {"ms_per_solve": ms, "iterations": it, "rel_residual": rel,
+                                          "max_err_vs_exact": err, "unknowns_per_s": n / (ms * 1e-3),
+                                          "status": st}
+    ok = [p for p, r in res["by_preconditioner"].items() if r["status"] == 0]
+    best = min(ok, key=lambda p: res["by_preconditioner"][p]["ms_per_solve"], default="f64")
+    res.update({"preconditioner": best, **res["by_preconditioner"][best]})
+    del u, vd, fd, ued, plan
+    torch.cuda.empty_cache()
+    return res
+
+
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of the
 # current kernels at n = 999, scaled by a streaming kernel of known traffic
 # (FETCH x 1.970, WRITE x 1.000); recorded here because counters cannot be read
@@ -186,6 +235,8 @@ def main() -> int:
                     help="problems in the batched leg (k in 2..8, 8..64 elements per axis); 0 skips it")
     ap.add_argument("--ch-steps", type=int, default=1000,
                     help="Cahn-Hilliard steps at n = 257 (64^3 Q^4 elements); 0 skips the leg")
+    ap.add_argument("--schrodinger-ne", type=int, default=200,
+                    help="elements per axis of the variable-coefficient PCG leg (0 = skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain elementwise copy of f (N*8 bytes read + written) so that HBM "
                          "counters of the kernels can be scaled against a kernel of known traffic")
@@ -351,6 +402,8 @@ def main() -> int:
         out["batched"] = bench_batch(args, P, torch, dev, log)
     if args.ch_steps > 0:
         out["cahn_hilliard"] = bench_ch(args, P, torch, dev, log)
+    if args.schrodinger_ne > 0:
+        out["schrodinger_pcg"] = bench_schrodinger(args, P, torch, dev, log)
 
     if not args.no_cpu_baseline:
         import oracle as O

@@ -122,7 +122,9 @@ struct ResidualArgs {
   const double* v = nullptr;
   const double* f = nullptr;
   const double* d = nullptr;
-  const double* wt = nullptr;  // optional per-node weight of the d term: cd * (wa + wt) * (d or v)
+  // optional per-node weight of the d term, cd * (wa + wt) * (d or v); FP64 output
+  // (r_kind 0) of the single launch only
+  const double* wt = nullptr;
   double wa = 0.0;
   void* r = nullptr;
   int r_kind = 0;
@@ -140,8 +142,6 @@ struct ResDesc {
   const double* v = nullptr;
   const double* f = nullptr;
   const double* d = nullptr;
-  const double* wt = nullptr;
-  double wa = 0.0;
   void* r = nullptr;
   const double* hx = nullptr;
   const double* hy = nullptr;

@@ -33,7 +33,7 @@
 namespace semfd {
 namespace {
 
-constexpr int DOT_BLOCKS = 1024, DOT_THREADS = 256, MAXDOT = 2;
+constexpr int DOT_BLOCKS = 4096, DOT_THREADS = 256, MAXDOT = 2;
 
 inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 

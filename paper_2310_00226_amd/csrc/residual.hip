@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -118,7 +119,7 @@ struct TileGeo {
 // thread's register window of 2 KH + 1 planes, whose front is loaded from global
 // memory one plane ahead.  Out-of-domain values are zero in the tile and the
 // window (their band coefficients are zero as well).
-template <int KH, class TR>
+template <int KH, class TR, bool W>
 __device__ __forceinline__ void march_body(const double* __restrict__ v, const double* __restrict__ f,
                                            const double* __restrict__ dg, const double* __restrict__ wt,
                                            TR* __restrict__ r, int ldr, long rplane,
@@ -135,7 +136,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
   const int i0 = bz * xchunk;
   const int i1 = min(nx, i0 + xchunk);
   const long plane = (long)ny * nz;
-  const bool has_f = f != nullptr, has_d = dg != nullptr, has_w = wt != nullptr;  // uniform
+  const bool has_f = f != nullptr, has_d = dg != nullptr;  // uniform
   int jr[RW];
   bool ok[RW];
 #pragma unroll
@@ -180,7 +181,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       w[q][d] = in ? x : 0.0;
     }
   // prefetched operands of the current plane
-  double hv[G::NH], fv[RW], dv[RW], wv[RW], wn[RW];
+  double hv[G::NH], fv[RW], dv[RW], wv[W ? RW : 1], wn[RW];
   auto prefetch = [&](int i) {  // halo and f/d of plane i, window front v[i + KH]
     const int ic = i < nx ? i : nx - 1;
 #pragma unroll
@@ -196,7 +197,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       wn[q] = in ? x : 0.0;
       fv[q] = (has_f && ok[q]) ? f[at(ic, q)] : 0.0;
       dv[q] = (has_d && ok[q]) ? dg[at(ic, q)] : 0.0;
-      wv[q] = (has_w && ok[q]) ? c.wa + wt[at(ic, q)] : 1.0;
+      if constexpr (W) wv[q] = ok[q] ? c.wa + wt[at(ic, q)] : 1.0;
     }
   };
   if (i0 < i1) prefetch(i0);
@@ -211,7 +212,8 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
       fc[q] = fv[q];
-      dc[q] = (has_d ? dv[q] : w[q][KH]) * wv[q];
+      dc[q] = has_d ? dv[q] : w[q][KH];
+      if constexpr (W) dc[q] *= wv[q];
     }
     __syncthreads();  // the plane-i tile is complete (and plane i-2's readers are done)
     prefetch(i + 1);  // halo, f, d of plane i + 1 and the window front v[i + 1 + KH]
@@ -239,7 +241,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
   }
 }
 
-template <int KH, class TR>
+template <int KH, class TR, bool W>
 __global__ __launch_bounds__(RT) void residual_march_kernel(const double* __restrict__ v,
                                                                   const double* __restrict__ f,
                                                                   const double* __restrict__ dg,
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(RT) void residual_march_kernel(const double* __rest
                                                                   const double* __restrict__ hz, int nx, int ny,
                                                                   int nz, int xchunk, Coef c) {
   __shared__ double lds[2 * TileGeo<KH>::PLANE];
-  march_body<KH, TR>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, c, blockIdx.x, blockIdx.y,
+  march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, c, blockIdx.x, blockIdx.y,
                      blockIdx.z, lds);
 }
 
@@ -273,8 +275,9 @@ __global__ __launch_bounds__(RT) void residual_march_batch(const ResDesc* __rest
   const int bx = (int)(rb % d.gx);
   const int by = (int)((rb / d.gx) % d.gy);
   const int bz = (int)(rb / ((long)d.gx * d.gy));
-  march_body<KH, TR>(d.v, d.f, d.d, d.wt, (TR*)d.r, d.ldr, d.rplane, d.hx, d.hy, d.hz, d.nx, d.ny, d.nz, d.xchunk,
-                     Coef{d.cf, d.cd, d.ch, d.wa}, bx, by, bz, lds);
+  march_body<KH, TR, false>(d.v, d.f, d.d, nullptr, (TR*)d.r, d.ldr, d.rplane, d.hx, d.hy, d.hz, d.nx, d.ny, d.nz,
+                            d.xchunk,
+                     Coef{d.cf, d.cd, d.ch, 0.0}, bx, by, bz, lds);
 }
 
 // x is split into chunks so that the grid fills the chip even for thin (y, z)
@@ -294,8 +297,17 @@ void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], cons
                   hipStream_t stream) {
   int gx, gy, gz, xchunk;
   march_grid(dims, KH, &gx, &gy, &gz, &xchunk);
-  residual_march_kernel<KH, TR><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
-      ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
+  // the per-node weight (an FP64 operator application of the variable-coefficient
+  // solver) has its own instantiation, so that the others keep their registers
+  if constexpr (std::is_same<TR, double>::value) {
+    if (ra.wt) {
+      residual_march_kernel<KH, TR, true><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
+          ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
+      return;
+    }
+  }
+  residual_march_kernel<KH, TR, false><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
+      ra.v, ra.f, ra.d, nullptr, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
 }
 
 template <int KH>
@@ -343,6 +355,7 @@ hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], in
   const long plane = (long)dims[1] * dims[2];
   if (dims[0] <= 0 || plane <= 0) return hipSuccess;
   if (!ra.v || !ra.r || ra.ldr < dims[2] || k < 1) return hipErrorInvalidValue;
+  if (ra.wt && ra.r_kind != 0) return hipErrorInvalidValue;  // weights: FP64 output only
   // in-plane offsets are 32-bit; the grid's y and z extents are limited to 65535
   if ((dims[1] + RY - 1) / RY > 65535 || dims[0] > 65535 || plane > 0x7fffffffL) return hipErrorInvalidValue;
   switch (ra.r_kind) {
@@ -364,13 +377,12 @@ hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], in
 bool residual_desc(const ResidualArgs& ra, const double* const hb[3], int k, const int dims[3], ResDesc* d) {
   if (k < 1 || k > 8 || !ra.v || !ra.r || ra.ldr < dims[2] || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0)
     return false;
+  if (ra.wt) return false;  // the batched residual has no per-node weight
   if ((long)dims[1] * dims[2] > 0x7fffffffL) return false;
   if (ra.r_kind == 3 && ra.rplane <= 0) return false;
   d->v = ra.v;
   d->f = ra.f;
   d->d = ra.d;
-  d->wt = ra.wt;
-  d->wa = ra.wa;
   d->r = ra.r;
   d->hx = hb[0];
   d->hy = hb[1];
