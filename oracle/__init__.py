@@ -15,6 +15,7 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   fd_solve, apply_h3, residual, residual_at, dense_system          pinned
   ch_step                                                          pinned
   schrodinger_apply, pcg_schrodinger                               pinned
+  spectral_apply                                                   pinned
 """
 from .sem_oracle import (  # noqa: F401
     gll,
@@ -35,5 +36,6 @@ from .sem_oracle import (  # noqa: F401
     ch_operator_residual,
     schrodinger_apply,
     pcg_schrodinger,
+    spectral_apply,
     rel_max_err,
 )

@@ -368,6 +368,33 @@ def ch_operator_residual(prob: Problem, phi_np1, phi_n, phi_nm1, eps, mob, dt):
 
 
 # ---------------------------------------------------------------------------
+# Other spectral multipliers on the same transforms (Sec. 1's list of
+# applications: exponential time differencing and fractional powers)
+# ---------------------------------------------------------------------------
+
+
+def spectral_apply(prob: Problem, kind: str, a: float, param: float, f: np.ndarray) -> np.ndarray:
+    """u = S_3 g(Lambda3D + a) S_3^{-1} f = g(H_3 + a I) f with S_3^{-1} = S_3^T M_3 (the
+    transforms of eq. 3D-Poisson) and g(x) = exp(-param x) ("exp": the solution
+    operator of u_t = Lap u - a u over a time param) or x^(-param) ("power": the
+    fractional Helmholtz operator; param = 1 is the solve of eq. 3D-Poisson)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    lam = prob.lam3() + a
+    t = f
+    for ax in (2, 1, 0):
+        t = mode_product(t, prob.eig[ax][2], ax)
+    if kind == "exp":
+        t = t * np.exp(-param * lam)
+    elif kind == "power":
+        t = t * lam ** (-param)
+    else:
+        raise ValueError(kind)
+    for ax in (2, 1, 0):
+        t = mode_product(t, prob.eig[ax][1], ax)
+    return t
+
+
+# ---------------------------------------------------------------------------
 # Variable coefficients: alpha u - Lap u + V(x) u = f by PCG (the paper's
 # Schrodinger-equation section, eq. shrodinger)
 # ---------------------------------------------------------------------------
