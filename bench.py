@@ -364,6 +364,20 @@ def main() -> int:
     achieved = flops_launch / (launch_ms * 1e-3) / 1e12
     solve_tflops = fd_flops / (ms * 1e-3) / 1e12  # six mode products
     log(f"mode product (y, NN): {launch_ms:.3f} ms/launch, {achieved:.1f} TFLOP/s; solve {solve_tflops:.1f} TFLOP/s")
+    # other spectral multipliers on the same FP64 transforms (only the third
+    # forward product's epilogue differs from the solve)
+    spectral = {}
+    for kind, param in (("exp", 1e-3), ("power", 0.5)):
+        plan.apply_spectral(kind, alpha, param, f, tmp)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.kernel_reps):
+            plan.apply_spectral(kind, alpha, param, f, tmp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        spectral[f"{kind}_ms"] = e0.elapsed_time(e1) / args.kernel_reps
+    log(f"spectral multipliers (FP64): exp(-1e-3 (L + alpha)) {spectral['exp_ms']:.1f} ms, "
+        f"(L + alpha)^-0.5 {spectral['power_ms']:.1f} ms per application")
     if args.calib_copy:
         tmp.copy_(f)           # device-to-device copy: reads and writes N * 8 bytes
         torch.neg(f, out=tmp)  # elementwise kernel with the same traffic
@@ -389,6 +403,8 @@ def main() -> int:
                                f"n={nx} per axis ({N} unknowns), FP64 fast-diagonalisation solve",
                    "k": k, "elements_per_axis": ne[0], "n": nx, "unknowns": N, "alpha": alpha},
         "solve_tflops": solve_tflops,
+        "spectral_multipliers": {"workload": "u = g(H_3 + alpha) f at the same n, FP64: exp(-1e-3 x) and x^-0.5",
+                                 **spectral},
         "plan_seconds": plan_s,
         "roofline_f64": {"bound": "mfma", "kernel": "mode_nn_f64 (y-axis mode product)",
                          "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

@@ -131,6 +131,25 @@ sem_status sem_solve_refined(sem_plan *p, sem_prec prec, double tol, int max_ite
  * the first refinement iteration); u must not alias f.  Asynchronous. */
 sem_status sem_solve_lowp(sem_plan *p, sem_prec prec, const double *f, double *u);
 
+/* ---- other spectral multipliers --------------------------------------------- */
+
+typedef enum { SEM_SPECTRAL_EXP = 1, SEM_SPECTRAL_POWER = 2 } sem_spectral;
+
+/* u = g(H_3 + a I) f = S_3 g(Lambda3D + a) S_3^{-1} f on the transforms of the
+ * solve (eq. 3D-Poisson with its divide replaced; the paper's introduction and
+ * conclusion name exponential time differencing and spectral fractional
+ * Laplacians as such multipliers), FP64:
+ *  SEM_SPECTRAL_EXP:   g(x) = exp(-param x), param = t >= 0: the solution at time t
+ *                      of u_t = Lap u - a u, u(0) = f;
+ *  SEM_SPECTRAL_POWER: g(x) = x^(-param): the fractional operator (-Lap + a)^(-param)
+ *                      (param = 1: the solve with alpha = a; param < 0: a positive
+ *                      fractional power).
+ * f, u: device FP64 arrays of N nodal values (u may alias f); uses the plan
+ * workspace like sem_solve.  Asynchronous on the plan stream.  SEM_EINVAL: null
+ * pointers, unknown kind, non-finite a or param, t < 0.  SEM_ESINGULAR: a
+ * negative power with min(Lambda3D) + a <= 0. */
+sem_status sem_apply_spectral(sem_plan *p, int kind, double a, double param, const double *f, double *u);
+
 /* ---- variable coefficients (PCG) ---------------------------------------------- */
 
 /* Bytes of the caller-provided workspace of sem_pcg_solve: four FP64 arrays of N

@@ -46,6 +46,7 @@ def _load():
         "sem_solve_refined": (c_int, [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, POINTER(c_int),
                                       POINTER(c_double)]),
         "sem_solve_lowp": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+        "sem_apply_spectral": (c_int, [c_void_p, c_int, c_double, c_double, c_void_p, c_void_p]),
         "sem_pcg_workspace_bytes": (c_int, [c_void_p, POINTER(c_size_t)]),
         "sem_pcg_solve": (c_int, [c_void_p, c_void_p, c_double, c_int, c_double, c_int, c_void_p, c_void_p,
                                   c_void_p, c_size_t, POINTER(c_int), POINTER(c_double)]),
@@ -204,6 +205,19 @@ class Plan:
         up = _dev_ptr(u, "u", self.numel, torch.float64)
         self._prepare(pv)
         check(lib.sem_solve_lowp(self._p, pv, fp, up))
+        return u
+
+    def apply_spectral(self, kind: str, a: float, param: float, f, u=None):
+        """u = g(H_3 + a I) f with g(x) = exp(-param x) ("exp") or x^(-param) ("power")
+        (sem_apply_spectral)."""
+        import torch
+        if u is None:
+            u = torch.empty_like(f)
+        kv = {"exp": 1, "power": 2}[kind]
+        fp = _dev_ptr(f, "f", self.numel, torch.float64)
+        up = _dev_ptr(u, "u", self.numel, torch.float64)
+        self._prepare(SEM_F64)
+        check(lib.sem_apply_spectral(self._p, kv, float(a), float(param), fp, up))
         return u
 
     def pcg_solve(self, v, f, u=None, shift: float = None, prec: str = "f64", tol: float = 1e-12,

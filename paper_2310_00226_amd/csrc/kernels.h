@@ -7,7 +7,8 @@
 
 namespace semfd {
 
-enum { EPI_STORE = 0, EPI_DIVIDE = 1, EPI_ACCUM = 2 };
+// EPI_SPECTRAL (FP64 kernels only): another multiplier than the divide (EpiArgs::kind)
+enum { EPI_STORE = 0, EPI_DIVIDE = 1, EPI_ACCUM = 2, EPI_SPECTRAL = 3 };
 
 // Arguments of the fused epilogues.
 //   EPI_DIVIDE: out = acc / (alpha + b1 L + b2 L^2),  L = lx[row] + ly[col / nz] + lz[col % nz]
@@ -20,11 +21,23 @@ struct EpiArgs {
   const double* lz = nullptr;
   double alpha = 0.0, b1 = 1.0, b2 = 0.0;
   long nz = 1;
+  // multiplier of EPI_SPECTRAL: SPECTRAL_EXP = exp(-param (L + alpha)),
+  // SPECTRAL_POWER = (L + alpha)^(-param); EPI_DIVIDE divides by
+  // alpha + b1 L + b2 L^2
+  int kind = 0;
+  double param = 0.0;
 };
+constexpr int SPECTRAL_EXP = 1, SPECTRAL_POWER = 2;
 
 // Denominator of the spectral divide, FP64.
 __host__ __device__ inline double spectral_den(double lam, double alpha, double b1, double b2) {
   return alpha + lam * (b1 + b2 * lam);
+}
+
+// v times the multiplier of the EPI_SPECTRAL epilogue at eigenvalue sum lam.
+__device__ inline double spectral_mul(double v, double lam, const EpiArgs& e) {
+  if (e.kind == SPECTRAL_EXP) return v * exp(-e.param * (lam + e.alpha));
+  return v * pow(fmax(lam + e.alpha, 0.0), -e.param);  // SPECTRAL_POWER; L >= 0 up to rounding
 }
 
 // One FP64 mode product along `axis` of a row-major (dims[0], dims[1], dims[2])

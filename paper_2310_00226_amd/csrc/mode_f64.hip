@@ -159,7 +159,7 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
   // f64 16x16 accumulator layout: lane, register r  ->  row 4r + lane/16, col lane%16
   double* __restrict__ yp = y + (size_t)p * L * Q;
   double cden[4] = {0.0, 0.0, 0.0, 0.0};
-  if constexpr (EPI == EPI_DIVIDE) {
+  if constexpr (EPI == EPI_DIVIDE || EPI == EPI_SPECTRAL) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const long q = q0 + wn + 16 * j + fr;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
       const int l = l0 + wm + 16 * i + 4 * r + fk;
       if (l >= L) continue;
       double* __restrict__ yrow = yp + (size_t)l * Q;
-      const double lxl = EPI == EPI_DIVIDE ? epi.lx[l] : 0.0;
+      const double lxl = (EPI == EPI_DIVIDE || EPI == EPI_SPECTRAL) ? epi.lx[l] : 0.0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const long q = q0 + wn + 16 * j + fr;
@@ -183,6 +183,7 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
         const double v = acc[i][j][r];
         if constexpr (EPI == EPI_STORE) yrow[q] = v;
         else if constexpr (EPI == EPI_DIVIDE) yrow[q] = v / spectral_den(lxl + cden[j], epi.alpha, epi.b1, epi.b2);
+        else if constexpr (EPI == EPI_SPECTRAL) yrow[q] = spectral_mul(v, lxl + cden[j], epi);
         else yrow[q] += v;
       }
     }
@@ -309,6 +310,8 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
         if constexpr (EPI == EPI_STORE) yrow[l] = v;
         else if constexpr (EPI == EPI_DIVIDE)
           yrow[l] = v / spectral_den(epi.lx[l] + epi.ly[0] + epi.lz[0], epi.alpha, epi.b1, epi.b2);
+        else if constexpr (EPI == EPI_SPECTRAL)
+          yrow[l] = spectral_mul(v, epi.lx[l] + epi.ly[0] + epi.lz[0], epi);
         else yrow[l] += v;
       }
     }
@@ -341,6 +344,10 @@ hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg,
       case EPI_DIVIDE:
         mode_nn_f64<EPI_DIVIDE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, Q, tiles_l, tiles_q, ntiles, nbp, ea);
         break;
+      case EPI_SPECTRAL:
+        mode_nn_f64<EPI_SPECTRAL><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, Q, tiles_l, tiles_q, ntiles, nbp,
+                                                               ea);
+        break;
       default:
         mode_nn_f64<EPI_ACCUM><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, Q, tiles_l, tiles_q, ntiles, nbp, ea);
         break;
@@ -358,6 +365,9 @@ hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg,
         break;
       case EPI_DIVIDE:  // only reached for the x axis with ny = nz = 1
         mode_nt_f64<EPI_DIVIDE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, tiles_l, ntiles, nbp, ea);
+        break;
+      case EPI_SPECTRAL:
+        mode_nt_f64<EPI_SPECTRAL><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, tiles_l, ntiles, nbp, ea);
         break;
       default:
         mode_nt_f64<EPI_ACCUM><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, tiles_l, ntiles, nbp, ea);

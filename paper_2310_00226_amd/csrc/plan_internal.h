@@ -42,8 +42,11 @@ struct sem_plan {
 namespace semfd {
 // Spectral multiplier of an FD application: 1 / (alpha + b1 L + b2 L^2) with L the
 // sum of the three 1D eigenvalues (Helmholtz: {alpha, 1, 0}).
+// kind / param select another multiplier of the FP64 path (EpiArgs::kind).
 struct Spectral {
   double alpha, b1, b2;
+  int kind = 0;
+  double param = 0.0;
 };
 // Buffers of the low-precision solves inside the plan workspace.
 struct LpWork {

@@ -274,11 +274,14 @@ hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, dou
   div.alpha = sp.alpha;
   div.b1 = sp.b1;
   div.b2 = sp.b2;
+  div.kind = sp.kind;
+  div.param = sp.param;
   div.nz = p->dims[2];
   hipError_t e;
   if ((e = launch_mode_f64(f, tmp, p->d_gf[2], p->ld[2], p->dims, 2, EPI_STORE, none, p->stream)) != hipSuccess ||
       (e = launch_mode_f64(tmp, u, p->d_gf[1], p->ld[1], p->dims, 1, EPI_STORE, none, p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(u, tmp, p->d_gf[0], p->ld[0], p->dims, 0, EPI_DIVIDE, div, p->stream)) != hipSuccess ||
+      (e = launch_mode_f64(u, tmp, p->d_gf[0], p->ld[0], p->dims, 0, sp.kind ? EPI_SPECTRAL : EPI_DIVIDE, div,
+                           p->stream)) != hipSuccess ||
       (e = launch_mode_f64(tmp, u, p->d_gb[2], p->ld[2], p->dims, 2, EPI_STORE, none, p->stream)) != hipSuccess ||
       (e = launch_mode_f64(u, tmp, p->d_gb[1], p->ld[1], p->dims, 1, EPI_STORE, none, p->stream)) != hipSuccess ||
       (e = launch_mode_f64(tmp, u, p->d_gb[0], p->ld[0], p->dims, 0, EPI_STORE, none, p->stream)) != hipSuccess)

@@ -270,6 +270,26 @@ sem_status sem_solve(sem_plan* p, const double* f, double* u) {
   return SEM_OK;
 }
 
+sem_status sem_apply_spectral(sem_plan* p, int kind, double a, double param, const double* f, double* u) {
+  if (!p || !f || !u) return fail(SEM_EINVAL, "sem_apply_spectral: null argument");
+  if (kind != SEM_SPECTRAL_EXP && kind != SEM_SPECTRAL_POWER)
+    return fail(SEM_EINVAL, "sem_apply_spectral: unknown multiplier %d", kind);
+  if (!std::isfinite(a) || !std::isfinite(param)) return fail(SEM_EINVAL, "sem_apply_spectral: non-finite parameter");
+  if (kind == SEM_SPECTRAL_EXP && param < 0.0) return fail(SEM_EINVAL, "sem_apply_spectral: time must be >= 0");
+  const double lmin = p->ax[0].lam[0] + p->ax[1].lam[0] + p->ax[2].lam[0] + a;
+  if (kind == SEM_SPECTRAL_POWER && param > 0.0 && !(lmin > 0.0))
+    return fail(SEM_ESINGULAR, "sem_apply_spectral: negative power of a singular operator (min L + a = %.3e)", lmin);
+  void* ws = nullptr;
+  sem_status st = plan_workspace(p, workspace_need(p, SEM_F64), &ws);
+  if (st != SEM_OK) return st;
+  Spectral sp{a, 1.0, 0.0};
+  sp.kind = kind == SEM_SPECTRAL_EXP ? SPECTRAL_EXP : SPECTRAL_POWER;
+  sp.param = param;
+  hipError_t e = fd64(p, sp, f, u, (double*)ws);
+  if (e != hipSuccess) return hip_fail(e, "sem_apply_spectral");
+  return SEM_OK;
+}
+
 sem_status sem_residual(sem_plan* p, const double* u, const double* f, double* r) {
   if (!p || !u || !f || !r) return fail(SEM_EINVAL, "sem_residual: null argument");
   if (r == u) return fail(SEM_EINVAL, "sem_residual: r must not alias u");
