@@ -38,6 +38,7 @@ namespace {
 
 constexpr int NBUCKET = 6;
 constexpr int SPLIT_MIN_DIM = 160;
+constexpr int TUNE_REPS = 5;
 constexpr int TILE_CANDIDATES[4] = {128, 96, 64, 32};
 // pass variants: 0 = forward z from f (FP64 input), 1 = forward z from r,
 // 2..5 = passes 1..4 (2 ... 4 = forward y, forward x + divide, backward z, backward y),
@@ -263,16 +264,21 @@ sem_status autotune(sem_batch* b) {
         break;
       }
       const int grid = b->cus * lp_batch_blocks_per_cu(tr);
-      float ms = 0.f;
-      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-        if (rep == 1) e = hipEventRecord(t0, b->stream);
+      // one warm-up launch, then the fastest of TUNE_REPS timed launches (the small
+      // buckets run for microseconds, where single timings are noisy)
+      float ms = INFINITY;
+      e = launch_mode_f32_batch(1, 1, EPI_STORE, tr, b->d_desc, (int)ds.size(), tiles, b->d_active, grid, b->stream);
+      for (int rep = 0; rep < TUNE_REPS && e == hipSuccess; ++rep) {
+        float one = 0.f;
+        e = hipEventRecord(t0, b->stream);
         if (e == hipSuccess)
           e = launch_mode_f32_batch(1, 1, EPI_STORE, tr, b->d_desc, (int)ds.size(), tiles, b->d_active, grid,
                                     b->stream);
+        if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&one, t0, t1);
+        ms = std::min(ms, one);
       }
-      if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(t1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
       if (e != hipSuccess) {
         st = hip_fail(e, "sem_batch: autotune run");
         break;
