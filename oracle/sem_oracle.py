@@ -329,14 +329,16 @@ def dense_solve(prob: Problem, f: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 
-def ch_step(prob: Problem, phi_n, phi_nm1, eps: float, mob: float, dt: float):
+def ch_step(prob: Problem, phi_n, phi_nm1, eps: float, mob: float, dt: float, forcing=None):
     """One step of eq. (chscheme-2): phi_{n+1} = D phi_hat + (m dt/eps) D Lap F'(phi_bar).
 
     a = 3/2, phi_hat = 2 phi_n - phi_{n-1}/2, phi_bar = 2 phi_n - phi_{n-1},
     F'(phi) = phi^3 - phi (F = (phi^2 - 1)^2 / 4), D = (a I + m dt eps Lap^2)^{-1}.
     The discrete Laplacian is -H_3, so in the eigenbasis Lap -> -Lambda3D:
     phi_{n+1} = S_3 [ (F_3 phi_hat - (m dt/eps) Lambda3D F_3 g) / (a + m dt eps Lambda3D^2) ].
-    (prob.alpha is not used.)
+    (prob.alpha is not used.)  `forcing` (nodal values of a source s at t_{n+1},
+    as in the accuracy test of the BDF2 scheme, where a manufactured solution
+    defines s) adds dt * s to phi_hat: BDF2 applied to phi_t = m Lap mu + s.
     """
     a = 1.5
     phi_hat = 2.0 * phi_n - 0.5 * phi_nm1
@@ -351,6 +353,8 @@ def ch_step(prob: Problem, phi_n, phi_nm1, eps: float, mob: float, dt: float):
     def bwd(v):
         return mode_product(mode_product(mode_product(v, sz, 2), sy, 1), sx, 0)
 
+    if forcing is not None:
+        phi_hat = phi_hat + dt * forcing
     c = (fwd(phi_hat) - (mob * dt / eps) * lam * fwd(g)) / (a + mob * dt * eps * lam * lam)
     return bwd(c)
 

@@ -90,6 +90,30 @@ def schrodinger_data(x, y, z, alpha: float, beta: float):
     return v, u, f
 
 
+def ch_manufactured(x, y, z, t: float, eps: float, mob: float):
+    """(phi*, s) of the Cahn-Hilliard accuracy test at time t: the exact solution
+    phi* = cos(pi x) cos(pi y) cos(pi z) e^t on [-1, 1]^3 (homogeneous Neumann) and
+    the source s = phi*_t - m Lap mu*, mu* = -eps Lap phi* + (phi*^3 - phi*)/eps,
+    which makes phi* solve phi_t = m Lap mu + s (eq. CH-sys plus a source).
+    With C = cos cos cos: Lap C = -3 pi^2 C, and cos^3(pi x) = (3 cos(pi x) +
+    cos(3 pi x))/4 gives Lap(C^3) term by term."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    pi = math.pi
+    c = [np.cos(pi * v) for v in (x, y, z)]
+    c3 = [np.cos(pi * v) ** 3 for v in (x, y, z)]
+    d2c3 = [(-3.0 * pi * pi * np.cos(pi * v) - 9.0 * pi * pi * np.cos(3.0 * pi * v)) / 4.0 for v in (x, y, z)]
+    C = _outer3(*c)
+    lap_c3 = _outer3(d2c3[0], c3[1], c3[2]) + _outer3(c3[0], d2c3[1], c3[2]) + _outer3(c3[0], c3[1], d2c3[2])
+    et, e3t = math.exp(t), math.exp(3.0 * t)
+    phi = C * et
+    # Lap mu* = -eps Lap^2 phi* + (Lap(phi*^3) - Lap phi*)/eps, Lap^2 C = 9 pi^4 C
+    lap_mu = -eps * (9.0 * pi ** 4) * C * et + (lap_c3 * e3t + 3.0 * pi * pi * C * et) / eps
+    s = phi - mob * lap_mu
+    return phi, s
+
+
 def normal_noise(shape, seed: int, scale: float = 1.0, chunks: int = 16) -> np.ndarray:
     """Seeded N(0, scale^2) array of `shape` (float64).
 
