@@ -246,6 +246,13 @@ sem_status sem_ch_set_stream(sem_ch *c, void *hip_stream);
  * the first call, and again whenever phi_n / phi_nm1 change address); 0: the same
  * kernels launched one by one. */
 sem_status sem_ch_set_graphs(sem_ch *c, int enable);
+/* Optional source term (the accuracy test of the BDF2 scheme adds the source of a
+ * manufactured solution): s = device array of N doubles read by every following
+ * step as the nodal source at the new time level t_{n+1}, entering the step as
+ * dt * s (BDF2 for phi_t = m Lap mu + s); NULL removes it.  The caller updates the
+ * contents between steps (ordered on the stream of sem_ch_set_stream); a new
+ * pointer re-captures the step graphs.  SEM_EINVAL: null handle. */
+sem_status sem_ch_set_forcing(sem_ch *c, const double *s);
 /* Advance nsteps >= 0 steps.  phi_n, phi_nm1: device arrays of N doubles (distinct),
  * holding phi_n and phi_{n-1} on entry (first step: pass phi_0 in both) and
  * phi_{n+nsteps}, phi_{n+nsteps-1} on return.  Asynchronous. */

@@ -62,6 +62,7 @@ def _load():
         "sem_ch_destroy": (None, [c_void_p]),
         "sem_ch_dims": (c_int, [c_void_p, POINTER(c_int)]),
         "sem_ch_set_stream": (c_int, [c_void_p, c_void_p]),
+        "sem_ch_set_forcing": (c_int, [c_void_p, c_void_p]),
         "sem_ch_set_graphs": (c_int, [c_void_p, c_int]),
         "sem_ch_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
         "sem_last_error": (c_char_p, []),
@@ -303,6 +304,17 @@ class CahnHilliard:
 
     def set_graphs(self, enable: bool):
         check(lib.sem_ch_set_graphs(self._c, 1 if enable else 0))
+
+    def set_forcing(self, s=None):
+        """Source term read by every following step at the new time level (or None)."""
+        import torch
+        if s is None:
+            self._forcing = None
+            check(lib.sem_ch_set_forcing(self._c, c_void_p(None)))
+            return
+        ptr = _dev_ptr(s, "s", self.numel, torch.float64)
+        self._forcing = s  # keep the array alive while the stepper may read it
+        check(lib.sem_ch_set_forcing(self._c, ptr))
 
     def step(self, phi_n, phi_nm1, nsteps: int = 1):
         """Advance in place: on return phi_n, phi_nm1 hold phi_{n+nsteps}, phi_{n+nsteps-1}."""

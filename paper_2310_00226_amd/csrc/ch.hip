@@ -49,6 +49,7 @@ struct sem_ch {
   double* w = nullptr;     // H_3 phi during sweeps
   semfd::LpWork lw;
   double* tmp64 = nullptr;  // FP64 FD scratch (plan workspace) in FP64 mode
+  const double* forcing = nullptr;  // optional source s at t_{n+1} (caller-owned)
   int use_graphs = 1;
   hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
   const double* key_n = nullptr;
@@ -96,7 +97,7 @@ hipError_t enqueue_step(sem_ch* c, const double* prev, const double* cur, double
   hipError_t e;
   ch_pointwise_kernel<<<grid_for(c->N), 256, 0, c->stream>>>(cur, prev, c->phat, c->g, c->N);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  {  // rhs = phi_hat - (m dt / eps) H_3 g
+  {  // rhs = phi_hat (+ dt s) - (m dt / eps) H_3 g
     ResidualArgs ra;
     ra.v = c->g;
     ra.f = c->phat;
@@ -105,6 +106,10 @@ hipError_t enqueue_step(sem_ch* c, const double* prev, const double* cur, double
     ra.ldr = p->dims[2];
     ra.cf = 1.0;
     ra.cd = 0.0;
+    if (c->forcing) {  // BDF2 for phi_t = m Lap mu + s: the source enters as dt s
+      ra.d = c->forcing;
+      ra.cd = -c->dt;
+    }
     ra.ch = c->mob * c->dt / c->eps;
     if ((e = launch_residual(ra, hb, p->k, p->dims, c->stream)) != hipSuccess) return e;
   }
@@ -264,6 +269,13 @@ sem_status sem_ch_set_stream(sem_ch* c, void* s) {
 sem_status sem_ch_set_graphs(sem_ch* c, int enable) {
   if (!c) return set_error(SEM_EINVAL, "sem_ch_set_graphs: null handle");
   c->use_graphs = enable ? 1 : 0;
+  return SEM_OK;
+}
+
+sem_status sem_ch_set_forcing(sem_ch* c, const double* s) {
+  if (!c) return set_error(SEM_EINVAL, "sem_ch_set_forcing: null handle");
+  if (s != c->forcing) drop_graphs(c);  // the captured steps hold the old pointer
+  c->forcing = s;
   return SEM_OK;
 }
 

@@ -136,3 +136,70 @@ def test_ch_full_size_n257(torch, P, sweeps):
     _log(f"[ch]   mass drift after 103 steps {drift:.2e} (scale {scale:.2e})")
     assert drift <= 1e-11 * scale
     assert np.all(np.isfinite(phi)) and np.max(np.abs(phi)) < 1.0
+
+
+@pytest.mark.parametrize("prec_sweeps", [("f64", 0), ("f32", 1)], ids=lambda c: f"{c[0]}-s{c[1]}")
+def test_ch_forced_steps_match_oracle(torch, P, prec_sweeps):
+    """Steps with the source of the BDF2 accuracy test (changed before every step,
+    graph replays) against the oracle's forced steps; then the source removed."""
+    from workloads import ch_manufactured
+    prec, sweeps = prec_sweeps
+    eps, mob, dt = 0.2, 0.01, 0.01
+    box = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0)
+    ne = (4, 5, 3)
+    prob = O.Problem(5, ne, box, 0.0, "neumann")
+    xs = [o.x for o in prob.axes]
+    ch = P.CahnHilliard(5, ne, box, eps, mob, dt, prec=prec, refine_sweeps=sweeps)
+    cur, _ = ch_manufactured(*xs, 0.0, eps, mob)
+    prev, _ = ch_manufactured(*xs, -dt, eps, mob)
+    a, b = _dev(torch, cur), _dev(torch, prev)
+    sd = torch.empty_like(a)
+    ch.set_forcing(sd)
+    tol = 1e-12 if prec == "f64" else 1e-10
+    for n in range(5):
+        _, s = ch_manufactured(*xs, (n + 1) * dt, eps, mob)
+        sd.copy_(torch.from_numpy(s))
+        ch.step(a, b, 1)
+        cur, prev = O.ch_step(prob, cur, prev, eps, mob, dt, forcing=s), cur
+        err = O.rel_max_err(a.cpu().numpy(), cur)
+        assert err <= tol, (n, err)
+    ch.set_forcing(None)
+    ch.step(a, b, 1)
+    cur = O.ch_step(prob, cur, prev, eps, mob, dt)
+    assert O.rel_max_err(a.cpu().numpy(), cur) <= tol
+
+
+def test_ch_bdf2_second_order_gpu(torch, P):
+    """The accuracy test of the BDF2 scheme in the paper's configuration (Q^5, 51
+    nodes per axis, eps = 0.2, m = 0.01, exact start) with the benchmarked step
+    (FP32 solve + one FP64 sweep): relative l2 error at T = 0.1 falls by ~4 per
+    halving of dt, and equals the oracle's to 1e-6 relative."""
+    from workloads import ch_manufactured
+    eps, mob, T = 0.2, 0.01, 0.1
+    box = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0)
+    ne = (10, 10, 10)
+    prob = O.Problem(5, ne, box, 0.0, "neumann")
+    xs = [o.x for o in prob.axes]
+    errs, errs_ref = [], []
+    for dt in (0.02, 0.01, 0.005, 0.0025):
+        ch = P.CahnHilliard(5, ne, box, eps, mob, dt, prec="f32", refine_sweeps=1)
+        cur, _ = ch_manufactured(*xs, 0.0, eps, mob)
+        prev, _ = ch_manufactured(*xs, -dt, eps, mob)
+        a, b = _dev(torch, cur), _dev(torch, prev)
+        sd = torch.empty_like(a)
+        ch.set_forcing(sd)
+        for n in range(int(round(T / dt))):
+            _, s = ch_manufactured(*xs, (n + 1) * dt, eps, mob)
+            sd.copy_(torch.from_numpy(s))
+            ch.step(a, b, 1)
+            if dt == 0.02:
+                cur, prev = O.ch_step(prob, cur, prev, eps, mob, dt, forcing=s), cur
+        ex, _ = ch_manufactured(*xs, T, eps, mob)
+        u = a.cpu().numpy()
+        errs.append(np.linalg.norm(u - ex) / np.linalg.norm(ex))
+        if dt == 0.02:
+            errs_ref.append(np.linalg.norm(cur - ex) / np.linalg.norm(ex))
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    _log(f"[ch] BDF2 accuracy test: errors {['%.2e' % e for e in errs]}, ratios {['%.2f' % r for r in ratios]}")
+    assert all(3.6 <= r <= 4.4 for r in ratios), (errs, ratios)
+    assert abs(errs[0] - errs_ref[0]) <= 1e-6 * errs_ref[0]
