@@ -38,6 +38,9 @@ namespace {
 
 constexpr int NBUCKET = 6;
 constexpr int SPLIT_MIN_DIM = 160;
+// side streams of the split-BF16 solves (with the batch stream: the four hardware
+// queues a process gets by default)
+constexpr int NSIDE = 3;
 constexpr int TUNE_REPS = 5;
 constexpr int TILE_CANDIDATES[4] = {128, 96, 64, 32};
 // pass variants: 0 = forward z from f (FP64 input), 1 = forward z from r,
@@ -84,6 +87,9 @@ struct sem_batch {
   std::vector<ResDesc> h_rdesc;
   std::vector<Group> groups;
   std::vector<Group> rgroups;  // residual groups: var = k
+  hipStream_t side[NSIDE] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_start = nullptr;
+  hipEvent_t ev_side[NSIDE] = {nullptr, nullptr, nullptr};
 };
 
 namespace semfd {
@@ -295,15 +301,15 @@ sem_status autotune(sem_batch* b) {
   return st;
 }
 
-// One refinement iteration of solve i in split BF16 on the batch stream: the FP64
+// One refinement iteration of solve i in split BF16 on `stream`: the FP64
 // residual written as split BF16 (from the second iteration on), then the FD
 // application that stores (first iteration) or accumulates the update into u and
 // leaves max|delta|, max|u| in the solve's norm slots.
-hipError_t split_iteration(sem_batch* b, int i, int it, const double* f, double* u) {
+hipError_t split_iteration(sem_batch* b, int i, int it, const double* f, double* u, hipStream_t stream) {
   sem_plan* p = b->plans[i];
   const LpWork& w = b->lw[i];
   hipStream_t keep = p->stream;
-  p->stream = b->stream;
+  p->stream = stream;
   hipError_t e = hipSuccess;
   if (it > 0) {
     ResidualArgs ra;  // r = f - alpha u - H_3 u
@@ -317,7 +323,7 @@ hipError_t split_iteration(sem_batch* b, int i, int it, const double* f, double*
     ra.cd = p->alpha;
     ra.ch = 1.0;
     const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
-    e = launch_residual(ra, hb, p->k, p->dims, b->stream);
+    e = launch_residual(ra, hb, p->k, p->dims, stream);
   }
   if (e == hipSuccess)
     e = lp_fd(p, w, Spectral{p->alpha, 1.0, 0.0}, it == 0 ? f : nullptr, u, it == 0 ? 1 : 0, b->d_norms + 2 * i);
@@ -333,6 +339,14 @@ extern "C" {
 void sem_batch_destroy(sem_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  for (int s = 0; s < NSIDE; ++s) {
+    if (b->side[s]) {
+      (void)hipStreamSynchronize(b->side[s]);
+      (void)hipStreamDestroy(b->side[s]);
+    }
+    if (b->ev_side[s]) (void)hipEventDestroy(b->ev_side[s]);
+  }
+  if (b->ev_start) (void)hipEventDestroy(b->ev_start);
   (void)hipFree(b->d_desc);
   (void)hipFree(b->d_rdesc);
   (void)hipFree(b->d_active);
@@ -378,6 +392,15 @@ sem_status sem_batch_create(int count, sem_plan* const* plans, sem_batch** out) 
       (e = hipMalloc(&b->d_norms, 2 * sizeof(unsigned long long) * (size_t)count)) != hipSuccess) {
     sem_batch_destroy(b);
     return hip_fail(e, "sem_batch_create: device allocation");
+  }
+  for (int s = 0; s < NSIDE && e == hipSuccess; ++s) {
+    e = hipStreamCreateWithFlags(&b->side[s], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_side[s], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    sem_batch_destroy(b);
+    return hip_fail(e, "sem_batch_create: side streams");
   }
   sem_status st = autotune(b);
   if (st != SEM_OK) {
@@ -437,6 +460,27 @@ sem_status sem_batch_solve(sem_batch* b, sem_prec prec, double tol, int max_iter
   }
   sem_status st = build_descs(b, f, u, split);
   if (st != SEM_OK) return st;
+  // split solves: largest first onto the least-loaded side stream (cost ~ N (nx + ny + nz))
+  std::vector<int> order, lane(n, 0);
+  for (int i = 0; i < n; ++i)
+    if (split[i]) order.push_back(i);
+  auto cost = [&](int i) {
+    const int* d = b->plans[i]->dims;
+    return (double)d[0] * d[1] * d[2] * (d[0] + d[1] + d[2]);
+  };
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  double load[NSIDE] = {0.0, 0.0, 0.0};
+  for (int i : order) {
+    int s = 0;
+    for (int t = 1; t < NSIDE; ++t)
+      if (load[t] < load[s]) s = t;
+    lane[i] = s;
+    load[s] += cost(i);
+  }
+  // on an error after side-stream work was queued, wait for it before returning
+  auto drain = [&]() {
+    for (int s = 0; s < NSIDE; ++s) (void)hipStreamSynchronize(b->side[s]);
+  };
   std::vector<int> active(n, 1), done_it(n, 0), dev_active(n, 0);
   std::vector<double> prev(n, INFINITY), prev2(n, INFINITY);
   std::vector<unsigned long long> hn(2 * n);
@@ -447,23 +491,52 @@ sem_status sem_batch_solve(sem_batch* b, sem_prec prec, double tol, int max_iter
     if ((e = hipMemcpyAsync(b->d_active, dev_active.data(), n * sizeof(int), hipMemcpyHostToDevice, b->stream)) !=
         hipSuccess)
       return hip_fail(e, "sem_batch_solve: active flags");
+    zero_u64_n<<<(2 * n + 255) / 256, 256, 0, b->stream>>>(b->d_norms, 2 * n);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sem_batch_solve: norm reset");
+    // split solves on the side streams, after the norm reset and concurrently with
+    // the persistent launches below
+    if (!order.empty()) {
+      if ((e = hipEventRecord(b->ev_start, b->stream)) != hipSuccess) return hip_fail(e, "sem_batch_solve: event");
+      for (int s = 0; s < NSIDE; ++s)
+        if ((e = hipStreamWaitEvent(b->side[s], b->ev_start, 0)) != hipSuccess)
+          return hip_fail(e, "sem_batch_solve: event");
+      for (int i : order)
+        if (active[i] && (e = split_iteration(b, i, it, f[i], u[i], b->side[lane[i]])) != hipSuccess) {
+          drain();
+          return hip_fail(e, "sem_batch_solve: split-BF16 solve");
+        }
+      for (int s = 0; s < NSIDE && e == hipSuccess; ++s) e = hipEventRecord(b->ev_side[s], b->side[s]);
+      if (e != hipSuccess) {
+        drain();
+        return hip_fail(e, "sem_batch_solve: event");
+      }
+    }
     if (it > 0)
       for (const Group& g : b->rgroups)
         if ((e = launch_residual_batch(g.var, 1, b->d_rdesc + g.off, g.count, g.tiles, b->d_active, b->stream)) !=
-            hipSuccess)
+            hipSuccess) {
+          drain();
           return hip_fail(e, "sem_batch_solve: residual");
-    zero_u64_n<<<(2 * n + 255) / 256, 256, 0, b->stream>>>(b->d_norms, 2 * n);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sem_batch_solve: norm reset");
+        }
     const int seq[6] = {it == 0 ? 0 : 1, 2, 3, 4, 5, it == 0 ? 6 : 7};
     for (int v : seq)
-      if ((e = run_variant(b, v)) != hipSuccess) return hip_fail(e, "sem_batch_solve: mode products");
-    for (int i = 0; i < n; ++i)
-      if (active[i] && split[i] && (e = split_iteration(b, i, it, f[i], u[i])) != hipSuccess)
-        return hip_fail(e, "sem_batch_solve: split-BF16 solve");
+      if ((e = run_variant(b, v)) != hipSuccess) {
+        drain();
+        return hip_fail(e, "sem_batch_solve: mode products");
+      }
+    // the norm read-back waits for the side streams
+    if (!order.empty())
+      for (int s = 0; s < NSIDE && e == hipSuccess; ++s) e = hipStreamWaitEvent(b->stream, b->ev_side[s], 0);
+    if (e != hipSuccess) {
+      drain();
+      return hip_fail(e, "sem_batch_solve: event");
+    }
     if ((e = hipMemcpyAsync(hn.data(), b->d_norms, hn.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                             b->stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(b->stream)) != hipSuccess)
+        (e = hipStreamSynchronize(b->stream)) != hipSuccess) {
+      drain();
       return hip_fail(e, "sem_batch_solve: norm readback");
+    }
     int left = 0;
     for (int i = 0; i < n; ++i) {
       if (!active[i]) continue;
