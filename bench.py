@@ -46,7 +46,7 @@ def bench_batch(args, P, torch, dev, log):
     alpha ~ U[0, 10], N(0,1) right-hand sides (seed 2311); FP64 refinement to
     ||delta|| <= tol ||u||.  Two batch precisions are timed: FP32 mode products for
     every problem (one persistent launch per pass), and SEM_BF16X3, where the
-    problems with every dimension >= 160 run split-BF16 passes; the faster one is
+    problems with every dimension >= 96 run split-BF16 passes; the faster one is
     reported."""
     from concurrent.futures import ThreadPoolExecutor
 
@@ -85,20 +85,20 @@ def bench_batch(args, P, torch, dev, log):
         outs[prec] = us
     best = min((p for p in per_prec if per_prec[p]["status"] == 0), key=lambda p: per_prec[p]["ms_per_batch"],
                default="f32")
-    nsplit = sum(1 for p in plans if min(p.shape) >= 160)
+    nsplit = sum(1 for p in plans if min(p.shape) >= 96)
     res = {"workload": f"{len(plans)} independent Q^k Helmholtz solves, k in 2..8, 8..64 elements per axis, "
                        f"alpha in [0,10], Dirichlet [-1,1]^3, N(0,1) rhs (seed 2311)",
            "unknowns": total, "precision": best, **per_prec[best], "by_precision": per_prec,
            "tile_rows": batch.tile_rows(), "setup_seconds": plan_s,
            "dtype": ("f32 mode products" if best == "f32" else
-                     f"split-bf16 mode products for the {nsplit} problems with every dimension >= 160, "
+                     f"split-bf16 mode products for the {nsplit} problems with every dimension >= 96, "
                      f"f32 for the rest") + ", f64 residual/update"}
     if not args.no_cpu_baseline:
         import oracle as O
         # the two smallest problems, and the smallest one that ran split BF16,
         # checked against the oracle
         order = sorted(range(len(plans)), key=lambda i: plans[i].numel)
-        check = order[:2] + ([next(i for i in order if min(plans[i].shape) >= 160)] if best == "bf16x3" else [])
+        check = order[:2] + ([next(i for i in order if min(plans[i].shape) >= 96)] if best == "bf16x3" else [])
         errs = []
         for i in check:
             s = specs[i]

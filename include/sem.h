@@ -204,8 +204,9 @@ sem_status sem_batch_tile_rows(const sem_batch *b, int rows[6]);
  *           tile shape over all still-unconverged problems, each residual one
  *           launch per k.  One synchronisation per iteration (norm read-back).
  *  SEM_BF16X3: as SEM_F32, except that every problem whose three dimensions are
- *           all >= 160 runs its iterations with the split-BF16 mode products of
- *           sem_solve_refined (one launch per pass, on the batch stream, after
+ *           all >= 96 runs its iterations with the split-BF16 mode products of
+ *           sem_solve_refined (one launch per pass, on three side streams that
+ *           wait on and are joined back into the batch stream, concurrently with
  *           the persistent launches of the other problems); all problems refine
  *           in FP64 to the same tol.
  *  SEM_F64: one FP64 sem_solve per problem on the batch stream.

@@ -11,11 +11,14 @@
 //
 // Split-BF16 batches (SEM_BF16X3): a solve whose every dimension reaches
 // SPLIT_MIN_DIM runs the split-BF16 passes of the single solves (right-hand-side
-// conversion, six DMA mode products, residual written as split BF16) on the batch
-// stream, one launch per pass: with 256 x 256 tiles such a pass has at least 100
-// tiles and keeps the chip busy by itself, and these passes are 1.3-2.3x faster
-// than the FP32 ones from n = 191 to 511.  The other solves share the persistent
-// FP32 launches as in an FP32 batch.  Both refine in FP64 to the same tolerance.
+// conversion, six DMA mode products, residual written as split BF16), one launch
+// per pass, on one of NSIDE side streams; the side streams run concurrently with
+// each other and with the persistent FP32 launches of the other solves on the
+// batch stream, so a small pass need not fill the chip by itself.  These passes
+// are 1.3-2.3x faster than the FP32 ones from n = 191 to 511 when run alone;
+// with the concurrency the batch time is flat for thresholds of 48..96 (245-249
+// ms for the 256-problem workload) and grows above (270 ms at 160, 343 at 256).
+// Both paths refine in FP64 to the same tolerance.
 //
 // Tile shape: the FP32 kernel has 128 x 128, 96 x 128, 64 x 128 and 32 x 128 block tiles
 // (factor rows x tensor rows).  Short contraction lengths waste most of a
@@ -37,7 +40,7 @@ namespace semfd {
 namespace {
 
 constexpr int NBUCKET = 6;
-constexpr int SPLIT_MIN_DIM = 160;
+constexpr int SPLIT_MIN_DIM = 96;
 // side streams of the split-BF16 solves (with the batch stream: the four hardware
 // queues a process gets by default)
 constexpr int NSIDE = 3;
