@@ -16,6 +16,7 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   ch_step                                                          pinned
   schrodinger_apply, pcg_schrodinger                               pinned
   spectral_apply                                                   pinned
+  periodic boundary condition (axis_operators, axis_eigen, Problem) pinned
 """
 from .sem_oracle import (  # noqa: F401
     gll,

@@ -36,8 +36,8 @@ def lib():
             l = ctypes.CDLL(LIB)
             dp = ctypes.POINTER(ctypes.c_double)
             l.oracle_eig_refine.restype = ctypes.c_int
-            l.oracle_eig_refine.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                            ctypes.c_double, dp, dp, dp, dp, dp]
+            l.oracle_eig_refine.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_double, ctypes.c_double, dp, dp, dp, dp, dp]
             _lib = l
     return _lib
 
@@ -51,8 +51,9 @@ def eig_refine(ops, xr: np.ndarray, wr: np.ndarray, lam: np.ndarray, s: np.ndarr
     wr = np.ascontiguousarray(wr, dtype=np.float64)
     md = np.ascontiguousarray(ops.M, dtype=np.float64)
     off = 1 if ops.bc == "dirichlet" else 0
+    per = 1 if ops.bc == "periodic" else 0
     dp = ctypes.POINTER(ctypes.c_double)
-    st = lib().oracle_eig_refine(n, ops.k, ops.ne, off, ops.a, ops.b, xr.ctypes.data_as(dp), wr.ctypes.data_as(dp),
+    st = lib().oracle_eig_refine(n, ops.k, ops.ne, off, per, ops.a, ops.b, xr.ctypes.data_as(dp), wr.ctypes.data_as(dp),
                                  md.ctypes.data_as(dp), lo.ctypes.data_as(dp), so.ctypes.data_as(dp))
     if st != 0:
         raise MemoryError("oracle_eig_refine: allocation failed")

@@ -16,6 +16,15 @@
  *     E_ij   = (T_ij + lam_j R_ij) / (lam_j - lam_i)   (i != j),
  *     X_new  = X (I + E).
  * Pairs closer than a relative 1e-15 keep only the symmetric part R_ij / 2.
+ * With periodic conditions the spectrum has exactly double eigenvalues (the
+ * translation by one element is a symmetry of the discrete operator, and its
+ * Bloch phases +theta and -theta give the same eigenvalues) and, at the Bloch
+ * phase pi, pairs split only by the discretisation error (1.4e-10 lambda_max
+ * for Q^20 with 10 elements).  One Newton step across such a gap g leaves a
+ * second-order error (eps lambda_max / g)^2 in S^T M S; inside the pair any
+ * M-orthonormal basis has K s - lambda M s ~ eps lambda_max.  So pairs closer
+ * than a relative 1e-8 are treated as one eigenspace there (symmetric part
+ * only: no rotation inside it).
  *
  * K is not taken from its FP64 entries: the lowest eigenvalues come out of a
  * cancellation of ratio lambda_max / lambda_min, so FP64 rounding of K's entries
@@ -25,13 +34,14 @@
  * the off-diagonal row sum (as the paper's LegendreD does), K_ref = D^T W D, element
  * matrix K_ref / h (Appendix SEGenerator1D).  M (diagonal, well conditioned) is
  * used as given.  `off` = 1 for homogeneous Dirichlet (the end nodes are removed),
- * 0 for Neumann.
+ * 0 for Neumann and periodic; `per` = 1 for periodic (full node ne*k is node 0).
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
-int oracle_eig_refine(int n, int k, int ne, int off, double a, double b, const double *xr, const double *wr,
+int oracle_eig_refine(int n, int k, int ne, int off, int per, double a, double b, const double *xr,
+                      const double *wr,
                       const double *M, double *lam, double *S) {
   if (n <= 0) return 0;
   const size_t nn = (size_t)n * n;
@@ -72,21 +82,26 @@ int oracle_eig_refine(int n, int k, int ne, int off, double a, double b, const d
       Ke[i * np + j] = acc / h;
     }
   /* K X: rows of the full (ne*k+1)-node numbering, element by element; for Dirichlet
-   * the removed end nodes carry zero in every column of X */
+   * the removed end nodes carry zero in every column of X; periodic: full nodes
+   * gf and gf + n are the same unknown (only node 0 has the alias n = ne*k) */
 #pragma omp parallel for schedule(static)
   for (int g = 0; g < n; ++g) {
     long double *row = KX + (size_t)g * n;
     for (int j = 0; j < n; ++j) row[j] = 0.0L;
-    const int gf = g + off; /* full index */
-    for (int e = (gf - 1) / k < 0 ? 0 : (gf - 1) / k; e <= gf / k && e < ne; ++e) {
-      const int li = gf - e * k; /* local index of gf in element e */
-      if (li < 0 || li > k) continue;
-      for (int lj = 0; lj < np; ++lj) {
-        const int qf = e * k + lj, q = qf - off;
-        if (q < 0 || q >= n || qf >= nfull) continue;
-        const long double kv = Ke[li * np + lj];
-        const long double *xq = X + (size_t)q * n;
-        for (int j = 0; j < n; ++j) row[j] += kv * xq[j];
+    for (int alias = 0; alias <= per; ++alias) {
+      const int gf = g + off + alias * n; /* full index */
+      if (gf >= nfull) continue;
+      for (int e = (gf - 1) / k < 0 ? 0 : (gf - 1) / k; e <= gf / k && e < ne; ++e) {
+        const int li = gf - e * k; /* local index of gf in element e */
+        if (li < 0 || li > k) continue;
+        for (int lj = 0; lj < np; ++lj) {
+          const int qf = e * k + lj;
+          const int q = per ? qf % n : qf - off;
+          if (q < 0 || q >= n || qf >= nfull) continue;
+          const long double kv = Ke[li * np + lj];
+          const long double *xq = X + (size_t)q * n;
+          for (int j = 0; j < n; ++j) row[j] += kv * xq[j];
+        }
       }
     }
   }
@@ -112,7 +127,7 @@ int oracle_eig_refine(int n, int k, int ne, int off, double a, double b, const d
     if (fabsl(L[i]) > lmax) lmax = fabsl(L[i]);
   }
   /* E overwrites T */
-  const long double tiny = 1e-15L * (lmax > 0 ? lmax : 1.0L);
+  const long double tiny = (per ? 1e-8L : 1e-15L) * (lmax > 0 ? lmax : 1.0L);
 #pragma omp parallel for schedule(static)
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {

@@ -102,7 +102,7 @@ class AxisOps:
     ne: int
     a: float
     b: float
-    bc: str          # "dirichlet" | "neumann" (homogeneous)
+    bc: str          # "dirichlet" | "neumann" (homogeneous) | "periodic"
     x: np.ndarray    # node coordinates of the unknowns
     K: np.ndarray    # dense stiffness, n x n
     M: np.ndarray    # lumped mass (diagonal), length n
@@ -116,9 +116,14 @@ def axis_operators(k: int, ne: int, a: float, b: float, bc: str) -> AxisOps:
     neighbouring elements share their end node, giving ne*k + 1 nodes; element
     matrices are K_ref / h and h * diag(w).  Homogeneous Neumann keeps every
     node (natural condition).  Homogeneous Dirichlet removes the two boundary
-    nodes, leaving ne*k - 1 unknowns (the DoF counts of Table 1).
+    nodes, leaving ne*k - 1 unknowns (the DoF counts of Table 1).  Periodic
+    (Sec. 2.4 lists it among the boundary conditions of the same tensor form;
+    Sec. 4 uses it for the Schroedinger tables) identifies the node at b with the
+    node at a: the last row and column of the Neumann matrices are added onto the
+    first, leaving ne*k unknowns (the DoF counts of Tables tab7c and tab8, e.g.
+    250^3 = (50 * 5)^3 for Q^5).
     """
-    if bc not in ("dirichlet", "neumann"):
+    if bc not in ("dirichlet", "neumann", "periodic"):
         raise ValueError(bc)
     xr, w, k_ref = element_matrices(k)
     h = (b - a) / (2.0 * ne)
@@ -139,6 +144,12 @@ def axis_operators(k: int, ne: int, a: float, b: float, bc: str) -> AxisOps:
     if bc == "dirichlet":
         sl = slice(1, nfull - 1)
         return AxisOps(k, ne, a, b, bc, xfull[sl].copy(), kfull[sl, sl].copy(), mfull[sl].copy(), h)
+    if bc == "periodic":
+        # P^T K P, P^T m with P the (n+1) x n map of node g to node g mod n
+        n = nfull - 1
+        fold = np.zeros((nfull, n))
+        fold[np.arange(nfull), np.arange(nfull) % n] = 1.0
+        return AxisOps(k, ne, a, b, bc, xfull[:n].copy(), fold.T @ kfull @ fold, fold.T @ mfull, h)
     return AxisOps(k, ne, a, b, bc, xfull, kfull, mfull, h)
 
 
