@@ -18,7 +18,9 @@
  * u[(i*n_y + j)*n_z + l] is the value at node (x_i, y_j, z_l).  (The paper stores
  * the same array column-major; only the storage order differs.)  Values are
  * nodal; with Dirichlet conditions only interior nodes are unknowns
- * (n_a = ne_a*k - 1), with Neumann all nodes are (n_a = ne_a*k + 1).
+ * (n_a = ne_a*k - 1), with Neumann all nodes are (n_a = ne_a*k + 1), with
+ * periodic conditions the node at the upper end of an axis is the node at its
+ * lower end (n_a = ne_a*k; node 0 sits at box[2a]).
  *
  * Memory: array arguments named f, u, r, phi are DEVICE pointers owned by the
  * caller, float64, at least 8-byte aligned, on the device the plan was created
@@ -41,7 +43,12 @@ extern "C" {
 
 typedef struct sem_plan sem_plan;
 
-typedef enum { SEM_BC_DIRICHLET = 0, SEM_BC_NEUMANN = 1 } sem_bc; /* homogeneous (Sec. 2.1 remark) */
+/* Boundary conditions on all six faces: homogeneous Dirichlet or Neumann (Sec. 2.1
+ * remark), or periodic on every axis (Sec. 2.4 names periodic boundaries among
+ * those of the same tensor form; Sec. 4 solves its Schroedinger problem with
+ * them).  Periodic: the 1D stiffness and mass couple the last element to the
+ * first, the factors stay dense n x n (for k > 1 they are not Fourier matrices). */
+typedef enum { SEM_BC_DIRICHLET = 0, SEM_BC_NEUMANN = 1, SEM_BC_PERIODIC = 2 } sem_bc;
 
 /* Arithmetic of the mode products.  The residual, the solution update and the
  * 1D eigen-decompositions are always FP64. */
@@ -57,7 +64,7 @@ typedef enum {
   SEM_EINVAL = 1,      /* invalid argument */
   SEM_ENOMEM = 2,      /* device or host allocation failed */
   SEM_EDEVICE = 3,     /* HIP runtime error or device fault */
-  SEM_ESINGULAR = 4,   /* the operator has a zero eigenvalue (Neumann with alpha = 0) */
+  SEM_ESINGULAR = 4,   /* the operator has a zero eigenvalue (Neumann / periodic, alpha = 0) */
   SEM_ENOCONV = 5,     /* iterative refinement stopped without meeting the tolerance */
   SEM_ENONFINITE = 6   /* a residual or update became NaN / Inf */
 } sem_status;
@@ -68,7 +75,8 @@ typedef enum {
  * elements on [box[2a], box[2a+1]], GLL rule of degree k), their generalised
  * eigen-decompositions in FP64 on the host (Sec. 2.3), and upload the factors to
  * the current HIP device.  k >= 1, ne[a] >= 1, box[2a] < box[2a+1], alpha >= 0.
- * Returns SEM_ESINGULAR when alpha + min eigenvalue sum is 0 (Neumann, alpha = 0).
+ * Returns SEM_ESINGULAR when alpha + min eigenvalue sum is 0 (Neumann or periodic
+ * with alpha = 0: the constants are in the kernel).
  * Synchronous.  The plan owns its factor storage (a few MB) until destroyed. */
 sem_status sem_plan_create(int k, const int ne[3], const double box[6], double alpha, sem_bc bc, sem_plan **out);
 void sem_plan_destroy(sem_plan *p);

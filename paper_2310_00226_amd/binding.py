@@ -13,7 +13,8 @@ from ctypes import POINTER, c_char_p, c_double, c_int, c_size_t, c_void_p
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libsemfd.so")
 
-SEM_BC_DIRICHLET, SEM_BC_NEUMANN = 0, 1
+SEM_BC_DIRICHLET, SEM_BC_NEUMANN, SEM_BC_PERIODIC = 0, 1, 2
+_BC = {"dirichlet": SEM_BC_DIRICHLET, "neumann": SEM_BC_NEUMANN, "periodic": SEM_BC_PERIODIC}
 SEM_F64, SEM_F32, SEM_BF16, SEM_BF16X3 = 0, 1, 2, 3
 PRECISIONS = {"f64": SEM_F64, "f32": SEM_F32, "bf16": SEM_BF16, "bf16x3": SEM_BF16X3}
 STATUS = {0: "SEM_OK", 1: "SEM_EINVAL", 2: "SEM_ENOMEM", 3: "SEM_EDEVICE", 4: "SEM_ESINGULAR",
@@ -105,7 +106,7 @@ def _dev_ptr(t, name, n=None, dtype=None):
 def axis_host(k: int, ne: int, a: float, b: float, bc: str):
     """1D operators of one axis as built by the plan (host only): dict of x, mass, lam, S, F."""
     import numpy as np
-    bcv = SEM_BC_DIRICHLET if bc == "dirichlet" else SEM_BC_NEUMANN
+    bcv = _BC[bc]
     n = c_int(0)
     check(lib.sem_axis_host(k, ne, a, b, bcv, ctypes.byref(n), None, None, None, None, None))
     n = n.value
@@ -121,7 +122,7 @@ class Plan:
     def __init__(self, k: int, ne, box, alpha: float, bc: str = "dirichlet", device=None):
         import torch
         self._p = c_void_p(None)
-        bcv = {"dirichlet": SEM_BC_DIRICHLET, "neumann": SEM_BC_NEUMANN}[bc]
+        bcv = _BC[bc]
         ne_arr = (c_int * 3)(*[int(v) for v in ne])
         box_arr = (c_double * 6)(*[float(v) for v in box])
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)

@@ -351,7 +351,7 @@ static void parallel_rows(int n, int nthreads, F&& fn) {
 // ((k+1)^2, already divided by h): FP64 rounding of K's entries alone would shift
 // the lowest eigenvalues by ~ eps * lambda_max, since they come out of a
 // cancellation of ratio lambda_max / lambda_min.
-static void refine_eigenpairs(int n, int k, int ne, const std::vector<long double>& ke, int off,
+static void refine_eigenpairs(int n, int k, int ne, const std::vector<long double>& ke, int off, bool per,
                               const std::vector<double>& mass, std::vector<double>& lam, std::vector<double>& S,
                               int nthreads) {
   typedef long double ld;
@@ -363,17 +363,21 @@ static void refine_eigenpairs(int n, int k, int ne, const std::vector<long doubl
     for (int p = p0; p < p1; ++p) {
       ld* row = &KX[(size_t)p * n];
       std::fill(row, row + n, 0.0L);
-      const int pf = p + off;  // full-numbering index
-      // elements containing node pf: e = pf / k (as its left/inner node) and pf / k - 1 (as right end)
-      for (int e = std::max(0, (pf - 1) / k); e <= std::min(ne - 1, pf / k); ++e) {
-        const int li = pf - e * k;
-        if (li < 0 || li > k) continue;
-        for (int lj = 0; lj < np; ++lj) {
-          const int qf = e * k + lj, q = qf - off;
-          if (q < 0 || q >= n || qf >= nfull) continue;
-          const ld kv = ke[(size_t)li * np + lj];
-          const ld* xq = &X[(size_t)q * n];
-          for (int j = 0; j < n; ++j) row[j] += kv * xq[j];
+      // periodic: full nodes p and p + n are one unknown (only p = 0 has the alias)
+      for (int alias = 0; alias <= (per ? 1 : 0); ++alias) {
+        const int pf = p + off + alias * n;  // full-numbering index
+        if (pf >= nfull) continue;
+        // elements containing node pf: e = pf / k (as its left/inner node) and pf / k - 1 (as right end)
+        for (int e = std::max(0, (pf - 1) / k); e <= std::min(ne - 1, pf / k); ++e) {
+          const int li = pf - e * k;
+          if (li < 0 || li > k) continue;
+          for (int lj = 0; lj < np; ++lj) {
+            const int qf = e * k + lj, q = per ? qf % n : qf - off;
+            if (q < 0 || q >= n || qf >= nfull) continue;
+            const ld kv = ke[(size_t)li * np + lj];
+            const ld* xq = &X[(size_t)q * n];
+            for (int j = 0; j < n; ++j) row[j] += kv * xq[j];
+          }
         }
       }
     }
@@ -402,7 +406,14 @@ static void refine_eigenpairs(int n, int k, int ne, const std::vector<long doubl
     L[i] = T[(size_t)i * n + i] / (1.0L - R[(size_t)i * n + i]);
     lmax = std::max(lmax, std::fabs(L[i]));
   }
-  const ld tiny = 1e-15L * (lmax > 0 ? lmax : 1.0L);
+  // Pairs closer than tiny keep only the symmetric part of the update (no rotation
+  // inside the pair).  Periodic spectra hold exactly double eigenvalues (Bloch
+  // phases +theta and -theta) and, at phase pi, pairs split only by the
+  // discretisation error (1.4e-10 lambda_max for Q^20 with 10 elements), across
+  // which one Newton step would leave a second-order error (eps lambda_max / gap)^2
+  // in S^T M S; inside such a pair any M-orthonormal basis is accurate to
+  // eps lambda_max in K s - lambda M s.
+  const ld tiny = (per ? 1e-8L : 1e-15L) * (lmax > 0 ? lmax : 1.0L);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
       const size_t ij = (size_t)i * n + j;
@@ -482,9 +493,9 @@ static std::vector<long double> element_stiffness_ld(int k, const std::vector<do
 void build_axis(const AxisSpec& spec, AxisData& out, int nthreads) {
   const int k = spec.k, ne = spec.ne;
   if (k < 1 || ne < 1) throw std::invalid_argument("k >= 1 and ne >= 1 required");
-  const bool dir = spec.dirichlet;
+  const bool dir = spec.dirichlet, per = spec.periodic && !spec.dirichlet;
   const int nfull = ne * k + 1;
-  const int n = dir ? nfull - 2 : nfull;
+  const int n = dir ? nfull - 2 : per ? nfull - 1 : nfull;
   if (n < 1) throw std::invalid_argument("Dirichlet needs ne*k >= 2");
   std::vector<double> xr, wr, D;
   gll_rule(k, xr, wr);
@@ -520,6 +531,12 @@ void build_axis(const AxisSpec& spec, AxisData& out, int nthreads) {
       if (d != k) s += kb[(size_t)g * bw + d];
     kb[(size_t)g * bw + k] = -s;
   }
+  if (per) {
+    // fold the last node onto the first: its row (couplings through offsets
+    // d <= k) adds onto row 0 (couplings through d >= k), its mass onto node 0
+    for (int d = 0; d < bw; ++d) kb[d] += kb[(size_t)(nfull - 1) * bw + d];
+    mf[0] += mf[nfull - 1];
+  }
   const int off = dir ? 1 : 0;
   out.n = n;
   out.k = k;
@@ -527,21 +544,24 @@ void build_axis(const AxisSpec& spec, AxisData& out, int nthreads) {
   out.x.assign(xf.begin() + off, xf.begin() + off + n);
   out.mass.assign(mf.begin() + off, mf.begin() + off + n);
   out.hband.assign((size_t)n * bw, 0.0);
+  auto column = [&](int g, int d) {  // unknown coupled to g through offset d - k, or -1
+    int col = g - k + d;             // in restricted numbering
+    if (per) return ((col % n) + n) % n;
+    return col < 0 || col >= n ? -1 : col;
+  };
   for (int g = 0; g < n; ++g)
-    for (int d = 0; d < bw; ++d) {
-      int col = g - k + d;  // in restricted numbering
-      if (col < 0 || col >= n) continue;
-      out.hband[(size_t)g * bw + d] = kb[(size_t)(g + off) * bw + d] / out.mass[g];
-    }
-  // symmetric S1 = M^{-1/2} K M^{-1/2}, dense
+    for (int d = 0; d < bw; ++d)
+      if (column(g, d) >= 0) out.hband[(size_t)g * bw + d] = kb[(size_t)(g + off) * bw + d] / out.mass[g];
+  // symmetric S1 = M^{-1/2} K M^{-1/2}, dense (periodic offsets that alias one
+  // node add up)
   std::vector<double> mh(n);
   for (int g = 0; g < n; ++g) mh[g] = std::sqrt(out.mass[g]);
   std::vector<double> s1((size_t)n * n, 0.0);
   for (int g = 0; g < n; ++g)
     for (int d = 0; d < bw; ++d) {
-      int col = g - k + d;
-      if (col < 0 || col >= n) continue;
-      s1[(size_t)g * n + col] = kb[(size_t)(g + off) * bw + d] / (mh[g] * mh[col]);
+      const int col = column(g, d);
+      if (col < 0) continue;
+      s1[(size_t)g * n + col] += kb[(size_t)(g + off) * bw + d] / (mh[g] * mh[col]);
     }
   for (int i = 0; i < n; ++i)
     for (int j = i + 1; j < n; ++j) {
@@ -556,7 +576,7 @@ void build_axis(const AxisSpec& spec, AxisData& out, int nthreads) {
     for (int c = 0; c < n; ++c) out.S[(size_t)r * n + c] = s1[(size_t)r * n + c] / mh[r];
   if (n > 1) {
     const std::vector<long double> ke = element_stiffness_ld(k, xr, wr, spec.a, spec.b, ne);
-    refine_eigenpairs(n, k, ne, ke, off, out.mass, out.lam, out.S, nthreads);
+    refine_eigenpairs(n, k, ne, ke, off, per, out.mass, out.lam, out.S, nthreads);
   }
   // forward factor F = S^T M  (= Q^T M^{1/2})
   out.F.assign((size_t)n * n, 0.0);

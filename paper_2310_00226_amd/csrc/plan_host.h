@@ -8,9 +8,10 @@ struct AxisSpec {
   int k;           // polynomial degree
   int ne;          // number of elements
   double a, b;     // interval
-  bool dirichlet;  // homogeneous Dirichlet (true) or Neumann (false)
+  bool dirichlet;         // homogeneous Dirichlet (true) or Neumann / periodic (false)
+  bool periodic = false;  // periodic: the node at b is the node at a (n = ne k)
   bool operator==(const AxisSpec& o) const {
-    return k == o.k && ne == o.ne && a == o.a && b == o.b && dirichlet == o.dirichlet;
+    return k == o.k && ne == o.ne && a == o.a && b == o.b && dirichlet == o.dirichlet && periodic == o.periodic;
   }
 };
 
@@ -20,6 +21,8 @@ struct AxisData {
   std::vector<double> x;      // node coordinates (n)
   std::vector<double> mass;   // lumped mass diagonal (n)
   std::vector<double> hband;  // H = M^{-1} K banded rows: n x (2k+1), entry [g][d] = H(g, g-k+d)
+                              // (periodic: the coupling of node g through offset d - k to node
+                              // (g-k+d) mod n; offsets that alias one node keep separate entries)
   std::vector<double> lam;    // eigenvalues ascending (n)
   std::vector<double> S;      // backward factor S (n x n row-major), K S = M S Lambda, S^T M S = I
   std::vector<double> F;      // forward factor F = S^T M (n x n row-major)

@@ -11,6 +11,10 @@
 // ResidualArgs), which also gives H_3 v alone and the residual of the
 // Cahn-Hilliard operator a I + c H_3^2 in two passes.
 //
+// Periodic conditions (per != 0): H couples node g through offset d - k to node
+// (g - k + d) mod n on every axis; the kernels read v at the wrapped indices
+// (the band rows of the plan hold the wrap-around couplings).
+//
 // HBM-bound: per node it reads v and f and writes r (24 bytes in FP64).  A block
 // owns a (4 y) x (64 z) column of nodes and marches along x: the 2k+1 values of v
 // along x that a node needs sit in a register window (each v value is loaded
@@ -62,7 +66,7 @@ __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restr
                                                            long rplane, const double* __restrict__ hx,
                                                            const double* __restrict__ hy,
                                                            const double* __restrict__ hz, int k, int nx, int ny,
-                                                           int nz, Coef c) {
+                                                           int nz, int per, Coef c) {
   const int bw = 2 * k + 1;
   const long jl = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long plane = (long)ny * nz;
@@ -72,6 +76,15 @@ __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restr
   const int l = (int)(jl - (long)j * nz);
   const size_t idx = (size_t)i * plane + jl;
   double s = 0.0;
+  if (per) {
+    const size_t zrow = idx - l, ycol = idx - (size_t)j * nz;  // node (i, j, 0) and (i, 0, l)
+    const double *rz = hz + (size_t)l * bw, *ry = hy + (size_t)j * bw, *rx = hx + (size_t)i * bw;
+    for (int d = 0; d < bw; ++d) {
+      s += rz[d] * v[zrow + (((l - k + d) % nz) + nz) % nz];
+      s += ry[d] * v[ycol + (size_t)((((j - k + d) % ny) + ny) % ny) * nz];
+      s += rx[d] * v[(size_t)((((i - k + d) % nx) + nx) % nx) * plane + jl];
+    }
+  } else {
   {
     const double* hrow = hz + (size_t)l * bw;
     const int d0 = l - k < 0 ? k - l : 0;
@@ -89,6 +102,7 @@ __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restr
     const int d0 = i - k < 0 ? k - i : 0;
     const int d1 = i + k >= nx ? k + (nx - 1 - i) : 2 * k;
     for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (long)(d - k) * plane];
+  }
   }
   const double dv = (dg ? dg[idx] : v[idx]) * (wt ? c.wa + wt[idx] : 1.0);
   const double fv = f ? f[idx] : 0.0;
@@ -125,7 +139,8 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
                                            TR* __restrict__ r, int ldr, long rplane,
                                            const double* __restrict__ hx, const double* __restrict__ hy,
                                            const double* __restrict__ hz, int nx, int ny, int nz, int xchunk,
-                                           const Coef& c, int bx, int by, int bz, double* __restrict__ lds) {
+                                           bool per, const Coef& c, int bx, int by, int bz,
+                                           double* __restrict__ lds) {
   constexpr int BW = 2 * KH + 1;
   typedef TileGeo<KH> G;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -137,12 +152,18 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
   const int i1 = min(nx, i0 + xchunk);
   const long plane = (long)ny * nz;
   const bool has_f = f != nullptr, has_d = dg != nullptr;  // uniform
-  int jr[RW];
-  bool ok[RW];
+  // ok: the thread's node exists and gets an output; ld: its tile cell holds a
+  // value of v (periodic: every cell, read at the wrapped node); so: the in-plane
+  // offset of that value
+  int jr[RW], so[RW];
+  bool ok[RW], ld[RW];
+  const int ls = per ? l % nz : l;
 #pragma unroll
   for (int q = 0; q < RW; ++q) {
     jr[q] = y0 + RW * wave + q;  // wave-uniform
     ok[q] = lok && jr[q] < ny;
+    ld[q] = per || ok[q];
+    so[q] = ld[q] ? (per ? jr[q] % ny : jr[q]) * nz + ls : 0;
   }
   double cz[BW];
 #pragma unroll
@@ -163,20 +184,27 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       const int cs = sdx % (2 * KH);
       col = cs < KH ? cs : cs + TZ;
     }
-    const int gy = y0 - KH + row, gz = z0 - KH + col;
+    int gy = y0 - KH + row, gz = z0 - KH + col;
+    bool inside = gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+    if (per) {
+      gy = ((gy % ny) + ny) % ny;
+      gz = ((gz % nz) + nz) % nz;
+      inside = true;
+    }
     const bool in = idx < G::HALO;
     hl[h] = in ? row * G::COLS + col : -1;
-    hg[h] = (in && gy >= 0 && gy < ny && gz >= 0 && gz < nz) ? gy * nz + gz : -1;
+    hg[h] = (in && inside) ? gy * nz + gz : -1;
   }
-  auto at = [&](int i, int q) -> size_t { return (size_t)i * plane + (size_t)jr[q] * nz + (lok ? l : 0); };
+  auto at = [&](int i, int q) -> size_t { return (size_t)i * plane + (size_t)so[q]; };
   // x windows: w[q][d] = v[i - KH + d] at (jr[q], l), zero outside the domain
   double w[RW][BW];
 #pragma unroll
   for (int q = 0; q < RW; ++q)
 #pragma unroll
     for (int d = 0; d < BW; ++d) {
-      const int ii = i0 - KH + d;
-      const bool in = ok[q] && ii >= 0 && ii < nx;
+      int ii = i0 - KH + d;
+      if (per) ii = ((ii % nx) + nx) % nx;
+      const bool in = ld[q] && ii >= 0 && ii < nx;
       const double x = v[in ? at(ii, q) : 0];
       w[q][d] = in ? x : 0.0;
     }
@@ -189,10 +217,11 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       const double x = v[(size_t)ic * plane + (hg[h] >= 0 ? hg[h] : 0)];
       hv[h] = hg[h] >= 0 ? x : 0.0;
     }
-    const int inext = i + KH;  // enters the window when plane i - 1 is done
+    int inext = i + KH;  // enters the window when plane i - 1 is done
+    if (per && inext >= nx) inext %= nx;
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
-      const bool in = ok[q] && inext < nx;
+      const bool in = ld[q] && inext < nx;
       const double x = v[in ? at(inext, q) : 0];
       wn[q] = in ? x : 0.0;
       fv[q] = (has_f && ok[q]) ? f[at(ic, q)] : 0.0;
@@ -250,10 +279,10 @@ __global__ __launch_bounds__(RT) void residual_march_kernel(const double* __rest
                                                                   const double* __restrict__ hx,
                                                                   const double* __restrict__ hy,
                                                                   const double* __restrict__ hz, int nx, int ny,
-                                                                  int nz, int xchunk, Coef c) {
+                                                                  int nz, int xchunk, int per, Coef c) {
   __shared__ double lds[2 * TileGeo<KH>::PLANE];
-  march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, c, blockIdx.x, blockIdx.y,
-                     blockIdx.z, lds);
+  march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per != 0, c, blockIdx.x,
+                        blockIdx.y, blockIdx.z, lds);
 }
 
 // Residuals of many solves (same k) in one launch: descriptor i owns blocks
@@ -276,8 +305,7 @@ __global__ __launch_bounds__(RT) void residual_march_batch(const ResDesc* __rest
   const int by = (int)((rb / d.gx) % d.gy);
   const int bz = (int)(rb / ((long)d.gx * d.gy));
   march_body<KH, TR, false>(d.v, d.f, d.d, nullptr, (TR*)d.r, d.ldr, d.rplane, d.hx, d.hy, d.hz, d.nx, d.ny, d.nz,
-                            d.xchunk,
-                     Coef{d.cf, d.cd, d.ch, 0.0}, bx, by, bz, lds);
+                            d.xchunk, d.per != 0, Coef{d.cf, d.cd, d.ch, 0.0}, bx, by, bz, lds);
 }
 
 // x is split into chunks so that the grid fills the chip even for thin (y, z)
@@ -302,12 +330,14 @@ void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], cons
   if constexpr (std::is_same<TR, double>::value) {
     if (ra.wt) {
       residual_march_kernel<KH, TR, true><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
-          ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
+          ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
+          ra.periodic, c);
       return;
     }
   }
   residual_march_kernel<KH, TR, false><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
-      ra.v, ra.f, ra.d, nullptr, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, c);
+      ra.v, ra.f, ra.d, nullptr, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
+      ra.periodic, c);
 }
 
 template <int KH>
@@ -341,8 +371,7 @@ hipError_t launch_typed(const ResidualArgs& ra, TR* r, const double* const hb[3]
       const long plane = (long)dims[1] * dims[2];
       dim3 block(256), grid((unsigned)((plane + 255) / 256), (unsigned)dims[0]);
       residual_any_kernel<TR><<<grid, block, 0, stream>>>(ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1],
-                                                          hb[2],
-                                                          k, dims[0], dims[1], dims[2], c);
+                                                          hb[2], k, dims[0], dims[1], dims[2], ra.periodic, c);
     }
   }
   return hipGetLastError();
@@ -396,6 +425,7 @@ bool residual_desc(const ResidualArgs& ra, const double* const hb[3], int k, con
   d->cf = ra.cf;
   d->cd = ra.cd;
   d->ch = ra.ch;
+  d->per = ra.periodic;
   return true;
 }
 

@@ -95,18 +95,31 @@ extern "C" {
 
 const char* sem_last_error(void) { return g_last_error.c_str(); }
 
+namespace {
+bool valid_bc(sem_bc bc) { return bc == SEM_BC_DIRICHLET || bc == SEM_BC_NEUMANN || bc == SEM_BC_PERIODIC; }
+// unknowns on an axis of ne elements: interior nodes (Dirichlet), all ne k + 1
+// nodes (Neumann), or ne k with the node at b identified with the node at a
+long axis_unknowns(sem_bc bc, long ne, long k) {
+  return bc == SEM_BC_DIRICHLET ? ne * k - 1 : bc == SEM_BC_PERIODIC ? ne * k : ne * k + 1;
+}
+AxisSpec axis_spec(int k, int ne, double a, double b, sem_bc bc) {
+  AxisSpec s{k, ne, a, b, bc == SEM_BC_DIRICHLET};
+  s.periodic = bc == SEM_BC_PERIODIC;
+  return s;
+}
+}  // namespace
+
 sem_status sem_axis_host(int k, int ne, double a, double b, sem_bc bc, int* n, double* x, double* mass, double* lam,
                          double* S, double* F) {
-  if (k < 1 || ne < 1 || !(a < b) || !std::isfinite(a) || !std::isfinite(b) ||
-      (bc != SEM_BC_DIRICHLET && bc != SEM_BC_NEUMANN))
+  if (k < 1 || ne < 1 || !(a < b) || !std::isfinite(a) || !std::isfinite(b) || !valid_bc(bc))
     return fail(SEM_EINVAL, "sem_axis_host: invalid argument");
   if (bc == SEM_BC_DIRICHLET && ne * k < 2) return fail(SEM_EINVAL, "Dirichlet needs ne*k >= 2");
-  const int nn = bc == SEM_BC_DIRICHLET ? ne * k - 1 : ne * k + 1;
+  const int nn = (int)axis_unknowns(bc, ne, k);
   if (n) *n = nn;
   if (!x && !mass && !lam && !S && !F) return SEM_OK;
   try {
     AxisData d;
-    build_axis(AxisSpec{k, ne, a, b, bc == SEM_BC_DIRICHLET}, d, host_threads());
+    build_axis(axis_spec(k, ne, a, b, bc), d, host_threads());
     if (x) std::memcpy(x, d.x.data(), sizeof(double) * nn);
     if (mass) std::memcpy(mass, d.mass.data(), sizeof(double) * nn);
     if (lam) std::memcpy(lam, d.lam.data(), sizeof(double) * nn);
@@ -122,14 +135,14 @@ sem_status sem_plan_create(int k, const int ne[3], const double box[6], double a
   if (!out || !ne || !box) return fail(SEM_EINVAL, "sem_plan_create: null argument");
   *out = nullptr;
   if (k < 1 || k > 64) return fail(SEM_EINVAL, "sem_plan_create: k must be in [1, 64]");
-  if (bc != SEM_BC_DIRICHLET && bc != SEM_BC_NEUMANN) return fail(SEM_EINVAL, "sem_plan_create: bad bc");
+  if (!valid_bc(bc)) return fail(SEM_EINVAL, "sem_plan_create: bad bc");
   if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SEM_EINVAL, "sem_plan_create: alpha must be finite, >= 0");
   long total = 1;
   for (int a = 0; a < 3; ++a) {
     if (ne[a] < 1) return fail(SEM_EINVAL, "sem_plan_create: ne[%d] < 1", a);
     if (!(box[2 * a] < box[2 * a + 1]) || !std::isfinite(box[2 * a]) || !std::isfinite(box[2 * a + 1]))
       return fail(SEM_EINVAL, "sem_plan_create: degenerate box on axis %d", a);
-    const long n = bc == SEM_BC_DIRICHLET ? (long)ne[a] * k - 1 : (long)ne[a] * k + 1;
+    const long n = axis_unknowns(bc, ne[a], k);
     if (n < 1) return fail(SEM_EINVAL, "sem_plan_create: Dirichlet axis %d has no interior node", a);
     if (n > 4096) return fail(SEM_EINVAL, "sem_plan_create: axis %d has %ld > 4096 unknowns", a, n);
     total *= n;
@@ -145,10 +158,10 @@ sem_status sem_plan_create(int k, const int ne[3], const double box[6], double a
   try {
     for (int a = 0; a < 3; ++a) {
       p->ne[a] = ne[a];
-      AxisSpec s{k, ne[a], box[2 * a], box[2 * a + 1], bc == SEM_BC_DIRICHLET};
+      const AxisSpec s = axis_spec(k, ne[a], box[2 * a], box[2 * a + 1], bc);
       int same = -1;
       for (int b = 0; b < a; ++b)
-        if (AxisSpec{k, ne[b], box[2 * b], box[2 * b + 1], bc == SEM_BC_DIRICHLET} == s) same = b;
+        if (axis_spec(k, ne[b], box[2 * b], box[2 * b + 1], bc) == s) same = b;
       if (same >= 0)
         p->ax[a] = p->ax[same];
       else
@@ -295,6 +308,7 @@ sem_status sem_residual(sem_plan* p, const double* u, const double* f, double* r
   if (r == u) return fail(SEM_EINVAL, "sem_residual: r must not alias u");
   const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
   ResidualArgs ra;
+  ra.periodic = p->bc == SEM_BC_PERIODIC;
   ra.v = u;
   ra.f = f;
   ra.r = r;
