@@ -17,6 +17,7 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   schrodinger_apply, pcg_schrodinger                               pinned
   spectral_apply                                                   pinned
   periodic boundary condition (axis_operators, axis_eigen, Problem) pinned
+  lift_boundary                                                    pinned
 """
 from .sem_oracle import (  # noqa: F401
     gll,
@@ -38,5 +39,6 @@ from .sem_oracle import (  # noqa: F401
     schrodinger_apply,
     pcg_schrodinger,
     spectral_apply,
+    lift_boundary,
     rel_max_err,
 )

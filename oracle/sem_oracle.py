@@ -317,6 +317,62 @@ def residual_at(prob: Problem, u: np.ndarray, f: np.ndarray, idx: np.ndarray) ->
     return out
 
 
+
+def _face_shape(shape, axis):
+    return tuple(n for a, n in enumerate(shape) if a != axis)
+
+
+def lift_boundary(prob: Problem, faces) -> np.ndarray:
+    """Correction c with which the homogeneous solve of f + c gives the solution
+    with non-homogeneous boundary data (Sec. 2.1 remark: the data move into the
+    right-hand side, the matrix to invert is unchanged).
+
+    faces[2a], faces[2a + 1] (None: homogeneous) hold the data on the face
+    x_a = box[2a] and x_a = box[2a + 1], as arrays of the plan's shape with axis a
+    removed (the face nodes whose other coordinates are unknowns).
+
+    Dirichlet (data = u on the face): write u = u_0 + u_b with u_b the data on the
+    full grid of ne k + 1 nodes per axis (zero elsewhere); the interior equations
+    of eq. matvec3D become A u_0 = M_3 f - A u_b, i.e. in nodal form
+    c = -(H_x (+) H_y (+) H_z) u_b restricted to the interior, with the full-grid
+    H = M^{-1} K of the Neumann assembly (alpha u_b vanishes inside).
+    Neumann (data = outward normal derivative): the weak form gains the boundary
+    integral of the data times v, by GLL quadrature on the face the face masses
+    times the data; divided by the lumped mass M_3 it is the data over the end
+    node's 1D mass, added on the face's nodes (edges and corners take the
+    contributions of every face they lie on).
+    """
+    c = np.zeros(prob.shape)
+    if prob.bc == "periodic":
+        if any(g is not None for g in faces):
+            raise ValueError("periodic problems have no boundary data")
+        return c
+    if prob.bc == "neumann":
+        for a in range(3):
+            m = prob.axes[a].M
+            for side, end in ((0, 0), (1, -1)):
+                g = faces[2 * a + side]
+                if g is None:
+                    continue
+                g = np.asarray(g, dtype=np.float64).reshape(_face_shape(prob.shape, a))
+                sl = [slice(None)] * 3
+                sl[a] = end
+                c[tuple(sl)] += g / m[end]
+        return c
+    full = [axis_operators(prob.k, prob.ne[a], prob.box[2 * a], prob.box[2 * a + 1], "neumann") for a in range(3)]
+    ub = np.zeros(tuple(o.x.size for o in full))
+    for a in range(3):
+        for side, end in ((0, 0), (1, -1)):
+            g = faces[2 * a + side]
+            if g is None:
+                continue
+            g = np.asarray(g, dtype=np.float64).reshape(_face_shape(prob.shape, a))
+            sl = [slice(1, -1)] * 3
+            sl[a] = end
+            ub[tuple(sl)] = g
+    hub = sum(mode_product(ub, full[a].K / full[a].M[:, None], a) for a in range(3))
+    return -hub[1:-1, 1:-1, 1:-1]
+
 def dense_system(prob: Problem):
     """Assembled dense A = K(x)M(x)M + M(x)K(x)M + M(x)M(x)K + alpha M(x)M(x)M and
     the diagonal of M(x)M(x)M, in the C (x-slowest) ordering (eq. matvec3D)."""
