@@ -285,6 +285,20 @@ __global__ __launch_bounds__(RT) void residual_march_kernel(const double* __rest
                         blockIdx.y, blockIdx.z, lds);
 }
 
+// The same march with at most 128 VGPRs (4 waves per SIMD, two blocks per CU).
+// For k = 5 without the weight it fits without spilling (127 instead of 130
+// VGPRs) and runs 10% faster (6.1 vs 6.8 ms at 1000^3); the weighted k = 5
+// march would spill 44 bytes per lane and gain nothing, k = 4 fits either way.
+template <int KH, class TR>
+__global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4, 8))) void residual_march_kernel_w4(
+    const double* __restrict__ v, const double* __restrict__ f, const double* __restrict__ dg, TR* __restrict__ r,
+    int ldr, long rplane, const double* __restrict__ hx, const double* __restrict__ hy, const double* __restrict__ hz,
+    int nx, int ny, int nz, int xchunk, int per, Coef c) {
+  __shared__ double lds[2 * TileGeo<KH>::PLANE];
+  march_body<KH, TR, false>(v, f, dg, nullptr, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per != 0, c,
+                            blockIdx.x, blockIdx.y, blockIdx.z, lds);
+}
+
 // Residuals of many solves (same k) in one launch: descriptor i owns blocks
 // [block0_i, block0_i + gx * gy * gz) of the grid; inactive solves are skipped.
 template <int KH, class TR>
@@ -335,9 +349,15 @@ void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], cons
       return;
     }
   }
-  residual_march_kernel<KH, TR, false><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
-      ra.v, ra.f, ra.d, nullptr, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
-      ra.periodic, c);
+  if constexpr (KH == 5) {
+    residual_march_kernel_w4<KH, TR><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
+        ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, ra.periodic,
+        c);
+  } else {
+    residual_march_kernel<KH, TR, false><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
+        ra.v, ra.f, ra.d, nullptr, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
+        ra.periodic, c);
+  }
 }
 
 template <int KH>
