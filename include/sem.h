@@ -112,6 +112,27 @@ sem_status sem_mode_product(sem_plan *p, int axis, int inverse, const double *in
  * H = M^{-1} K (eq. matvec3D in H-form), FP64, matrix-free.  r must not alias u. */
 sem_status sem_residual(sem_plan *p, const double *u, const double *f, double *r);
 
+/* Non-homogeneous boundary data (Sec. 2.1 remark: boundary values and fluxes go
+ * to the right-hand side, the matrix to invert stays the same).  Adds to the
+ * nodal right-hand side f (device, plan layout, in place) the terms that carry
+ * the data of the six faces; a following solve of the plan (sem_solve,
+ * sem_solve_refined, a batch) then returns the solution with that data.
+ * g[2a], g[2a+1]: device arrays with the data on the face x_a = box[2a] and
+ * x_a = box[2a+1], row-major over the two other axes in their order (n_y x n_z,
+ * n_x x n_z, n_x x n_y); a NULL face (or g == NULL) is homogeneous.
+ *   Dirichlet plans: the values of u on the face at the nodes whose two other
+ *     coordinates are unknowns (edge and corner values are not needed).  With u_b
+ *     the data on the full grid of ne k + 1 nodes per axis, f += -(H_x + H_y +
+ *     H_z) u_b at the unknowns (the k unknowns next to each face), H = M^{-1} K of
+ *     the full-grid assembly.
+ *   Neumann plans: the outward normal derivative at the face's nodes; by GLL
+ *     quadrature of the boundary integral, f += g / M_a(end node) on the face
+ *     (edges and corners sum the faces they lie on).
+ *   Periodic plans: SEM_EINVAL for any non-NULL face.
+ * Faces must not overlap f (SEM_EINVAL).  Asynchronous on the plan's stream;
+ * the faces of one axis are one launch, the axes are applied in order. */
+sem_status sem_lift_boundary(sem_plan *p, const double *const g[6], double *f);
+
 /* Mixed-precision solve with FP64 iterative refinement:
  *   u = 0, r = f;  repeat  delta = FD_prec(r),  u += delta,  r = f - M_3^{-1} A u
  *   until ||delta||_inf <= tol * ||u||_inf, or until the updates contract fast

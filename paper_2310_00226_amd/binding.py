@@ -44,6 +44,7 @@ def _load():
         "sem_solve": (c_int, [c_void_p, c_void_p, c_void_p]),
         "sem_mode_product": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
         "sem_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "sem_lift_boundary": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_void_p]),
         "sem_solve_refined": (c_int, [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, POINTER(c_int),
                                       POINTER(c_double)]),
         "sem_solve_lowp": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
@@ -272,6 +273,25 @@ class Plan:
         self._prepare(SEM_F64)
         check(lib.sem_residual(self._p, a, b, c))
         return r
+
+    def lift_boundary(self, faces, f):
+        """Add the terms of non-homogeneous boundary data to the right-hand side f
+        in place (sem_lift_boundary); faces: six tensors or None, face 2a / 2a+1 of
+        the shape of the plan without axis a.  Returns f."""
+        import torch
+        if len(faces) != 6:
+            raise ValueError("faces: expected six entries (x lower, x upper, y lower, ...)")
+        fp = _dev_ptr(f, "f", self.numel, torch.float64)
+        arr = (c_void_p * 6)()
+        for i, g in enumerate(faces):
+            if g is None:
+                continue
+            a = i // 2
+            m = self.numel // self.shape[a]
+            arr[i] = _dev_ptr(g, f"faces[{i}]", m, torch.float64).value
+        check(lib.sem_plan_set_stream(self._p, c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+        check(lib.sem_lift_boundary(self._p, arr, fp))
+        return f
 
 
 class CahnHilliard:

@@ -531,6 +531,21 @@ void build_axis(const AxisSpec& spec, AxisData& out, int nthreads) {
       if (d != k) s += kb[(size_t)g * bw + d];
     kb[(size_t)g * bw + k] = -s;
   }
+  if (dir) {
+    // Dirichlet data at the removed end nodes: unknown d (full node d + 1) couples to
+    // full node 0 through offset k - d - 1; unknown n-1-d (full n - d) to full node
+    // n + 1 through offset k + d + 1
+    const int depth = std::min(k, n);
+    out.lift_lo.assign(depth, 0.0);
+    out.lift_hi.assign(depth, 0.0);
+    for (int d = 0; d < depth; ++d) {
+      out.lift_lo[d] = -kb[(size_t)(d + 1) * bw + (k - d - 1)] / mf[d + 1];
+      out.lift_hi[d] = -kb[(size_t)(n - d) * bw + (k + d + 1)] / mf[n - d];
+    }
+  } else if (!per) {
+    out.lift_lo.assign(1, 1.0 / mf[0]);
+    out.lift_hi.assign(1, 1.0 / mf[nfull - 1]);
+  }
   if (per) {
     // fold the last node onto the first: its row (couplings through offsets
     // d <= k) adds onto row 0 (couplings through d >= k), its mass onto node 0

@@ -23,6 +23,11 @@ struct AxisData {
   std::vector<double> hband;  // H = M^{-1} K banded rows: n x (2k+1), entry [g][d] = H(g, g-k+d)
                               // (periodic: the coupling of node g through offset d - k to node
                               // (g-k+d) mod n; offsets that alias one node keep separate entries)
+  // non-homogeneous boundary data: the nodal right-hand side gains lift_lo[d] g_lo
+  // at unknown d and lift_hi[d] g_hi at unknown n-1-d (Dirichlet: -H(d, end node)
+  // of the full-grid assembly for the min(k, n) unknowns next to each end;
+  // Neumann: 1 / M at the end node; periodic: none)
+  std::vector<double> lift_lo, lift_hi;
   std::vector<double> lam;    // eigenvalues ascending (n)
   std::vector<double> S;      // backward factor S (n x n row-major), K S = M S Lambda, S^T M S = I
   std::vector<double> F;      // forward factor F = S^T M (n x n row-major)
