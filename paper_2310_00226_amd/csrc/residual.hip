@@ -165,9 +165,19 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
     ld[q] = per || ok[q];
     so[q] = ld[q] ? (per ? jr[q] % ny : jr[q]) * nz + ls : 0;
   }
-  double cz[BW];
+  // z-band coefficients of the thread's column: registers, or (weighted variant,
+  // whose registers would otherwise hold one block per CU) an LDS row per lane
+  // after the two plane tiles, written by wave 0 before the first barrier
+  double cz[W ? 1 : BW];
+  double* __restrict__ czl = lds + 2 * G::PLANE;
+  if constexpr (W) {
+    if (wave == 0)
 #pragma unroll
-  for (int d = 0; d < BW; ++d) cz[d] = lok ? hz[(size_t)l * BW + d] : 0.0;
+      for (int d = 0; d < BW; ++d) czl[d * 64 + lane] = lok ? hz[(size_t)l * BW + d] : 0.0;
+  } else {
+#pragma unroll
+    for (int d = 0; d < BW; ++d) cz[d] = lok ? hz[(size_t)l * BW + d] : 0.0;
+  }
   // halo cells of this thread: LDS index and in-plane global offset (-1: outside)
   int hl[G::NH], hg[G::NH];
 #pragma unroll
@@ -256,7 +266,8 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       for (int d = 0; d < BW; ++d) {
         s += hxr[d] * w[q][d];
         s += hyr[d] * T[(rc - KH + d) * G::COLS + KH + lane];
-        s += cz[d] * T[rc * G::COLS + lane + d];
+        if constexpr (W) s += czl[d * 64 + lane] * T[rc * G::COLS + lane + d];
+        else s += cz[d] * T[rc * G::COLS + lane + d];
       }
       if (ok[q]) {
         const size_t row0 = ((size_t)i * ny + jr[q]) * ldr;
@@ -280,7 +291,7 @@ __global__ __launch_bounds__(RT) void residual_march_kernel(const double* __rest
                                                                   const double* __restrict__ hy,
                                                                   const double* __restrict__ hz, int nx, int ny,
                                                                   int nz, int xchunk, int per, Coef c) {
-  __shared__ double lds[2 * TileGeo<KH>::PLANE];
+  __shared__ double lds[2 * TileGeo<KH>::PLANE + (W ? (2 * KH + 1) * 64 : 0)];
   march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per != 0, c, blockIdx.x,
                         blockIdx.y, blockIdx.z, lds);
 }
@@ -289,14 +300,15 @@ __global__ __launch_bounds__(RT) void residual_march_kernel(const double* __rest
 // For k = 5 without the weight it fits without spilling (127 instead of 130
 // VGPRs) and runs 10% faster (6.1 vs 6.8 ms at 1000^3); the weighted k = 5
 // march would spill 44 bytes per lane and gain nothing, k = 4 fits either way.
-template <int KH, class TR>
+template <int KH, class TR, bool W>
 __global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4, 8))) void residual_march_kernel_w4(
-    const double* __restrict__ v, const double* __restrict__ f, const double* __restrict__ dg, TR* __restrict__ r,
-    int ldr, long rplane, const double* __restrict__ hx, const double* __restrict__ hy, const double* __restrict__ hz,
-    int nx, int ny, int nz, int xchunk, int per, Coef c) {
-  __shared__ double lds[2 * TileGeo<KH>::PLANE];
-  march_body<KH, TR, false>(v, f, dg, nullptr, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per != 0, c,
-                            blockIdx.x, blockIdx.y, blockIdx.z, lds);
+    const double* __restrict__ v, const double* __restrict__ f, const double* __restrict__ dg,
+    const double* __restrict__ wt, TR* __restrict__ r, int ldr, long rplane, const double* __restrict__ hx,
+    const double* __restrict__ hy, const double* __restrict__ hz, int nx, int ny, int nz, int xchunk, int per,
+    Coef c) {
+  __shared__ double lds[2 * TileGeo<KH>::PLANE + (W ? (2 * KH + 1) * 64 : 0)];
+  march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per != 0, c, blockIdx.x,
+                        blockIdx.y, blockIdx.z, lds);
 }
 
 // Residuals of many solves (same k) in one launch: descriptor i owns blocks
@@ -343,16 +355,21 @@ void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], cons
   // solver) has its own instantiation, so that the others keep their registers
   if constexpr (std::is_same<TR, double>::value) {
     if (ra.wt) {
-      residual_march_kernel<KH, TR, true><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
-          ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
-          ra.periodic, c);
+      if constexpr (KH == 5)
+        residual_march_kernel_w4<KH, TR, true><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
+            ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
+            ra.periodic, c);
+      else
+        residual_march_kernel<KH, TR, true><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
+            ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
+            ra.periodic, c);
       return;
     }
   }
   if constexpr (KH == 5) {
-    residual_march_kernel_w4<KH, TR><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
-        ra.v, ra.f, ra.d, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk, ra.periodic,
-        c);
+    residual_march_kernel_w4<KH, TR, false><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
+        ra.v, ra.f, ra.d, nullptr, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
+        ra.periodic, c);
   } else {
     residual_march_kernel<KH, TR, false><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
         ra.v, ra.f, ra.d, nullptr, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
