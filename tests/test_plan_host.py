@@ -112,3 +112,35 @@ def test_plan_periodic_band_rows(P):
         o = O.axis_operators(k, ne, 0.0, 1.0, "periodic")
         h = d["S"] @ np.diag(d["lam"]) @ d["F"]
         np.testing.assert_allclose(h, o.K / o.M[:, None], rtol=0, atol=1e-11 * np.max(np.abs(o.K / o.M[:, None])))
+
+
+def _create(P, k, ne, box, alpha, bc):
+    """sem_plan_create through the raw C ABI: argument checks and the singularity
+    test run on the host before any device call."""
+    lib = ctypes.CDLL(P.binding.LIB_PATH)
+    lib.sem_plan_create.restype = ctypes.c_int
+    p = ctypes.c_void_p(None)
+    st = lib.sem_plan_create(ctypes.c_int(k), (ctypes.c_int * 3)(*ne), (ctypes.c_double * 6)(*box),
+                             ctypes.c_double(alpha), ctypes.c_int(bc), ctypes.byref(p))
+    return st, p
+
+
+@pytest.mark.parametrize("k,ne,bc,why", [
+    (6, (683, 1, 1), 0, "Dirichlet axis of 6 * 683 - 1 = 4097 unknowns"),
+    (4, (1024, 1, 1), 1, "Neumann axis of 4097 unknowns"),
+    (8, (513, 2, 2), 2, "periodic axis of 4104 unknowns"),
+    (65, (1, 1, 1), 1, "k > 64"),
+    (4, (2, 2, 2), 3, "unknown boundary condition"),
+    (4, (0, 2, 2), 1, "no element"),
+    (1, (1, 2, 2), 0, "Dirichlet axis without an interior node"),
+])
+def test_plan_create_rejects_before_device_use(P, k, ne, bc, why):
+    st, p = _create(P, k, ne, (0.0, 1.0) * 3, 1.0, bc)
+    assert st == 1 and not p.value, why  # SEM_EINVAL, no plan
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+def test_plan_create_singular_without_shift(P, bc):
+    """Neumann and periodic with alpha = 0: the constants are in the kernel."""
+    st, p = _create(P, 3, (2, 2, 2), (0.0, 1.0) * 3, 0.0, bc)
+    assert st == 4 and not p.value  # SEM_ESINGULAR
