@@ -91,10 +91,6 @@ sem_status plan_workspace(sem_plan* p, size_t need, void** out) {
 
 }  // namespace semfd
 
-extern "C" {
-
-const char* sem_last_error(void) { return g_last_error.c_str(); }
-
 namespace {
 bool valid_bc(sem_bc bc) { return bc == SEM_BC_DIRICHLET || bc == SEM_BC_NEUMANN || bc == SEM_BC_PERIODIC; }
 // unknowns on an axis of ne elements: interior nodes (Dirichlet), all ne k + 1
@@ -108,6 +104,11 @@ AxisSpec axis_spec(int k, int ne, double a, double b, sem_bc bc) {
   return s;
 }
 }  // namespace
+
+extern "C" {
+
+const char* sem_last_error(void) { return g_last_error.c_str(); }
+
 
 sem_status sem_axis_host(int k, int ne, double a, double b, sem_bc bc, int* n, double* x, double* mass, double* lam,
                          double* S, double* F) {
