@@ -471,6 +471,10 @@ def main() -> int:
         "variants": variants,
         "data": "synthetic: f = (3 pi^2 + 1) sin(pi x) sin(pi y) sin(pi z) + 1e-3 N(0,1), seed 2310",
         "config": {"workload": f"Q^4 SEM Helmholtz alpha=1, Dirichlet [-1,1]^3, {ne[0]}^3 elements, "
+                               f"n={nx} per axis ({N} unknowns), fast-diagonalisation solve to 1e-10 relative "
+                               f"error: {best.split('_')[0]} mode products with FP64 refinement"
+                               if best != "f64" else
+                               f"Q^4 SEM Helmholtz alpha=1, Dirichlet [-1,1]^3, {ne[0]}^3 elements, "
                                f"n={nx} per axis ({N} unknowns), FP64 fast-diagonalisation solve",
                    "k": k, "elements_per_axis": ne[0], "n": nx, "unknowns": N, "alpha": alpha},
         "solve_tflops": solve_tflops,
