@@ -18,6 +18,7 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   spectral_apply                                                   pinned
   periodic boundary condition (axis_operators, axis_eigen, Problem) pinned
   lift_boundary                                                    pinned
+  per-axis boundary conditions (Problem with three conditions)     pinned
 """
 from .sem_oracle import (  # noqa: F401
     gll,

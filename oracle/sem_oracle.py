@@ -206,23 +206,29 @@ def _axis_eigen_cached(k, ne, a, b, bc):
 
 
 class Problem:
-    """-Lap u + alpha u = f on a box with homogeneous Dirichlet or Neumann BCs,
-    Q^k SEM with ne[a] elements on axis a (Sec. 2, eq. pde / matvec3D)."""
+    """-Lap u + alpha u = f on a box, Q^k SEM with ne[a] elements on axis a
+    (Sec. 2, eq. pde / matvec3D), with homogeneous Dirichlet, homogeneous Neumann
+    or periodic conditions: one kind for every axis (bc a string), or one per
+    axis (bc a sequence of three; the operators are Kronecker sums of per-axis
+    1D operators, so each axis carries its own condition, Sec. 2.4 remark)."""
 
-    def __init__(self, k: int, ne, box, alpha: float, bc: str, eigen: bool = True):
+    def __init__(self, k: int, ne, box, alpha: float, bc, eigen: bool = True):
         """eigen=False builds only the 1D operators (enough for residuals)."""
         self.k = int(k)
         self.ne = tuple(int(v) for v in ne)
         self.box = tuple(float(v) for v in box)
         self.alpha = float(alpha)
         self.bc = bc
+        self.bcs = (bc,) * 3 if isinstance(bc, str) else tuple(bc)
+        if len(self.bcs) != 3:
+            raise ValueError(bc)
         if eigen:
-            pairs = [_axis_eigen_cached(self.k, self.ne[a], self.box[2 * a], self.box[2 * a + 1], bc)
+            pairs = [_axis_eigen_cached(self.k, self.ne[a], self.box[2 * a], self.box[2 * a + 1], self.bcs[a])
                      for a in range(3)]
             self.axes = [p[0] for p in pairs]
             self.eig = [p[1] for p in pairs]
         else:
-            self.axes = [axis_operators(self.k, self.ne[a], self.box[2 * a], self.box[2 * a + 1], bc)
+            self.axes = [axis_operators(self.k, self.ne[a], self.box[2 * a], self.box[2 * a + 1], self.bcs[a])
                          for a in range(3)]
             self.eig = None
 
@@ -331,47 +337,42 @@ def lift_boundary(prob: Problem, faces) -> np.ndarray:
     x_a = box[2a] and x_a = box[2a + 1], as arrays of the plan's shape with axis a
     removed (the face nodes whose other coordinates are unknowns).
 
-    Dirichlet (data = u on the face): write u = u_0 + u_b with u_b the data on the
-    full grid of ne k + 1 nodes per axis (zero elsewhere); the interior equations
-    of eq. matvec3D become A u_0 = M_3 f - A u_b, i.e. in nodal form
-    c = -(H_x (+) H_y (+) H_z) u_b restricted to the interior, with the full-grid
-    H = M^{-1} K of the Neumann assembly (alpha u_b vanishes inside).
-    Neumann (data = outward normal derivative): the weak form gains the boundary
-    integral of the data times v, by GLL quadrature on the face the face masses
-    times the data; divided by the lumped mass M_3 it is the data over the end
-    node's 1D mass, added on the face's nodes (edges and corners take the
+    Dirichlet axis a (data = u on the face): write u = u_0 + u_b with u_b the data
+    at the face nodes of the full grid (ne k + 1 nodes on axis a, zero elsewhere);
+    the equations at the unknowns become A u_0 = M_3 f - A u_b, i.e. in nodal
+    form c = -(H_x (+) H_y (+) H_z) u_b at the unknowns, H = M^{-1} K of the
+    full-grid (Neumann) assembly; alpha u_b vanishes there and so do the other
+    axes' terms (they keep the coordinate x_a, and x_a = an end is no unknown),
+    leaving c = -H_a(unknowns, end node) g along axis a.
+    Neumann axis a (data = outward normal derivative): the weak form gains the
+    boundary integral of the data times v, by GLL quadrature on the face the face
+    masses times the data; divided by the lumped mass M_3 it is the data over
+    the end node's 1D mass, added on the face's nodes (edges and corners take the
     contributions of every face they lie on).
+    Periodic axes have no faces.
     """
     c = np.zeros(prob.shape)
-    if prob.bc == "periodic":
-        if any(g is not None for g in faces):
-            raise ValueError("periodic problems have no boundary data")
-        return c
-    if prob.bc == "neumann":
-        for a in range(3):
-            m = prob.axes[a].M
-            for side, end in ((0, 0), (1, -1)):
-                g = faces[2 * a + side]
-                if g is None:
-                    continue
-                g = np.asarray(g, dtype=np.float64).reshape(_face_shape(prob.shape, a))
-                sl = [slice(None)] * 3
-                sl[a] = end
-                c[tuple(sl)] += g / m[end]
-        return c
-    full = [axis_operators(prob.k, prob.ne[a], prob.box[2 * a], prob.box[2 * a + 1], "neumann") for a in range(3)]
-    ub = np.zeros(tuple(o.x.size for o in full))
     for a in range(3):
-        for side, end in ((0, 0), (1, -1)):
+        bc = prob.bcs[a]
+        if all(faces[2 * a + s] is None for s in (0, 1)):
+            continue
+        if bc == "periodic":
+            raise ValueError("a periodic axis has no boundary data")
+        if bc == "neumann":
+            col = np.zeros((prob.shape[a], 2))
+            col[0, 0] = 1.0 / prob.axes[a].M[0]
+            col[-1, 1] = 1.0 / prob.axes[a].M[-1]
+        else:
+            full = axis_operators(prob.k, prob.ne[a], prob.box[2 * a], prob.box[2 * a + 1], "neumann")
+            hfull = full.K / full.M[:, None]
+            col = -hfull[1:-1][:, [0, -1]]
+        for side in (0, 1):
             g = faces[2 * a + side]
             if g is None:
                 continue
             g = np.asarray(g, dtype=np.float64).reshape(_face_shape(prob.shape, a))
-            sl = [slice(1, -1)] * 3
-            sl[a] = end
-            ub[tuple(sl)] = g
-    hub = sum(mode_product(ub, full[a].K / full[a].M[:, None], a) for a in range(3))
-    return -hub[1:-1, 1:-1, 1:-1]
+            c += np.moveaxis(np.multiply.outer(col[:, side], g), 0, a)
+    return c
 
 def dense_system(prob: Problem):
     """Assembled dense A = K(x)M(x)M + M(x)K(x)M + M(x)M(x)K + alpha M(x)M(x)M and
