@@ -79,6 +79,16 @@ typedef enum {
  * with alpha = 0: the constants are in the kernel).
  * Synchronous.  The plan owns its factor storage (a few MB) until destroyed. */
 sem_status sem_plan_create(int k, const int ne[3], const double box[6], double alpha, sem_bc bc, sem_plan **out);
+
+/* As sem_plan_create with one boundary condition per axis (bc[a] on both faces of
+ * axis a): the operators are Kronecker sums of per-axis 1D operators, so each
+ * axis carries its own condition (Sec. 2.4 remark), e.g. periodic in x and z
+ * with Dirichlet walls in y.  n_a follows bc[a]; SEM_ESINGULAR when no axis
+ * removes the constants (no Dirichlet axis) and alpha = 0.  Every call that
+ * takes a plan accepts such plans; sem_lift_boundary takes data on the faces of
+ * the Dirichlet and Neumann axes. */
+sem_status sem_plan_create_mixed(int k, const int ne[3], const double box[6], double alpha, const sem_bc bc[3],
+                                 sem_plan **out);
 void sem_plan_destroy(sem_plan *p);
 
 /* n[a] = number of unknowns per axis. */

@@ -34,6 +34,7 @@ def _load():
     dp = POINTER(c_double)
     sig = {
         "sem_plan_create": (c_int, [c_int, POINTER(c_int), dp, c_double, c_int, POINTER(c_void_p)]),
+        "sem_plan_create_mixed": (c_int, [c_int, POINTER(c_int), dp, c_double, POINTER(c_int), POINTER(c_void_p)]),
         "sem_plan_destroy": (None, [c_void_p]),
         "sem_plan_dims": (c_int, [c_void_p, POINTER(c_int)]),
         "sem_plan_nodes": (c_int, [c_void_p, c_int, dp]),
@@ -123,12 +124,15 @@ class Plan:
     def __init__(self, k: int, ne, box, alpha: float, bc: str = "dirichlet", device=None):
         import torch
         self._p = c_void_p(None)
-        bcv = _BC[bc]
+        bcs = (bc,) * 3 if isinstance(bc, str) else tuple(bc)
+        if len(bcs) != 3:
+            raise ValueError("bc: one name or one per axis")
+        bc_arr = (c_int * 3)(*[_BC[b] for b in bcs])
         ne_arr = (c_int * 3)(*[int(v) for v in ne])
         box_arr = (c_double * 6)(*[float(v) for v in box])
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         with torch.cuda.device(self.device):
-            check(lib.sem_plan_create(int(k), ne_arr, box_arr, float(alpha), bcv, ctypes.byref(self._p)))
+            check(lib.sem_plan_create_mixed(int(k), ne_arr, box_arr, float(alpha), bc_arr, ctypes.byref(self._p)))
         self.k, self.ne, self.box, self.alpha, self.bc = int(k), tuple(ne), tuple(box), float(alpha), bc
         dims = (c_int * 3)()
         check(lib.sem_plan_dims(self._p, dims))

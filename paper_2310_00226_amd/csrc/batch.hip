@@ -190,7 +190,7 @@ sem_status build_descs(sem_batch* b, const double* const* f, double* const* u, c
       sem_plan* p = b->plans[i];
       if (p->k != k || skip[i]) continue;
       ResidualArgs ra;
-      ra.periodic = p->bc == SEM_BC_PERIODIC;
+      ra.periodic = p->per_mask;
       ra.v = u ? u[i] : nullptr;
       ra.f = f ? f[i] : nullptr;
       ra.r = b->lw[i].r;
@@ -317,7 +317,7 @@ hipError_t split_iteration(sem_batch* b, int i, int it, const double* f, double*
   hipError_t e = hipSuccess;
   if (it > 0) {
     ResidualArgs ra;  // r = f - alpha u - H_3 u
-    ra.periodic = p->bc == SEM_BC_PERIODIC;
+    ra.periodic = p->per_mask;
     ra.v = u;
     ra.f = f;
     ra.r = w.r;

@@ -60,8 +60,8 @@ extern "C" sem_status sem_lift_boundary(sem_plan* p, const double* const g[6], d
     const double* lo = g[2 * a];
     const double* hi = g[2 * a + 1];
     if (!lo && !hi) continue;
-    if (p->bc == SEM_BC_PERIODIC)
-      return set_error(SEM_EINVAL, "sem_lift_boundary: a periodic plan has no boundary data");
+    if (p->bc[a] == SEM_BC_PERIODIC)
+      return set_error(SEM_EINVAL, "sem_lift_boundary: a periodic axis has no boundary data");
     const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
     const long count = (long)n[b1] * n[b2];
     if ((lo && overlaps(lo, count, f, p->N)) || (hi && overlaps(hi, count, f, p->N)))

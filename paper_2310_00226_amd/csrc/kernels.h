@@ -144,7 +144,7 @@ struct ResidualArgs {
   int ldr = 0;
   long rplane = 0;
   double cf = 1.0, cd = 0.0, ch = 1.0;
-  int periodic = 0;  // periodic conditions on every axis: neighbours wrap around
+  int periodic = 0;  // bit a set: axis a is periodic (its neighbours wrap around)
 };
 hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], int k, const int dims[3],
                            hipStream_t stream);
@@ -165,7 +165,7 @@ struct ResDesc {
   int ldr = 0, nx = 0, ny = 0, nz = 0, xchunk = 0, gx = 0, gy = 0, gz = 0;
   int sid = 0;
   double cf = 1.0, cd = 0.0, ch = 1.0;
-  int per = 0;  // periodic conditions (neighbours wrap around)
+  int per = 0;  // bit a set: axis a is periodic (neighbours wrap around)
 };
 // Fill the geometry and operands of one descriptor (block0 and sid are the
 // caller's); false if k or the arguments are outside what the batch kernel takes.

@@ -207,7 +207,7 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
   };
   // q = A p = (alpha + V) p + H_3 p
   ResidualArgs ra;
-  ra.periodic = p->bc == SEM_BC_PERIODIC;
+  ra.periodic = p->per_mask;
   ra.v = w.p;
   ra.f = nullptr;
   ra.wt = v;

@@ -16,7 +16,8 @@ struct sem_plan {
   int ld[3] = {0, 0, 0};  // padded factor dimension (multiple of 128)
   double box[6] = {0, 0, 0, 0, 0, 0};
   double alpha = 0.0;
-  sem_bc bc = SEM_BC_DIRICHLET;
+  sem_bc bc[3] = {SEM_BC_DIRICHLET, SEM_BC_DIRICHLET, SEM_BC_DIRICHLET};  // per axis
+  int per_mask = 0;  // bit a set: axis a is periodic
   size_t N = 0;
   semfd::AxisData ax[3];
   // FP64 device data

@@ -319,7 +319,7 @@ extern "C" sem_status sem_solve_refined(sem_plan* p, sem_prec prec, double tol, 
   const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
   const Spectral sp{p->alpha, 1.0, 0.0};
   ResidualArgs ra;  // r = f - alpha u - H_3 u in the intermediate format
-  ra.periodic = p->bc == SEM_BC_PERIODIC;
+  ra.periodic = p->per_mask;
   ra.v = u;
   ra.f = f;
   ra.r = w.r;

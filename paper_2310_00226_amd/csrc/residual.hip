@@ -11,9 +11,9 @@
 // ResidualArgs), which also gives H_3 v alone and the residual of the
 // Cahn-Hilliard operator a I + c H_3^2 in two passes.
 //
-// Periodic conditions (per != 0): H couples node g through offset d - k to node
-// (g - k + d) mod n on every axis; the kernels read v at the wrapped indices
-// (the band rows of the plan hold the wrap-around couplings).
+// Periodic conditions (bit a of `per` for axis a): H_a couples node g through
+// offset d - k to node (g - k + d) mod n_a; the kernels read v at the wrapped
+// indices along that axis (the plan's band rows hold the wrap-around couplings).
 //
 // HBM-bound: per node it reads v and f and writes r (24 bytes in FP64).  A block
 // owns a (4 y) x (64 z) column of nodes and marches along x: the 2k+1 values of v
@@ -76,33 +76,37 @@ __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restr
   const int l = (int)(jl - (long)j * nz);
   const size_t idx = (size_t)i * plane + jl;
   double s = 0.0;
-  if (per) {
-    const size_t zrow = idx - l, ycol = idx - (size_t)j * nz;  // node (i, j, 0) and (i, 0, l)
-    const double *rz = hz + (size_t)l * bw, *ry = hy + (size_t)j * bw, *rx = hx + (size_t)i * bw;
-    for (int d = 0; d < bw; ++d) {
-      s += rz[d] * v[zrow + (((l - k + d) % nz) + nz) % nz];
-      s += ry[d] * v[ycol + (size_t)((((j - k + d) % ny) + ny) % ny) * nz];
-      s += rx[d] * v[(size_t)((((i - k + d) % nx) + nx) % nx) * plane + jl];
-    }
-  } else {
   {
     const double* hrow = hz + (size_t)l * bw;
-    const int d0 = l - k < 0 ? k - l : 0;
-    const int d1 = l + k >= nz ? k + (nz - 1 - l) : 2 * k;
-    for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (d - k)];
+    if (per & 4) {
+      const size_t zrow = idx - l;  // node (i, j, 0)
+      for (int d = 0; d < bw; ++d) s += hrow[d] * v[zrow + (((l - k + d) % nz) + nz) % nz];
+    } else {
+      const int d0 = l - k < 0 ? k - l : 0;
+      const int d1 = l + k >= nz ? k + (nz - 1 - l) : 2 * k;
+      for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (d - k)];
+    }
   }
   {
     const double* hrow = hy + (size_t)j * bw;
-    const int d0 = j - k < 0 ? k - j : 0;
-    const int d1 = j + k >= ny ? k + (ny - 1 - j) : 2 * k;
-    for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (long)(d - k) * nz];
+    if (per & 2) {
+      const size_t ycol = idx - (size_t)j * nz;  // node (i, 0, l)
+      for (int d = 0; d < bw; ++d) s += hrow[d] * v[ycol + (size_t)((((j - k + d) % ny) + ny) % ny) * nz];
+    } else {
+      const int d0 = j - k < 0 ? k - j : 0;
+      const int d1 = j + k >= ny ? k + (ny - 1 - j) : 2 * k;
+      for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (long)(d - k) * nz];
+    }
   }
   {
     const double* hrow = hx + (size_t)i * bw;
-    const int d0 = i - k < 0 ? k - i : 0;
-    const int d1 = i + k >= nx ? k + (nx - 1 - i) : 2 * k;
-    for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (long)(d - k) * plane];
-  }
+    if (per & 1) {
+      for (int d = 0; d < bw; ++d) s += hrow[d] * v[(size_t)((((i - k + d) % nx) + nx) % nx) * plane + jl];
+    } else {
+      const int d0 = i - k < 0 ? k - i : 0;
+      const int d1 = i + k >= nx ? k + (nx - 1 - i) : 2 * k;
+      for (int d = d0; d <= d1; ++d) s += hrow[d] * v[idx + (long)(d - k) * plane];
+    }
   }
   const double dv = (dg ? dg[idx] : v[idx]) * (wt ? c.wa + wt[idx] : 1.0);
   const double fv = f ? f[idx] : 0.0;
@@ -139,7 +143,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
                                            TR* __restrict__ r, int ldr, long rplane,
                                            const double* __restrict__ hx, const double* __restrict__ hy,
                                            const double* __restrict__ hz, int nx, int ny, int nz, int xchunk,
-                                           bool per, const Coef& c, int bx, int by, int bz,
+                                           int per, const Coef& c, int bx, int by, int bz,
                                            double* __restrict__ lds) {
   constexpr int BW = 2 * KH + 1;
   typedef TileGeo<KH> G;
@@ -157,13 +161,14 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
   // offset of that value
   int jr[RW], so[RW];
   bool ok[RW], ld[RW];
-  const int ls = per ? l % nz : l;
+  const bool px = per & 1, py = per & 2, pz = per & 4;  // uniform
+  const int ls = pz ? l % nz : l;
 #pragma unroll
   for (int q = 0; q < RW; ++q) {
     jr[q] = y0 + RW * wave + q;  // wave-uniform
     ok[q] = lok && jr[q] < ny;
-    ld[q] = per || ok[q];
-    so[q] = ld[q] ? (per ? jr[q] % ny : jr[q]) * nz + ls : 0;
+    ld[q] = (lok || pz) && (jr[q] < ny || py);
+    so[q] = ld[q] ? (py ? jr[q] % ny : jr[q]) * nz + ls : 0;
   }
   // z-band coefficients of the thread's column: registers, or (weighted variant,
   // whose registers would otherwise hold one block per CU) an LDS row per lane
@@ -195,12 +200,9 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       col = cs < KH ? cs : cs + TZ;
     }
     int gy = y0 - KH + row, gz = z0 - KH + col;
-    bool inside = gy >= 0 && gy < ny && gz >= 0 && gz < nz;
-    if (per) {
-      gy = ((gy % ny) + ny) % ny;
-      gz = ((gz % nz) + nz) % nz;
-      inside = true;
-    }
+    if (py) gy = ((gy % ny) + ny) % ny;
+    if (pz) gz = ((gz % nz) + nz) % nz;
+    const bool inside = gy >= 0 && gy < ny && gz >= 0 && gz < nz;
     const bool in = idx < G::HALO;
     hl[h] = in ? row * G::COLS + col : -1;
     hg[h] = (in && inside) ? gy * nz + gz : -1;
@@ -213,7 +215,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
 #pragma unroll
     for (int d = 0; d < BW; ++d) {
       int ii = i0 - KH + d;
-      if (per) ii = ((ii % nx) + nx) % nx;
+      if (px) ii = ((ii % nx) + nx) % nx;
       const bool in = ld[q] && ii >= 0 && ii < nx;
       const double x = v[in ? at(ii, q) : 0];
       w[q][d] = in ? x : 0.0;
@@ -228,7 +230,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       hv[h] = hg[h] >= 0 ? x : 0.0;
     }
     int inext = i + KH;  // enters the window when plane i - 1 is done
-    if (per && inext >= nx) inext %= nx;
+    if (px && inext >= nx) inext %= nx;
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
       const bool in = ld[q] && inext < nx;
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(RT) void residual_march_kernel(const double* __rest
                                                                   const double* __restrict__ hz, int nx, int ny,
                                                                   int nz, int xchunk, int per, Coef c) {
   __shared__ double lds[2 * TileGeo<KH>::PLANE + (W ? (2 * KH + 1) * 64 : 0)];
-  march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per != 0, c, blockIdx.x,
+  march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per, c, blockIdx.x,
                         blockIdx.y, blockIdx.z, lds);
 }
 
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const double* __restrict__ hy, const double* __restrict__ hz, int nx, int ny, int nz, int xchunk, int per,
     Coef c) {
   __shared__ double lds[2 * TileGeo<KH>::PLANE + (W ? (2 * KH + 1) * 64 : 0)];
-  march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per != 0, c, blockIdx.x,
+  march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per, c, blockIdx.x,
                         blockIdx.y, blockIdx.z, lds);
 }
 
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(RT) void residual_march_batch(const ResDesc* __rest
   const int by = (int)((rb / d.gx) % d.gy);
   const int bz = (int)(rb / ((long)d.gx * d.gy));
   march_body<KH, TR, false>(d.v, d.f, d.d, nullptr, (TR*)d.r, d.ldr, d.rplane, d.hx, d.hy, d.hz, d.nx, d.ny, d.nz,
-                            d.xchunk, d.per != 0, Coef{d.cf, d.cd, d.ch, 0.0}, bx, by, bz, lds);
+                            d.xchunk, d.per, Coef{d.cf, d.cd, d.ch, 0.0}, bx, by, bz, lds);
 }
 
 // x is split into chunks so that the grid fills the chip even for thin (y, z)

@@ -133,17 +133,24 @@ sem_status sem_axis_host(int k, int ne, double a, double b, sem_bc bc, int* n, d
 }
 
 sem_status sem_plan_create(int k, const int ne[3], const double box[6], double alpha, sem_bc bc, sem_plan** out) {
-  if (!out || !ne || !box) return fail(SEM_EINVAL, "sem_plan_create: null argument");
+  const sem_bc bcs[3] = {bc, bc, bc};
+  return sem_plan_create_mixed(k, ne, box, alpha, bcs, out);
+}
+
+sem_status sem_plan_create_mixed(int k, const int ne[3], const double box[6], double alpha, const sem_bc bc3[3],
+                                 sem_plan** out) {
+  if (!out || !ne || !box || !bc3) return fail(SEM_EINVAL, "sem_plan_create: null argument");
   *out = nullptr;
   if (k < 1 || k > 64) return fail(SEM_EINVAL, "sem_plan_create: k must be in [1, 64]");
-  if (!valid_bc(bc)) return fail(SEM_EINVAL, "sem_plan_create: bad bc");
+  for (int a = 0; a < 3; ++a)
+    if (!valid_bc(bc3[a])) return fail(SEM_EINVAL, "sem_plan_create: bad bc on axis %d", a);
   if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SEM_EINVAL, "sem_plan_create: alpha must be finite, >= 0");
   long total = 1;
   for (int a = 0; a < 3; ++a) {
     if (ne[a] < 1) return fail(SEM_EINVAL, "sem_plan_create: ne[%d] < 1", a);
     if (!(box[2 * a] < box[2 * a + 1]) || !std::isfinite(box[2 * a]) || !std::isfinite(box[2 * a + 1]))
       return fail(SEM_EINVAL, "sem_plan_create: degenerate box on axis %d", a);
-    const long n = axis_unknowns(bc, ne[a], k);
+    const long n = axis_unknowns(bc3[a], ne[a], k);
     if (n < 1) return fail(SEM_EINVAL, "sem_plan_create: Dirichlet axis %d has no interior node", a);
     if (n > 4096) return fail(SEM_EINVAL, "sem_plan_create: axis %d has %ld > 4096 unknowns", a, n);
     total *= n;
@@ -154,15 +161,18 @@ sem_status sem_plan_create(int k, const int ne[3], const double box[6], double a
   if (!p) return fail(SEM_ENOMEM, "sem_plan_create: host allocation");
   p->k = k;
   p->alpha = alpha;
-  p->bc = bc;
+  for (int a = 0; a < 3; ++a) {
+    p->bc[a] = bc3[a];
+    if (bc3[a] == SEM_BC_PERIODIC) p->per_mask |= 1 << a;
+  }
   for (int a = 0; a < 6; ++a) p->box[a] = box[a];
   try {
     for (int a = 0; a < 3; ++a) {
       p->ne[a] = ne[a];
-      const AxisSpec s = axis_spec(k, ne[a], box[2 * a], box[2 * a + 1], bc);
+      const AxisSpec s = axis_spec(k, ne[a], box[2 * a], box[2 * a + 1], bc3[a]);
       int same = -1;
       for (int b = 0; b < a; ++b)
-        if (axis_spec(k, ne[b], box[2 * b], box[2 * b + 1], bc) == s) same = b;
+        if (axis_spec(k, ne[b], box[2 * b], box[2 * b + 1], bc3[b]) == s) same = b;
       if (same >= 0)
         p->ax[a] = p->ax[same];
       else
@@ -309,7 +319,7 @@ sem_status sem_residual(sem_plan* p, const double* u, const double* f, double* r
   if (r == u) return fail(SEM_EINVAL, "sem_residual: r must not alias u");
   const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
   ResidualArgs ra;
-  ra.periodic = p->bc == SEM_BC_PERIODIC;
+  ra.periodic = p->per_mask;
   ra.v = u;
   ra.f = f;
   ra.r = r;

@@ -144,3 +144,30 @@ def test_plan_create_singular_without_shift(P, bc):
     """Neumann and periodic with alpha = 0: the constants are in the kernel."""
     st, p = _create(P, 3, (2, 2, 2), (0.0, 1.0) * 3, 0.0, bc)
     assert st == 4 and not p.value  # SEM_ESINGULAR
+
+
+def _create_mixed(P, k, ne, box, alpha, bcs):
+    lib = ctypes.CDLL(P.binding.LIB_PATH)
+    lib.sem_plan_create_mixed.restype = ctypes.c_int
+    p = ctypes.c_void_p(None)
+    st = lib.sem_plan_create_mixed(ctypes.c_int(k), (ctypes.c_int * 3)(*ne), (ctypes.c_double * 6)(*box),
+                                   ctypes.c_double(alpha), (ctypes.c_int * 3)(*bcs), ctypes.byref(p))
+    return st, p
+
+
+@pytest.mark.parametrize("bcs,alpha,status", [
+    ((0, 1, 3), 1.0, 1),   # unknown condition on z
+    ((2, 2, -1), 1.0, 1),  # unknown condition on z
+    ((1, 2, 2), 0.0, 4),   # no Dirichlet axis and alpha = 0: singular
+    ((2, 1, 1), 0.0, 4),
+    ((0, 2, 1), -1.0, 1),  # negative alpha
+])
+def test_plan_create_mixed_rejects_before_device_use(P, bcs, alpha, status):
+    st, p = _create_mixed(P, 3, (2, 2, 2), (0.0, 1.0) * 3, alpha, bcs)
+    assert st == status and not p.value
+
+
+def test_mixed_axis_sizes_follow_each_condition(P):
+    """Through the host-only axis builder: n = ne k - 1, ne k + 1, ne k."""
+    for bc, n in (("dirichlet", 11), ("neumann", 13), ("periodic", 12)):
+        assert P.axis_host(3, 4, 0.0, 1.0, bc)["lam"].size == n
