@@ -130,15 +130,16 @@ sem_status sem_residual(sem_plan *p, const double *u, const double *f, double *r
  * g[2a], g[2a+1]: device arrays with the data on the face x_a = box[2a] and
  * x_a = box[2a+1], row-major over the two other axes in their order (n_y x n_z,
  * n_x x n_z, n_x x n_y); a NULL face (or g == NULL) is homogeneous.
- *   Dirichlet plans: the values of u on the face at the nodes whose two other
+ *   Dirichlet axes: the values of u on the face at the nodes whose two other
  *     coordinates are unknowns (edge and corner values are not needed).  With u_b
- *     the data on the full grid of ne k + 1 nodes per axis, f += -(H_x + H_y +
- *     H_z) u_b at the unknowns (the k unknowns next to each face), H = M^{-1} K of
- *     the full-grid assembly.
- *   Neumann plans: the outward normal derivative at the face's nodes; by GLL
+ *     the data on the full grid of ne k + 1 nodes along the axis, f += -(H_x +
+ *     H_y + H_z) u_b at the unknowns, which is -H_a(unknown, end node) g for the
+ *     min(k, n_a) unknowns next to each face (H = M^{-1} K of the full-grid
+ *     assembly).
+ *   Neumann axes: the outward normal derivative at the face's nodes; by GLL
  *     quadrature of the boundary integral, f += g / M_a(end node) on the face
  *     (edges and corners sum the faces they lie on).
- *   Periodic plans: SEM_EINVAL for any non-NULL face.
+ *   Periodic axes: SEM_EINVAL for any non-NULL face of theirs.
  * Faces must not overlap f (SEM_EINVAL).  Asynchronous on the plan's stream;
  * the faces of one axis are one launch, the axes are applied in order. */
 sem_status sem_lift_boundary(sem_plan *p, const double *const g[6], double *f);
