@@ -145,7 +145,15 @@ struct ResidualArgs {
   long rplane = 0;
   double cf = 1.0, cd = 0.0, ch = 1.0;
   int periodic = 0;  // bit a set: axis a is periodic (its neighbours wrap around)
+  // weighted march only (wt set, k <= 8, FP64 output): also the per-block partial
+  // sums of <v, r>_M = sum Mx_i My_j Mz_l v r, written to dot_partial[2 b] for
+  // block b of the launch (residual_march_blocks blocks); dot_mass = the 1D masses
+  double* dot_partial = nullptr;
+  const double* dot_mass[3] = {nullptr, nullptr, nullptr};
 };
+// Blocks of the single-launch march for these dimensions and k (0 for k > 8,
+// which takes the generic kernel).
+long residual_march_blocks(const int dims[3], int k);
 hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], int k, const int dims[3],
                            hipStream_t stream);
 

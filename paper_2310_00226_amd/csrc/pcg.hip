@@ -9,7 +9,8 @@
 // throughout (the iterates of plain PCG on the symmetric weak form).
 //
 // One iteration on the GPU: q = A p (the matrix-free residual kernel with the
-// per-node weight alpha + V), <p, q>; u += a p and r -= a q fused with <r, r>;
+// per-node weight alpha + V, which for k <= 8 also sums <p, q> per block); u += a p
+// and r -= a q fused with <r, r>;
 // z = P^{-1} r (an FP64 FD solve, or a low-precision one); <r, z> (and <z, q>);
 // p = z + b p.  The weighted inner products are two-stage block reductions
 // (fixed block count, partial sums added in a fixed order: deterministic); the
@@ -131,8 +132,13 @@ struct PcgWork {
   double *r, *z, *p, *q, *partial, *out;
 };
 
+// block partials: the dot kernels' DOT_BLOCKS, or the operator march's blocks
+size_t partial_slots(const sem_plan* p) {
+  return (size_t)std::max<long>(DOT_BLOCKS, residual_march_blocks(p->dims, p->k));
+}
+
 size_t pcg_need(const sem_plan* p) {
-  return 4 * align256(p->N * sizeof(double)) + align256(DOT_BLOCKS * MAXDOT * sizeof(double)) + 256;
+  return 4 * align256(p->N * sizeof(double)) + align256(partial_slots(p) * MAXDOT * sizeof(double)) + 256;
 }
 
 int dot_blocks(const sem_plan* p) {
@@ -187,7 +193,7 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
   const size_t vb = align256(n * sizeof(double));
   char* wb = (char*)work;
   PcgWork w{(double*)wb, (double*)(wb + vb), (double*)(wb + 2 * vb), (double*)(wb + 3 * vb),
-            (double*)(wb + 4 * vb), (double*)(wb + 4 * vb + align256(DOT_BLOCKS * MAXDOT * sizeof(double)))};
+            (double*)(wb + 4 * vb), (double*)(wb + 4 * vb + align256(partial_slots(p) * MAXDOT * sizeof(double)))};
 
   // preconditioner z = (shift I + H_3)^{-1} r
   const Spectral sp{shift, 1.0, 0.0};
@@ -221,6 +227,12 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
   const double* hb[3] = {p->d_hb[0], p->d_hb[1], p->d_hb[2]};
   const int nb = dot_blocks(p);
   const unsigned gdir = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  // <p, q> from the operator launch itself (k <= 8: the march kernel)
+  const long fused_blocks = residual_march_blocks(p->dims, p->k);
+  if (fused_blocks > 0) {
+    ra.dot_partial = w.partial;
+    for (int a = 0; a < 3; ++a) ra.dot_mass[a] = p->d_mass[a];
+  }
 
   hipError_t e;
   double h[2];
@@ -241,9 +253,17 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
   double rz = h[0];
   double rel = 1.0;
   for (int it = 1; it <= max_iter; ++it) {
-    if ((e = launch_residual(ra, hb, p->k, p->dims, p->stream)) != hipSuccess ||
-        (e = mdot(p, w, 1, w.p, w.q, nullptr, nullptr, h)) != hipSuccess)
+    if ((e = launch_residual(ra, hb, p->k, p->dims, p->stream)) != hipSuccess)
       return hip_fail(e, "sem_pcg_solve: operator");
+    if (fused_blocks > 0) {
+      mdot_final<<<1, DOT_THREADS, 0, p->stream>>>(w.partial, (int)fused_blocks, 1, w.out);
+      if ((e = hipGetLastError()) != hipSuccess ||
+          (e = hipMemcpyAsync(h, w.out, sizeof(double), hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
+          (e = hipStreamSynchronize(p->stream)) != hipSuccess)
+        return hip_fail(e, "sem_pcg_solve: <p, q>");
+    } else if ((e = mdot(p, w, 1, w.p, w.q, nullptr, nullptr, h)) != hipSuccess) {
+      return hip_fail(e, "sem_pcg_solve: <p, q>");
+    }
     const double pq = h[0];
     if (!std::isfinite(pq) || !std::isfinite(rz)) return set_error(SEM_ENONFINITE, "sem_pcg_solve: non-finite iterate");
     if (!(pq > 0.0) || !(rz > 0.0))

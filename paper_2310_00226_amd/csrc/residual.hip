@@ -58,6 +58,13 @@ struct Coef {
   double cf, cd, ch, wa;
 };
 
+// Optional fused inner product of the weighted march: per-block partial sums of
+// <v, r>_M at partial[2 b] (partial == nullptr: none).
+struct DotOut {
+  const double *mx = nullptr, *my = nullptr, *mz = nullptr;
+  double* partial = nullptr;
+};
+
 // Generic kernel (any k): one thread per node.
 template <class TR>
 __global__ __launch_bounds__(256) void residual_any_kernel(const double* __restrict__ v, const double* __restrict__ f,
@@ -144,7 +151,7 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
                                            const double* __restrict__ hx, const double* __restrict__ hy,
                                            const double* __restrict__ hz, int nx, int ny, int nz, int xchunk,
                                            int per, const Coef& c, int bx, int by, int bz,
-                                           double* __restrict__ lds) {
+                                           double* __restrict__ lds, const DotOut& dot = DotOut()) {
   constexpr int BW = 2 * KH + 1;
   typedef TileGeo<KH> G;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -241,6 +248,8 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       if constexpr (W) wv[q] = ok[q] ? c.wa + wt[at(ic, q)] : 1.0;
     }
   };
+  const bool fuse = W && dot.partial != nullptr;  // uniform
+  double acc = 0.0;
   if (i0 < i1) prefetch(i0);
   for (int i = i0; i < i1; ++i) {
     double* __restrict__ T = lds + ((i - i0) & 1) * G::PLANE;
@@ -273,12 +282,28 @@ __device__ __forceinline__ void march_body(const double* __restrict__ v, const d
       }
       if (ok[q]) {
         const size_t row0 = ((size_t)i * ny + jr[q]) * ldr;
-        put(r, row0 + l, c.cf * fc[q] - c.cd * dc[q] - c.ch * s, rplane);
+        const double o = c.cf * fc[q] - c.cd * dc[q] - c.ch * s;
+        put(r, row0 + l, o, rplane);
         zero_pad(r, row0, l, nz, ldr, rplane);
+        if constexpr (W)
+          if (fuse) acc += (dot.mx[i] * dot.my[jr[q]] * dot.mz[l]) * (w[q][KH] * o);
       }
 #pragma unroll
       for (int d = 0; d + 1 < BW; ++d) w[q][d] = w[q][d + 1];
       w[q][BW - 1] = wn[q];
+    }
+  }
+  if constexpr (W) {
+    if (fuse) {  // block sum in a fixed order: waves, then the 8 wave sums
+      __syncthreads();  // every wave is done with the plane tiles
+      for (int sh = 32; sh >= 1; sh >>= 1) acc += __shfl_xor(acc, sh);
+      if (lane == 0) lds[wave] = acc;
+      __syncthreads();
+      if (tid == 0) {
+        double t = 0.0;
+        for (int k = 0; k < RT / 64; ++k) t += lds[k];
+        dot.partial[2 * ((size_t)bx + (size_t)gridDim.x * ((size_t)by + (size_t)gridDim.y * bz))] = t;
+      }
     }
   }
 }
@@ -292,10 +317,11 @@ __global__ __launch_bounds__(RT) void residual_march_kernel(const double* __rest
                                                                   const double* __restrict__ hx,
                                                                   const double* __restrict__ hy,
                                                                   const double* __restrict__ hz, int nx, int ny,
-                                                                  int nz, int xchunk, int per, Coef c) {
+                                                                  int nz, int xchunk, int per, Coef c,
+                                                                  DotOut dot) {
   __shared__ double lds[2 * TileGeo<KH>::PLANE + (W ? (2 * KH + 1) * 64 : 0)];
   march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per, c, blockIdx.x,
-                        blockIdx.y, blockIdx.z, lds);
+                        blockIdx.y, blockIdx.z, lds, dot);
 }
 
 // The same march with at most 128 VGPRs (4 waves per SIMD, two blocks per CU).
@@ -307,10 +333,10 @@ __global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const double* __restrict__ v, const double* __restrict__ f, const double* __restrict__ dg,
     const double* __restrict__ wt, TR* __restrict__ r, int ldr, long rplane, const double* __restrict__ hx,
     const double* __restrict__ hy, const double* __restrict__ hz, int nx, int ny, int nz, int xchunk, int per,
-    Coef c) {
+    Coef c, DotOut dot) {
   __shared__ double lds[2 * TileGeo<KH>::PLANE + (W ? (2 * KH + 1) * 64 : 0)];
   march_body<KH, TR, W>(v, f, dg, wt, r, ldr, rplane, hx, hy, hz, nx, ny, nz, xchunk, per, c, blockIdx.x,
-                        blockIdx.y, blockIdx.z, lds);
+                        blockIdx.y, blockIdx.z, lds, dot);
 }
 
 // Residuals of many solves (same k) in one launch: descriptor i owns blocks
@@ -357,25 +383,27 @@ void launch_march(const ResidualArgs& ra, TR* r, const double* const hb[3], cons
   // solver) has its own instantiation, so that the others keep their registers
   if constexpr (std::is_same<TR, double>::value) {
     if (ra.wt) {
-      if constexpr (KH == 5)
+      DotOut dot;
+      if (ra.dot_partial) dot = DotOut{ra.dot_mass[0], ra.dot_mass[1], ra.dot_mass[2], ra.dot_partial};
+      if constexpr (KH == 4 || KH == 5)
         residual_march_kernel_w4<KH, TR, true><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
             ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
-            ra.periodic, c);
+            ra.periodic, c, dot);
       else
         residual_march_kernel<KH, TR, true><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
             ra.v, ra.f, ra.d, ra.wt, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
-            ra.periodic, c);
+            ra.periodic, c, dot);
       return;
     }
   }
   if constexpr (KH == 5) {
     residual_march_kernel_w4<KH, TR, false><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
         ra.v, ra.f, ra.d, nullptr, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
-        ra.periodic, c);
+        ra.periodic, c, DotOut());
   } else {
     residual_march_kernel<KH, TR, false><<<dim3(gx, gy, gz), dim3(RT), 0, stream>>>(
         ra.v, ra.f, ra.d, nullptr, r, ra.ldr, ra.rplane, hb[0], hb[1], hb[2], dims[0], dims[1], dims[2], xchunk,
-        ra.periodic, c);
+        ra.periodic, c, DotOut());
   }
 }
 
@@ -424,6 +452,7 @@ hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], in
   if (dims[0] <= 0 || plane <= 0) return hipSuccess;
   if (!ra.v || !ra.r || ra.ldr < dims[2] || k < 1) return hipErrorInvalidValue;
   if (ra.wt && ra.r_kind != 0) return hipErrorInvalidValue;  // weights: FP64 output only
+  if (ra.dot_partial && (!ra.wt || k > 8)) return hipErrorInvalidValue;  // fused dot: weighted march only
   // in-plane offsets are 32-bit; the grid's y and z extents are limited to 65535
   if ((dims[1] + RY - 1) / RY > 65535 || dims[0] > 65535 || plane > 0x7fffffffL) return hipErrorInvalidValue;
   switch (ra.r_kind) {
@@ -440,6 +469,13 @@ hipError_t launch_residual(const ResidualArgs& ra, const double* const hb[3], in
     default:
       return hipErrorInvalidValue;
   }
+}
+
+long residual_march_blocks(const int dims[3], int k) {
+  if (k < 1 || k > 8 || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0) return 0;
+  int gx, gy, gz, xchunk;
+  march_grid(dims, k, &gx, &gy, &gz, &xchunk);
+  return (long)gx * gy * gz;
 }
 
 bool residual_desc(const ResidualArgs& ra, const double* const hb[3], int k, const int dims[3], ResDesc* d) {
