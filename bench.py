@@ -166,8 +166,10 @@ def bench_paper_configs(args, P, torch, dev, log):
     comparison with its figures (context, not the metric's workload): the FP64
     solve of -Lap u + u = f, Q^5, homogeneous Neumann, [-1, 1]^3, 200^3 elements
     (n = 1001; the paper: ~0.8 s per solve on one A100 in MATLAB), also refined
-    from split-BF16 mode products; and the Cahn-Hilliard step at the same size
-    (eps = 0.02, m = 0.02, dt = 1e-3; the paper: 1.27 s per step), FP64 solve."""
+    from split-BF16 mode products; the Cahn-Hilliard step at the same size
+    (eps = 0.02, m = 0.02, dt = 1e-3; the paper: 1.27 s per step), FP64 solve;
+    and the FP64 solve at the sizes of the paper's timing tables (201^3 .. 951^3,
+    and 1251^3 for its largest, 1250^3)."""
     from workloads import ch_initial, normal_noise
     box = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0)
     res = {}
@@ -226,6 +228,39 @@ def bench_paper_configs(args, P, torch, dev, log):
                                              "Cahn-Hilliard section"}
     del a, b, ch
     torch.cuda.empty_cache()
+    # FP64 solve time across the sizes of the paper's timing tables (Q^5, Neumann,
+    # alpha = 1; A100 seconds for 200 solves: Table tab2 for 201^3 .. 951^3, Table
+    # tab4 for 1250^3, the largest the A100 held; here 1251^3)
+    paper_200 = {201: 0.900, 501: 11.1, 751: 53.1, 951: 134.0, 1251: 406.0}
+    sizes = []
+    for ne in (40, 100, 150, 190, 250):
+        plan = P.Plan(5, (ne, ne, ne), box, 1.0, "neumann")
+        n = plan.shape[0]
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(2314)
+        f = torch.randn(plan.shape, dtype=torch.float64, device=dev, generator=gen)
+        u = torch.empty_like(f)
+        plan.solve(f, u)
+        torch.cuda.synchronize()
+        reps = 200 if n <= 201 else 10
+        e0.record(stream)
+        for _ in range(reps):
+            plan.solve(f, u)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        pa = 1e3 * paper_200[n] / 200
+        log(f"paper sizes: FP64 solve n={n}: {ms:.2f} ms ({plan.numel / (ms * 1e-3):.3e} unknowns/s); "
+            f"paper A100 {pa:.1f} ms per solve")
+        sizes.append({"n": n, "unknowns": plan.numel, "ms_per_solve": ms, "solves_timed": reps,
+                      "unknowns_per_s": plan.numel / (ms * 1e-3), "paper_a100_ms_per_solve": pa})
+        del f, u, plan
+        torch.cuda.empty_cache()
+    res["solve_sizes"] = {"workload": "FP64 solve of -Lap u + u = f, Q^5, homogeneous Neumann, [-1,1]^3, "
+                                      "N(0,1) right-hand side (torch generator, seed 2314)",
+                          "paper_context": "A100 (MATLAB, FP64) time for 200 solves / 200, Tables tab2 and tab4 "
+                                           "(1250^3 there, 1251^3 here)",
+                          "by_size": sizes}
     return res
 
 
