@@ -158,6 +158,33 @@ def bench_schrodinger(args, P, torch, dev, log):
     res.update({"preconditioner": best, **res["by_preconditioner"][best]})
     del u, vd, fd, ued, plan
     torch.cuda.empty_cache()
+    # the smaller sizes of Table tab5 (A100 seconds per solve), split-BF16 preconditioner
+    paper_tab5 = {200: 0.104, 500: 1.18, 750: 5.30}
+    sizes = []
+    for nes in (40, 100, 150):
+        plan = P.Plan(5, (nes, nes, nes), SCHRODINGER_BOX, alpha, "periodic")
+        v, ue, f = schrodinger_data(*(plan.nodes(a) for a in range(3)), alpha, beta)
+        vd, fd, ued = (torch.from_numpy(a).to(dev) for a in (v, f, ue))
+        del v, f, ue
+        u = torch.empty_like(fd)
+        plan.pcg_solve(vd, fd, u, shift=alpha + beta / 2, prec="bf16x3", tol=1e-12)  # warm-up
+        torch.cuda.synchronize()
+        e0.record(stream)
+        _, it, rel, st = plan.pcg_solve(vd, fd, u, shift=alpha + beta / 2, prec="bf16x3", tol=1e-12,
+                                        raise_on_error=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        n = plan.shape[0]
+        err = float((u - ued).abs().max())
+        log(f"schrodinger n={n}^3: {ms:.1f} ms, {it} iterations, max error vs exact {err:.2e}; "
+            f"paper A100 {1e3 * paper_tab5[n]:.0f} ms")
+        sizes.append({"n": n, "ms_per_solve": ms, "iterations": it, "status": st, "max_err_vs_exact": err,
+                      "paper_a100_ms_per_solve": 1e3 * paper_tab5[n]})
+        del u, vd, fd, ued, plan
+        torch.cuda.empty_cache()
+    res["smaller_sizes"] = {"preconditioner": "bf16x3", "paper_context": "Table tab5, A100 (MATLAB, FP64)",
+                            "by_size": sizes}
     return res
 
 
