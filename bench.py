@@ -255,6 +255,24 @@ def bench_paper_configs(args, P, torch, dev, log):
                                              "Cahn-Hilliard section"}
     del a, b, ch
     torch.cuda.empty_cache()
+    # two smaller sizes of the paper's Cahn-Hilliard timing table (A100 s per step)
+    ch_sizes = []
+    for nec, paper_s in ((100, 0.0846), (150, 0.402)):
+        ch = P.CahnHilliard(5, (nec, nec, nec), box, 0.02, 0.02, 1e-3, prec="f64", refine_sweeps=0)
+        a = torch.from_numpy(ch_initial(ch.shape, 2312, 0.05)).to(dev)
+        b = a.clone()
+        ch.step(a, b, 2)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        ch.step(a, b, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_s = e0.elapsed_time(e1) / steps
+        log(f"paper sizes: FP64 Cahn-Hilliard step n={ch.shape[0]}: {ms_s:.2f} ms; paper A100 {1e3 * paper_s:.1f} ms")
+        ch_sizes.append({"n": ch.shape[0], "ms_per_step": ms_s, "paper_a100_ms_per_step": 1e3 * paper_s})
+        del a, b, ch
+        torch.cuda.empty_cache()
+    res["cahn_hilliard"]["smaller_sizes"] = ch_sizes
     # FP64 solve time across the sizes of the paper's timing tables (Q^5, Neumann,
     # alpha = 1; A100 seconds for 200 solves: Table tab2 for 201^3 .. 951^3, Table
     # tab4 for 1250^3, the largest the A100 held; here 1251^3)
