@@ -80,8 +80,12 @@ def bench_batch(args, P, torch, dev, log):
         ms = e0.elapsed_time(e1) / reps
         log(f"batch solve {prec}: {ms:.1f} ms, {total / (ms * 1e-3):.3e} unknowns/s, "
             f"iterations {min(its)}..{max(its)}, status {st}")
+        # algorithmic mode-product flop: 4 N (n_x + n_y + n_z) per FD application,
+        # one application per refinement iteration of each problem
+        flop = sum(4.0 * pl.numel * sum(pl.shape) * it for pl, it in zip(plans, its))
         per_prec[prec] = {"ms_per_batch": ms, "unknowns_per_s": total / (ms * 1e-3),
-                          "iterations": [min(its), max(its)], "status": st}
+                          "iterations": [min(its), max(its)], "status": st,
+                          "mode_product_tflops": flop / (ms * 1e-3) / 1e12}
         outs[prec] = us
     best = min((p for p in per_prec if per_prec[p]["status"] == 0), key=lambda p: per_prec[p]["ms_per_batch"],
                default="f32")
