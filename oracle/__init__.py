@@ -8,10 +8,14 @@ Every function follows the paper (Liu, Shen & Zhang, "A simple GPU
 implementation of spectral-element methods for solving 3D Poisson type
 equations on rectangular domains and its applications", arXiv 2310.00226) and
 cites the section / equation it restates.  All arithmetic is float64; numpy's
-matmul and symmetric eigensolver serve as library primitives.
+matmul and symmetric eigensolver serve as library primitives.  The eigenpairs
+alone go beyond float64: a long-double cyclic Jacobi iteration (eigjac.c) on the
+operator assembled from 40-digit element matrices (mpmath), started from
+numpy's eigenvectors, pinned against a 30-digit mpmath reference.
 
 Parity status of each function (what pins it is in tests/test_oracle_*.py):
   gll, diff_matrix, element_matrices, axis_operators, axis_eigen   pinned
+  element_matrices_hp (through axis_eigen, 30-digit reference)     pinned
   fd_solve, apply_h3, residual, residual_at, dense_system          pinned
   ch_step                                                          pinned
   schrodinger_apply, pcg_schrodinger                               pinned

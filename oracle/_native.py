@@ -1,6 +1,6 @@
 """Loader of the oracle's C helper (test infrastructure only).
 
-oracle/eigref.c is compiled with gcc into oracle/liboracle_eigref.so, by
+oracle/eigjac.c is compiled with gcc into oracle/liboracle_eigjac.so, by
 __graft_entry__.build() or, when missing or older than its source, here on first use.
 """
 from __future__ import annotations
@@ -13,8 +13,8 @@ import threading
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "eigref.c")
-LIB = os.path.join(HERE, "liboracle_eigref.so")
+SRC = os.path.join(HERE, "eigjac.c")
+LIB = os.path.join(HERE, "liboracle_eigjac.so")
 _lock = threading.Lock()
 _lib = None
 
@@ -35,26 +35,37 @@ def lib():
                 build()
             l = ctypes.CDLL(LIB)
             dp = ctypes.POINTER(ctypes.c_double)
-            l.oracle_eig_refine.restype = ctypes.c_int
-            l.oracle_eig_refine.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                            ctypes.c_double, ctypes.c_double, dp, dp, dp, dp, dp]
+            ci = ctypes.c_int
+            l.oracle_eig_jacobi.restype = ci
+            l.oracle_eig_jacobi.argtypes = [ci, ci, ci, ci, ci, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                            dp, dp, dp]
             _lib = l
     return _lib
 
 
-def eig_refine(ops, xr: np.ndarray, wr: np.ndarray, lam: np.ndarray, s: np.ndarray):
-    """One extended-precision refinement step (see eigref.c); returns new (lam, S)."""
-    n = lam.size
-    lo = np.array(lam, dtype=np.float64, copy=True)
-    so = np.array(s, dtype=np.float64, copy=True, order="C")
-    xr = np.ascontiguousarray(xr, dtype=np.float64)
-    wr = np.ascontiguousarray(wr, dtype=np.float64)
-    md = np.ascontiguousarray(ops.M, dtype=np.float64)
+def eig_jacobi(ops, q0: np.ndarray):
+    """Eigenpairs of the axis ops by long-double cyclic Jacobi started from q0
+    (see eigjac.c); returns (lam, S), ascending, S^T M S = I."""
+    import mpmath
+
+    from .sem_oracle import element_matrices_hp
+    n = q0.shape[0]
+    (khi, klo), (whi, wlo) = element_matrices_hp(ops.k)
+    with mpmath.workdps(50):
+        h = (mpmath.mpf(ops.b) - mpmath.mpf(ops.a)) / (2 * ops.ne)
+        h_hi = float(h)
+        h_lo = float(h - mpmath.mpf(h_hi))
+    q = np.ascontiguousarray(q0, dtype=np.float64)
+    lam = np.empty(n)
+    s = np.empty((n, n))
     off = 1 if ops.bc == "dirichlet" else 0
     per = 1 if ops.bc == "periodic" else 0
     dp = ctypes.POINTER(ctypes.c_double)
-    st = lib().oracle_eig_refine(n, ops.k, ops.ne, off, per, ops.a, ops.b, xr.ctypes.data_as(dp), wr.ctypes.data_as(dp),
-                                 md.ctypes.data_as(dp), lo.ctypes.data_as(dp), so.ctypes.data_as(dp))
-    if st != 0:
-        raise MemoryError("oracle_eig_refine: allocation failed")
-    return lo, so
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (khi, klo, whi, wlo)]
+    st = lib().oracle_eig_jacobi(n, ops.k, ops.ne, off, per, *(a.ctypes.data_as(dp) for a in arrs), h_hi, h_lo,
+                                 q.ctypes.data_as(dp), lam.ctypes.data_as(dp), s.ctypes.data_as(dp))
+    if st == 1:
+        raise MemoryError("oracle_eig_jacobi: allocation failed")
+    if st == 2:
+        raise RuntimeError("oracle_eig_jacobi: Jacobi sweeps did not converge")
+    return lam, s

@@ -153,6 +153,62 @@ def axis_operators(k: int, ne: int, a: float, b: float, bc: str) -> AxisOps:
     return AxisOps(k, ne, a, b, bc, xfull, kfull, mfull, h)
 
 
+def element_matrices_hp(k: int, digits: int = 40):
+    """Reference-element stiffness and GLL weights to `digits` significant digits
+    (mpmath), returned as (hi, lo) pairs of float64 arrays (value = hi + lo).
+
+    Same definitions as element_matrices (Sec. 2.1, Appendix generator): interior
+    nodes are the roots of P_k', polished by Newton's method in high precision from
+    the float64 nodes; weights 2 / (k(k+1) P_k(x)^2); D[i, j] = l_j'(x_i) by the
+    product formula, D[i, i] = sum_{m != i} 1 / (x_i - x_m); K_ref = D^T W D.
+    Used where float64 rounding of the operator itself matters: the eigenvalues at
+    the bottom of the spectrum come out of a cancellation of ratio
+    lambda_max / lambda_min.
+    """
+    import mpmath
+    key = (k, digits)
+    if key in _HP_CACHE:
+        return _HP_CACHE[key]
+    with mpmath.workdps(digits + 10):
+        x0, _ = gll(k)
+        xs = [mpmath.mpf(-1)] + [mpmath.mpf(float(v)) for v in x0[1:-1]] + [mpmath.mpf(1)]
+
+        def leg(xv):
+            p_prev, p = mpmath.mpf(1), xv
+            for m in range(1, k):
+                p_prev, p = p, ((2 * m + 1) * xv * p - m * p_prev) / (m + 1)
+            return p, p_prev
+
+        for j in range(1, k):
+            xv = xs[j]
+            for _ in range(8):
+                p, pm1 = leg(xv)
+                dp = k * (xv * p - pm1) / (xv * xv - 1)
+                d2p = (2 * xv * dp - k * (k + 1) * p) / (1 - xv * xv)
+                xv = xv - dp / d2p
+            xs[j] = xv
+        ws = [2 / (k * (k + 1) * leg(xv)[0] ** 2) for xv in xs]
+        npt = k + 1
+        om = [mpmath.fprod(xs[i] - xs[m] for m in range(npt) if m != i) for i in range(npt)]
+        d = [[(om[i] / om[j]) / (xs[i] - xs[j]) if i != j else
+              mpmath.fsum(1 / (xs[i] - xs[m]) for m in range(npt) if m != i) for j in range(npt)]
+             for i in range(npt)]
+        kref = [[mpmath.fsum(d[q][i] * ws[q] * d[q][j] for q in range(npt)) for j in range(npt)]
+                for i in range(npt)]
+
+        def split(vals):
+            hi = np.array([float(v) for v in vals])
+            lo = np.array([float(v - mpmath.mpf(float(v))) for v in vals])
+            return hi, lo
+
+        out = (split([kref[i][j] for i in range(npt) for j in range(npt)]), split(ws))
+    _HP_CACHE[key] = out
+    return out
+
+
+_HP_CACHE: dict = {}
+
+
 def axis_eigen(ops: AxisOps, refine: bool = True):
     """Generalised eigenpairs K s = lambda M s, ascending, M-orthonormal.
 
@@ -165,10 +221,9 @@ def axis_eigen(ops: AxisOps, refine: bool = True):
     FP64 dense eigensolver leaves absolute eigenvalue errors ~ eps * lambda_max,
     which the divide of eq. 3D-Poisson turns into relative errors of the lowest
     (dominant) solution modes of ~ eps * cond (~1e-11 at n ~ 1000).  With
-    `refine`, one extended-precision Newton step (Ogita & Aishima 2018, in
-    oracle/eigref.c) brings the pairs to FP64 rounding; it forms K X in long
-    double from the element matrices, since FP64 rounding of K's entries alone
-    shifts the lowest eigenvalues by ~ eps * lambda_max.
+    `refine`, numpy's eigenvectors only start a cyclic Jacobi iteration in x87 long
+    double on the operator assembled from high-precision element matrices
+    (oracle/eigjac.c), which brings the pairs to FP64 rounding.
     """
     mh = np.sqrt(ops.M)
     s1 = ops.K / (mh[:, None] * mh[None, :])
@@ -178,11 +233,8 @@ def axis_eigen(ops: AxisOps, refine: bool = True):
     lam, q = lam[order], q[:, order]
     s = q / mh[:, None]
     if refine and lam.size > 1:
-        from ._native import eig_refine
-        xr, wr = gll(ops.k)
-        lam, s = eig_refine(ops, xr, wr, lam, s)
-        order = np.argsort(lam, kind="stable")
-        lam, s = lam[order], s[:, order]
+        from ._native import eig_jacobi
+        lam, s = eig_jacobi(ops, q)
     f = (s * ops.M[:, None]).T
     return lam, s, f
 

@@ -136,9 +136,9 @@ def test_table1_reproduced(row):
     e = O.fd_solve(p, f) - u
     h = p.axes[0].h
     err = math.sqrt(h ** 3 * np.sum(e * e))
-    # three significant digits as printed.  The two Q^6 32^3 rows (~5e-11) sit at the FP64
-    # rounding level of a solve whose eigenpairs carry absolute errors ~ eps * lambda_max (as an
-    # unrefined dense eigensolver leaves them): about 1e-12 in this norm at n ~ 190, which the
-    # printed values include.  Those rows get that absolute allowance.
-    tol = max(0.0051 * err_paper, 2e-12)
+    # three significant digits as printed.  The two Q^6 32^3 rows (~5e-11) sit near the FP64
+    # rounding level of the paper's own solve (its eigenpairs come from a plain FP64 dense
+    # eigensolver, absolute errors ~ eps * lambda_max, about 1e-12 in this norm at n ~ 190),
+    # which the printed values include: 2% there (the oracle lands at -0.2% and -1.8%).
+    tol = (0.02 if err_paper < 1e-10 else 0.0051) * err_paper
     assert abs(err - err_paper) <= tol, (err, err_paper)
