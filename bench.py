@@ -41,6 +41,33 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def host_info() -> dict:
+    """Host cores for the CPU baseline: nproc, the CPUs this process may run on, the
+    CPU model, and the threads the BLAS behind numpy's matmul actually uses."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        affinity = os.cpu_count()
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"),
+                      default=None)
+    except Exception:  # pragma: no cover
+        pass
+    return {"nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": model,
+            "blas_threads": int(threads or affinity)}
+
+
 def bench_batch(args, P, torch, dev, log):
     """Batched workload: args.batch problems, k in {2..8}, 8..64 elements per axis,
     alpha ~ U[0, 10], N(0,1) right-hand sides (seed 2311); FP64 refinement to
@@ -584,12 +611,7 @@ def main() -> int:
 
     if not args.no_cpu_baseline:
         import oracle as O
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max((i.get("num_threads", 1) for i in threadpool_info() if i.get("internal_api") == "openblas"),
-                        default=os.cpu_count())
-        except Exception:  # pragma: no cover
-            cores = os.cpu_count()
+        host = host_info()
         u_host = u.cpu().numpy()
         del u, f
         torch.cuda.empty_cache()
@@ -601,9 +623,12 @@ def main() -> int:
         cpu_s = time.perf_counter() - t0
         err = O.rel_max_err(u_host, u_ref)
         log(f"oracle solve {cpu_s:.1f}s; GPU rel max err vs oracle {err:.3e}")
-        out["cpu_baseline"] = {"value": N / cpu_s, "unit": "unknowns/s", "cores": int(cores), "kind": "oracle",
+        out["cpu_baseline"] = {"value": N / cpu_s, "unit": "unknowns/s", "cores": host["blas_threads"],
+                               "kind": "oracle",
                                "sample": f"one full oracle FP64 solve of the same n={nx} workload "
-                                         f"(numpy/OpenBLAS matmuls), {cpu_s:.1f} s"}
+                                         f"(numpy/OpenBLAS matmuls), {cpu_s:.1f} s",
+                               "nproc": host["nproc"], "affinity_cpus": host["affinity_cpus"],
+                               "cpu_model": host["cpu_model"], "threads_used": host["blas_threads"]}
         out["rel_max_err_vs_oracle"] = err
     print(json.dumps(out), flush=True)
     return 0

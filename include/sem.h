@@ -150,8 +150,9 @@ sem_status sem_lift_boundary(sem_plan *p, const double *const g[6], double *f);
  *   enough that the remaining error is predicted below that: with
  *   r_k = ||delta_k|| / ||u_k|| and, from the third iteration on, q = the larger
  *   of r_k / r_{k-1} and r_{k-1} / r_{k-2}, stop when q < 1/2 and
- *   q r_k / (1 - q) <= tol (the next update and all later ones are at most that
- *   for a contraction that stays at q)  (iterations <= max_iter).
+ *   q r_k / (1 - q) <= tol / 10 (the next update and all later ones add up to
+ *   q r_k / (1 - q) for a contraction that stays at q; q is an estimate, hence
+ *   the factor of ten)  (iterations <= max_iter).
  * FD_prec is eq. 3D-Poisson with its six mode products in precision `prec`
  * (SEM_F32, SEM_BF16, SEM_BF16X3; SEM_F64 performs one FP64 solve); the update
  * of u and the residual are FP64.  tol = 0 runs exactly max_iter iterations.
@@ -199,25 +200,30 @@ sem_status sem_pcg_workspace_bytes(const sem_plan *p, size_t *bytes);
 /* alpha u - Lap u + V u = f (the paper's Schrodinger-equation section, eq.
  * shrodinger; alpha = the plan's alpha, V >= 0 given at the nodes) by
  * preconditioned conjugate gradients with the fast-diagonalisation solve of
- * (shift I - Lap) as the preconditioner (eq. 3D-Poisson with alpha := shift; the
- * paper takes shift = alpha + beta/2 for 0 <= V <= beta).  The operator is the
- * GLL-quadrature weak form divided by the lumped mass, A u = alpha u + H_3 u + V u,
- * applied matrix-free in FP64; the inner products are M_3-weighted.  Starts from
- * u = 0 and stops when ||f - A u||_M <= tol ||f||_M.
+ * (shift I - Lap) as the preconditioner (eq. 3D-Poisson with alpha := shift).
+ * The operator is the GLL-quadrature weak form divided by the lumped mass,
+ * A u = alpha u + H_3 u + V u, applied matrix-free in FP64; the inner products are
+ * M_3-weighted.  Starts from u = 0 and stops when ||f - A u||_M <= tol ||f||_M.
  *  v, f, u: device FP64 arrays of N nodal values (u must not alias f or v);
+ *  shift: > 0 as given; <= 0 selects the paper's choice alpha + beta / 2 for
+ *        0 <= V <= beta, with beta = max(V) reduced on the device;
  *  prec: precision of the preconditioner's mode products (SEM_F64, or SEM_F32 /
  *        SEM_BF16 / SEM_BF16X3, then with the flexible Polak-Ribiere update; the
  *        operator, the update and the inner products stay FP64);
  *  work: device buffer of sem_pcg_workspace_bytes bytes, 256-byte aligned.
  *        The preconditioner also uses the plan workspace.
- *  iters / relres (may be NULL): iterations and final ||r||_M / ||f||_M.
- * Synchronises with the plan stream once per inner product (three per iteration).
- * SEM_EINVAL: null pointers, aliasing, shift <= 0, tol < 0, max_iter < 1, small
- * or misaligned workspace.  SEM_ENOCONV: tol not met within max_iter, or a
- * non-positive curvature (V too negative: A not positive definite).
- * SEM_ENONFINITE: NaN / Inf in f or in an iterate. */
+ *  iters / relres / shift_used (may be NULL): iterations, final ||r||_M / ||f||_M
+ *        and the shift the preconditioner used.
+ * Synchronises with the plan stream once per inner product (three per iteration),
+ * and once more for the default shift.
+ * SEM_EINVAL: null pointers, aliasing, a non-finite shift, a default shift that is
+ * not > 0, tol < 0, max_iter < 1, small or misaligned workspace.  SEM_ENOCONV: tol
+ * not met within max_iter, or a non-positive curvature (V too negative: A not
+ * positive definite).  SEM_ENONFINITE: NaN / Inf in V (default shift), in f or in
+ * an iterate. */
 sem_status sem_pcg_solve(sem_plan *p, const double *v, double shift, sem_prec prec, double tol, int max_iter,
-                         const double *f, double *u, void *work, size_t work_bytes, int *iters, double *relres);
+                         const double *f, double *u, void *work, size_t work_bytes, int *iters, double *relres,
+                         double *shift_used);
 
 /* ---- batched solves ---------------------------------------------------------- */
 

@@ -52,7 +52,7 @@ def _load():
         "sem_apply_spectral": (c_int, [c_void_p, c_int, c_double, c_double, c_void_p, c_void_p]),
         "sem_pcg_workspace_bytes": (c_int, [c_void_p, POINTER(c_size_t)]),
         "sem_pcg_solve": (c_int, [c_void_p, c_void_p, c_double, c_int, c_double, c_int, c_void_p, c_void_p,
-                                  c_void_p, c_size_t, POINTER(c_int), POINTER(c_double)]),
+                                  c_void_p, c_size_t, POINTER(c_int), POINTER(c_double), POINTER(c_double)]),
         "sem_axis_host": (c_int, [c_int, c_int, c_double, c_double, c_int, POINTER(c_int), dp, dp, dp, dp, dp]),
         "sem_batch_create": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p)]),
         "sem_batch_destroy": (None, [c_void_p]),
@@ -231,8 +231,8 @@ class Plan:
                   max_iter: int = 500, raise_on_error: bool = True):
         """alpha u - Lap u + V u = f by PCG with the FD solve of (shift I - Lap) as
         preconditioner (sem_pcg_solve); v is the potential at the nodes (>= 0),
-        shift defaults to alpha + max(v)/2.  Returns (u, iterations, final relative
-        residual, status)."""
+        shift None lets the library take alpha + max(v)/2.  Returns (u, iterations,
+        final relative residual, status); the shift used is kept in last_pcg_shift."""
         import torch
         if u is None:
             u = torch.empty_like(f)
@@ -240,8 +240,6 @@ class Plan:
         vp = _dev_ptr(v, "v", self.numel, torch.float64)
         fp = _dev_ptr(f, "f", self.numel, torch.float64)
         up = _dev_ptr(u, "u", self.numel, torch.float64)
-        if shift is None:
-            shift = self.alpha + 0.5 * float(v.max())
         self._prepare(pv)
         need = c_size_t(0)
         check(lib.sem_pcg_workspace_bytes(self._p, ctypes.byref(need)))
@@ -251,8 +249,11 @@ class Plan:
             self._ws["pcg"] = work
         it = c_int(0)
         rel = c_double(0.0)
-        st = lib.sem_pcg_solve(self._p, vp, float(shift), pv, float(tol), int(max_iter), fp, up,
-                               c_void_p(work.data_ptr()), work.numel(), ctypes.byref(it), ctypes.byref(rel))
+        used = c_double(0.0)
+        st = lib.sem_pcg_solve(self._p, vp, 0.0 if shift is None else float(shift), pv, float(tol), int(max_iter),
+                               fp, up, c_void_p(work.data_ptr()), work.numel(), ctypes.byref(it), ctypes.byref(rel),
+                               ctypes.byref(used))
+        self.last_pcg_shift = used.value
         if raise_on_error:
             check(st)
         return u, it.value, rel.value, st

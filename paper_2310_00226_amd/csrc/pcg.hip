@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -121,6 +122,43 @@ __global__ __launch_bounds__(DOT_THREADS) void mdot_final(const double* __restri
   }
 }
 
+// Partial maxima of V per block (a NaN or Inf gives +Inf, so the caller sees a
+// non-finite shift), then their maximum: the default shift alpha + max(V) / 2.
+__global__ __launch_bounds__(DOT_THREADS) void vmax_partial(const double* __restrict__ v, size_t n,
+                                                            double* __restrict__ partial) {
+  __shared__ double sh[DOT_THREADS / 64];
+  double m = -INFINITY;
+  for (size_t g = (size_t)blockIdx.x * DOT_THREADS + threadIdx.x; g < n; g += (size_t)gridDim.x * DOT_THREADS) {
+    const double x = v[g];
+    m = fabs(x) <= DBL_MAX ? fmax(m, x) : INFINITY;
+  }
+  for (int s = 32; s >= 1; s >>= 1) m = fmax(m, __shfl_xor(m, s));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+    for (int w = 1; w < DOT_THREADS / 64; ++w) t = fmax(t, sh[w]);
+    partial[(size_t)blockIdx.x * MAXDOT] = t;
+  }
+}
+
+__global__ __launch_bounds__(DOT_THREADS) void default_shift(const double* __restrict__ partial, int nblocks,
+                                                             double alpha, double* __restrict__ out) {
+  __shared__ double sh[DOT_THREADS / 64];
+  double m = -INFINITY;
+  for (int b = threadIdx.x; b < nblocks; b += DOT_THREADS) m = fmax(m, partial[(size_t)b * MAXDOT]);
+  for (int s = 32; s >= 1; s >>= 1) m = fmax(m, __shfl_xor(m, s));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+    for (int w = 1; w < DOT_THREADS / 64; ++w) t = fmax(t, sh[w]);
+    out[0] = alpha + 0.5 * t;
+  }
+}
+
 // p = z + b p
 __global__ __launch_bounds__(256) void pcg_direction(double* __restrict__ p, const double* __restrict__ z, double b,
                                                      size_t n) {
@@ -177,12 +215,14 @@ sem_status sem_pcg_workspace_bytes(const sem_plan* p, size_t* bytes) {
 }
 
 sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec prec, double tol, int max_iter,
-                         const double* f, double* u, void* work, size_t work_bytes, int* iters, double* relres) {
+                         const double* f, double* u, void* work, size_t work_bytes, int* iters, double* relres,
+                         double* shift_used) {
   if (iters) *iters = 0;
+  if (shift_used) *shift_used = NAN;
   if (relres) *relres = NAN;
   if (!p || !v || !f || !u || !work) return set_error(SEM_EINVAL, "sem_pcg_solve: null argument");
   if (u == f || u == v) return set_error(SEM_EINVAL, "sem_pcg_solve: u must not alias f or V");
-  if (!(shift > 0.0) || !std::isfinite(shift)) return set_error(SEM_EINVAL, "sem_pcg_solve: shift must be > 0");
+  if (std::isnan(shift) || std::isinf(shift)) return set_error(SEM_EINVAL, "sem_pcg_solve: shift must be finite");
   if (!(tol >= 0.0) || !std::isfinite(tol) || max_iter < 1)
     return set_error(SEM_EINVAL, "sem_pcg_solve: invalid tol or max_iter");
   if (prec != SEM_F64 && prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3)
@@ -195,6 +235,22 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
   PcgWork w{(double*)wb, (double*)(wb + vb), (double*)(wb + 2 * vb), (double*)(wb + 3 * vb),
             (double*)(wb + 4 * vb), (double*)(wb + 4 * vb + align256(partial_slots(p) * MAXDOT * sizeof(double)))};
 
+  hipError_t e;
+  double h[2];
+  if (!(shift > 0.0)) {
+    // default: the paper's alpha + beta / 2 with beta = max(V)
+    const int nb0 = dot_blocks(p);
+    vmax_partial<<<nb0, DOT_THREADS, 0, p->stream>>>(v, n, w.partial);
+    default_shift<<<1, DOT_THREADS, 0, p->stream>>>(w.partial, nb0, p->alpha, w.out);
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipMemcpyAsync(h, w.out, sizeof(double), hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(p->stream)) != hipSuccess)
+      return hip_fail(e, "sem_pcg_solve: default shift");
+    shift = h[0];
+    if (!std::isfinite(shift)) return set_error(SEM_ENONFINITE, "sem_pcg_solve: non-finite potential");
+    if (!(shift > 0.0)) return set_error(SEM_EINVAL, "sem_pcg_solve: default shift alpha + max(V)/2 is not > 0");
+  }
+  if (shift_used) *shift_used = shift;
   // preconditioner z = (shift I + H_3)^{-1} r
   const Spectral sp{shift, 1.0, 0.0};
   LpWork lw;
@@ -234,8 +290,6 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
     for (int a = 0; a < 3; ++a) ra.dot_mass[a] = p->d_mass[a];
   }
 
-  hipError_t e;
-  double h[2];
   // u = 0, r = f
   if ((e = hipMemsetAsync(u, 0, n * sizeof(double), p->stream)) != hipSuccess ||
       (e = hipMemcpyAsync(w.r, f, n * sizeof(double), hipMemcpyDeviceToDevice, p->stream)) != hipSuccess ||

@@ -15,6 +15,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <numeric>
 #include <stdexcept>
 #include <thread>
@@ -23,94 +24,90 @@
 namespace semfd {
 
 // ----------------------------------------------------------------------------
-// Symmetric tridiagonal eigen-solver: implicit QL with Wilkinson-type shifts.
-// d[0..n-1] diagonal, e[0..n-2] off-diagonal.  If z != nullptr (n x n, row-major)
-// the plane rotations are accumulated into z's columns: on exit column j of z
-// holds the eigenvector of d[j] in z's original basis.  Rotations of one QL sweep
-// are recorded and then applied to the rows of z in parallel.
+// Symmetric tridiagonal eigen-solver: implicit symmetric QR steps with the
+// Wilkinson shift and deflation of negligible off-diagonal entries (Golub & Van
+// Loan, Matrix Computations, 4th ed., Algorithms 8.3.2 and 8.3.3).
+// d[0..n-1] diagonal, e[0..n-2] off-diagonal (e[i] couples i and i+1).  If
+// z != nullptr (n x n, row-major, leading dimension ldz) the Givens rotations are
+// accumulated into z's columns: on exit column j of z holds the eigenvector of
+// d[j] in z's original basis.  The rotations of one bulge chase are recorded and
+// then applied to the rows of z in parallel.
 // ----------------------------------------------------------------------------
-static void apply_rotations_rows(double* z, int n, int ld, int l, int m,
-                                 const std::vector<double>& cs, const std::vector<double>& sn,
-                                 int nthreads) {
-  // Sweep i = m-1 down to l rotates columns (i, i+1):
-  //   z[:, i+1] <- s z[:, i] + c z[:, i+1];  z[:, i] <- c z[:, i] - s z[:, i+1]
-  auto work = [&](int r0, int r1) {
+namespace {
+struct Givens {
+  double c, s;
+};
+
+// z[:, j] <- c z[:, j] + s z[:, j+1];  z[:, j+1] <- -s z[:, j] + c z[:, j+1]
+// for j = first, first + 1, ... in the order recorded
+void rotate_columns(double* z, int nrows, int ldz, int first, const std::vector<Givens>& g, int nthreads) {
+  auto rows = [&](int r0, int r1) {
     for (int r = r0; r < r1; ++r) {
-      double* row = z + (size_t)r * ld;
-      for (int i = m - 1, t = 0; i >= l; --i, ++t) {
-        const double c = cs[t], s = sn[t];
-        const double f = row[i + 1];
-        row[i + 1] = s * row[i] + c * f;
-        row[i] = c * row[i] - s * f;
+      double* row = z + (size_t)r * ldz;
+      for (size_t t = 0; t < g.size(); ++t) {
+        const int j = first + (int)t;
+        const double a = row[j], b = row[j + 1];
+        row[j] = g[t].c * a + g[t].s * b;
+        row[j + 1] = -g[t].s * a + g[t].c * b;
       }
     }
   };
-  const long cost = (long)n * (m - l);
+  const long cost = (long)nrows * (long)g.size();
   if (nthreads <= 1 || cost < 200000) {
-    work(0, n);
+    rows(0, nrows);
     return;
   }
   std::vector<std::thread> th;
-  for (int t = 0; t < nthreads; ++t) {
-    int r0 = (int)((long)n * t / nthreads), r1 = (int)((long)n * (t + 1) / nthreads);
-    th.emplace_back(work, r0, r1);
-  }
+  for (int t = 0; t < nthreads; ++t)
+    th.emplace_back(rows, (int)((long)nrows * t / nthreads), (int)((long)nrows * (t + 1) / nthreads));
   for (auto& x : th) x.join();
 }
+}  // namespace
 
-void tridiag_ql(int n, double* d, double* e_in, double* z, int ldz, int nthreads) {
-  if (n <= 0) return;
-  std::vector<double> e(n, 0.0);
-  for (int i = 0; i + 1 < n; ++i) e[i] = e_in[i];
-  std::vector<double> cs, sn;
-  cs.reserve(n);
-  sn.reserve(n);
-  for (int l = 0; l < n; ++l) {
-    int iter = 0;
-    for (;;) {
-      int m = l;
-      for (; m < n - 1; ++m) {
-        volatile double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-        volatile double sum = std::fabs(e[m]) + dd;  // negligible off-diagonal: deflate
-        if (sum == dd) break;
-      }
-      if (m == l) break;
-      if (++iter > 60) throw std::runtime_error("tridiagonal QL did not converge");
-      // shift from the trailing 2x2 of the leading block
-      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = std::hypot(g, 1.0);
-      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? std::fabs(r) : -std::fabs(r)));
-      double s = 1.0, c = 1.0, p = 0.0;
-      cs.clear();
-      sn.clear();
-      int i;
-      bool deflated = false;
-      for (i = m - 1; i >= l; --i) {
-        double f = s * e[i], b = c * e[i];
-        r = std::hypot(f, g);
-        e[i + 1] = r;
-        if (r == 0.0) {  // underflow: deflate
-          d[i + 1] -= p;
-          e[m] = 0.0;
-          deflated = true;
-          break;
-        }
-        s = f / r;
-        c = g / r;
-        g = d[i + 1] - p;
-        r = (d[i] - g) * s + 2.0 * c * b;
-        p = s * r;
-        d[i + 1] = g + p;
-        g = c * r - b;
-        cs.push_back(c);
-        sn.push_back(s);
-      }
-      if (z) apply_rotations_rows(z, n, ldz, deflated ? i + 1 : l, m, cs, sn, nthreads);
-      if (deflated) continue;
-      d[l] -= p;
-      e[l] = g;
-      e[m] = 0.0;
+void tridiag_qr(int n, double* d, double* e_in, double* z, int ldz, int nthreads) {
+  if (n <= 1) return;
+  std::vector<double> e(e_in, e_in + (n - 1));
+  std::vector<Givens> chase;
+  chase.reserve(n);
+  const double tol = 0.5 * std::numeric_limits<double>::epsilon();
+  int hi = n - 1, steps = 0;
+  while (hi > 0) {
+    for (int i = 0; i < hi; ++i)
+      if (std::fabs(e[i]) <= tol * (std::fabs(d[i]) + std::fabs(d[i + 1]))) e[i] = 0.0;
+    if (e[hi - 1] == 0.0) {  // d[hi] has converged
+      --hi;
+      steps = 0;
+      continue;
     }
+    int lo = hi - 1;  // the unreduced block [lo, hi]
+    while (lo > 0 && e[lo - 1] != 0.0) --lo;
+    if (++steps > 60) throw std::runtime_error("tridiagonal QR did not converge");
+    // Wilkinson shift: the eigenvalue of the trailing 2x2 closer to d[hi]
+    const double half = 0.5 * (d[hi - 1] - d[hi]), b = e[hi - 1];
+    const double mu = d[hi] - b * b / (half + (half >= 0.0 ? 1.0 : -1.0) * std::hypot(half, b));
+    // bulge chase: the first rotation acts on the shifted first column, each
+    // later one annihilates the bulge the previous one left below e[k-1]
+    chase.clear();
+    double x = d[lo] - mu, y = e[lo], bulge = 0.0;
+    for (int k = lo; k < hi; ++k) {
+      if (k > lo) {
+        x = e[k - 1];
+        y = bulge;
+      }
+      const double r = std::hypot(x, y);
+      const double c = r == 0.0 ? 1.0 : x / r, s = r == 0.0 ? 0.0 : y / r;
+      if (k > lo) e[k - 1] = r;
+      const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+      d[k] = c * c * dk + 2.0 * c * s * ek + s * s * dk1;
+      d[k + 1] = s * s * dk - 2.0 * c * s * ek + c * c * dk1;
+      e[k] = c * s * (dk1 - dk) + (c * c - s * s) * ek;
+      if (k + 1 < hi) {
+        bulge = s * e[k + 1];
+        e[k + 1] *= c;
+      }
+      chase.push_back({c, s});
+    }
+    if (z) rotate_columns(z, n, ldz, lo, chase, nthreads);
   }
 }
 
@@ -239,7 +236,7 @@ void sym_eig(int n, double* a, double* w, int nthreads) {
     return;
   }
   householder_tridiag(n, a, w, e.data(), nthreads);
-  tridiag_ql(n, w, e.data(), a, n, nthreads);
+  tridiag_qr(n, w, e.data(), a, n, nthreads);
   // sort ascending, permuting columns
   std::vector<int> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
@@ -279,7 +276,7 @@ void gll_rule(int k, std::vector<double>& x, std::vector<double>& w) {
     const int m = k - 1;
     std::vector<double> d(m, 0.0), e(std::max(m, 1), 0.0);
     for (int j = 1; j <= m - 1; ++j) e[j - 1] = std::sqrt((double)j * (j + 2) / ((2.0 * j + 1) * (2.0 * j + 3)));
-    tridiag_ql(m, d.data(), e.data(), nullptr, 0, 1);
+    tridiag_qr(m, d.data(), e.data(), nullptr, 0, 1);
     std::sort(d.begin(), d.end());
     for (int j = 0; j < m; ++j) x[j + 1] = d[j];
     // enforce the exact symmetry of the rule
@@ -451,28 +448,45 @@ static void refine_eigenpairs(int n, int k, int ne, const std::vector<long doubl
   }
 }
 
-// Element stiffness (k+1)^2 in long double, divided by the half width h, from the
-// FP64 GLL nodes: closed-form derivative matrix, diagonal = minus the off-diagonal
-// row sum, K_e = D^T W D / h.
-static std::vector<long double> element_stiffness_ld(int k, const std::vector<double>& xr,
-                                                     const std::vector<double>& wr, double a, double b, int ne) {
+// Element stiffness (k+1)^2 in long double, divided by the half width h: the
+// interior GLL nodes are polished in long double by Newton's method on P_k'
+// (from the FP64 nodes; P_k'' from Legendre's equation), weights
+// 2 / (k(k+1) P_k^2), closed-form derivative matrix with the diagonal set to
+// minus the off-diagonal row sum, K_e = D^T W D / h.  At high k the FP64 node
+// positions alone move the top of the spectrum by ~1e-13 relative.
+static std::vector<long double> element_stiffness_ld(int k, const std::vector<double>& xr, double a, double b,
+                                                     int ne) {
   typedef long double ld;
   const int np = k + 1;
-  std::vector<ld> p(np), D((size_t)np * np, 0.0L), ke((size_t)np * np, 0.0L);
-  for (int i = 0; i < np; ++i) {
-    ld p0 = 1.0L, p1 = xr[i];
+  auto legendre = [k](ld x, ld* pkm1) {
+    ld p0 = 1.0L, p1 = x;
     for (int j = 1; j < k; ++j) {
-      ld p2 = ((2.0L * j + 1.0L) * (ld)xr[i] * p1 - (ld)j * p0) / (ld)(j + 1);
+      const ld p2 = ((2.0L * j + 1.0L) * x * p1 - (ld)j * p0) / (ld)(j + 1);
       p0 = p1;
       p1 = p2;
     }
-    p[i] = k == 0 ? 1.0L : p1;
+    if (pkm1) *pkm1 = k == 0 ? 0.0L : p0;
+    return k == 0 ? 1.0L : p1;
+  };
+  std::vector<ld> x(np), w(np), p(np), D((size_t)np * np, 0.0L), ke((size_t)np * np, 0.0L);
+  for (int i = 0; i < np; ++i) {
+    x[i] = xr[i];
+    if (i > 0 && i < k)
+      for (int it = 0; it < 4; ++it) {
+        ld pm1;
+        const ld pk = legendre(x[i], &pm1);
+        const ld dp = k * (x[i] * pk - pm1) / (x[i] * x[i] - 1.0L);
+        const ld d2p = (2.0L * x[i] * dp - (ld)k * (k + 1) * pk) / (1.0L - x[i] * x[i]);
+        x[i] -= dp / d2p;
+      }
+    p[i] = legendre(x[i], nullptr);
+    w[i] = 2.0L / ((ld)k * (k + 1) * p[i] * p[i]);
   }
   for (int i = 0; i < np; ++i) {
     ld s = 0.0L;
     for (int j = 0; j < np; ++j) {
       if (i == j) continue;
-      D[(size_t)i * np + j] = p[i] / (p[j] * ((ld)xr[i] - (ld)xr[j]));
+      D[(size_t)i * np + j] = p[i] / (p[j] * (x[i] - x[j]));
       s += D[(size_t)i * np + j];
     }
     D[(size_t)i * np + i] = -s;
@@ -481,7 +495,7 @@ static std::vector<long double> element_stiffness_ld(int k, const std::vector<do
   for (int i = 0; i < np; ++i)
     for (int j = 0; j < np; ++j) {
       ld acc = 0.0L;
-      for (int q = 0; q < np; ++q) acc += D[(size_t)q * np + i] * (ld)wr[q] * D[(size_t)q * np + j];
+      for (int q = 0; q < np; ++q) acc += D[(size_t)q * np + i] * w[q] * D[(size_t)q * np + j];
       ke[(size_t)i * np + j] = acc / h;
     }
   return ke;
@@ -590,7 +604,7 @@ void build_axis(const AxisSpec& spec, AxisData& out, int nthreads) {
   for (int r = 0; r < n; ++r)
     for (int c = 0; c < n; ++c) out.S[(size_t)r * n + c] = s1[(size_t)r * n + c] / mh[r];
   if (n > 1) {
-    const std::vector<long double> ke = element_stiffness_ld(k, xr, wr, spec.a, spec.b, ne);
+    const std::vector<long double> ke = element_stiffness_ld(k, xr, spec.a, spec.b, ne);
     refine_eigenpairs(n, k, ne, ke, off, per, out.mass, out.lam, out.S, nthreads);
   }
   // forward factor F = S^T M  (= Q^T M^{1/2})

@@ -33,7 +33,7 @@ struct AxisData {
   std::vector<double> F;      // forward factor F = S^T M (n x n row-major)
 };
 
-void tridiag_ql(int n, double* d, double* e, double* z, int ldz, int nthreads);
+void tridiag_qr(int n, double* d, double* e, double* z, int ldz, int nthreads);
 void householder_tridiag(int n, double* a, double* d, double* e, int nthreads);
 void sym_eig(int n, double* a, double* w, int nthreads);
 void gll_rule(int k, std::vector<double>& x, std::vector<double>& w);

@@ -70,14 +70,15 @@ hipError_t zero_norms(unsigned long long* norms, hipStream_t stream);
 // two ratios r_k / r_{k-1} and r_{k-1} / r_{k-2} (from the third iteration on;
 // the convergence of the coarsest precisions alternates between fast and slow
 // steps), is below 1/2 and makes the predicted remaining error q r_k / (1 - q)
-// (a bound on the next update and all later ones for contraction q) <= tol.
-// prev = r_{k-1}, prev2 = r_{k-2}; infinite when not yet available.
+// (the next update and all later ones for contraction q) <= tol / 10: q is an
+// estimate from two ratios, not a bound, so the prediction keeps a factor of ten
+// in hand.  prev = r_{k-1}, prev2 = r_{k-2}; infinite when not yet available.
 inline bool refine_converged(double rel, double prev, double prev2, double tol) {
   if (!(tol > 0)) return false;
   if (rel <= tol) return true;
   if (prev > 0 && prev < 1e300 && prev2 > 0 && prev2 < 1e300) {
     const double q = fmax(rel / prev, prev / prev2);
-    if (q < 0.5 && rel * q / (1.0 - q) <= tol) return true;
+    if (q < 0.5 && rel * q / (1.0 - q) <= 0.1 * tol) return true;
   }
   return false;
 }

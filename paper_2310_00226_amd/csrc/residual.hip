@@ -15,12 +15,17 @@
 // offset d - k to node (g - k + d) mod n_a; the kernels read v at the wrapped
 // indices along that axis (the plan's band rows hold the wrap-around couplings).
 //
-// HBM-bound: per node it reads v and f and writes r (24 bytes in FP64).  A block
-// owns a (4 y) x (64 z) column of nodes and marches along x: the 2k+1 values of v
-// along x that a node needs sit in a register window (each v value is loaded
-// once, as the window front), the y and z neighbours of the current plane come
-// through the L1 cache, and the band coefficients of H_y, H_z of the thread's
-// (j, l) stay in registers for the whole march.
+// HBM-bound: per node it reads v and f and writes r (24 bytes in FP64).  For
+// k <= 8 a block of 8 waves owns a 16 (y) x 64 (z) column of nodes and marches
+// along x (residual_march_kernel): per x-plane the (16 + 2k) x (64 + 2k) tile of
+// v (core and a halo of k nodes in y and z) is staged in LDS, double-buffered with
+// one barrier per plane (the core from the thread's x-window registers, the halo
+// from global memory, mostly L2 hits); the y and z sums read the tile, the x sum
+// reads a register window of the 2k + 1 planes along x, whose front is loaded
+// one plane ahead.  The z-band coefficients of a thread's column stay in
+// registers (in LDS for the weighted variant), the y and x band rows are read
+// per plane.  x is cut into chunks so that thin (y, z) planes still fill the
+// chip.  Other k use a plain kernel with one thread per node.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -99,15 +99,42 @@ def test_pcg_rejects_invalid(torch, P):
     plan = P.Plan(3, (3, 3, 3), SCHRODINGER_BOX, 1.0, "neumann")
     v = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
     f = torch.ones_like(v)
-    for kw in ({"shift": 0.0}, {"shift": -1.0}, {"tol": -1.0}, {"max_iter": 0}):
+    for kw in ({"shift": float("nan")}, {"shift": float("inf")}, {"tol": -1.0}, {"max_iter": 0}):
         args = {"shift": 1.0, **kw}
         with pytest.raises(P.SemError):
             plan.pcg_solve(v, f, **args)
     with pytest.raises(P.SemError):
         plan.pcg_solve(v, f, u=f, shift=1.0)  # u aliases f
+    # default shift alpha + max(V)/2 not positive (V = -3, alpha = 1), or V not finite
+    with pytest.raises(P.SemError, match="SEM_EINVAL"):
+        plan.pcg_solve(torch.full_like(v, -3.0), f)
+    vbad = v.clone()
+    vbad[1, 2, 0] = float("nan")
+    with pytest.raises(P.SemError, match="SEM_ENONFINITE"):
+        plan.pcg_solve(vbad, f)
     # zero right-hand side: u = 0 in no iterations
     u, it, rel, st = plan.pcg_solve(v, torch.zeros_like(v), shift=1.0)
     assert st == 0 and it == 0 and float(u.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_pcg_default_shift_is_alpha_plus_half_max_v(torch, P, prec):
+    """Without a shift the library takes the paper's alpha + beta/2 with beta = max(V),
+    reduced on the device: the same iterates as the explicit shift (bit-equal)."""
+    k, ne, box, alpha, beta = 4, (9, 8, 10), SCHRODINGER_BOX, 1.0, 10.0
+    plan = P.Plan(k, ne, box, alpha, "neumann")
+    v, _, f = schrodinger_data(*(plan.nodes(a) for a in range(3)), alpha, beta)
+    vmax = float(np.max(v))
+    vd, fd = _dev(torch, v), _dev(torch, f)
+    u0, it0, rel0, st0 = plan.pcg_solve(vd, fd, prec=prec, tol=1e-12)
+    assert plan.last_pcg_shift == alpha + 0.5 * vmax
+    u1, it1, rel1, st1 = plan.pcg_solve(vd, fd, shift=alpha + 0.5 * vmax, prec=prec, tol=1e-12)
+    assert plan.last_pcg_shift == alpha + 0.5 * vmax
+    assert st0 == st1 == 0 and it0 == it1
+    assert torch.equal(u0, u1)
+    for sh in (0.0, -2.0):  # any shift <= 0 selects the default
+        u2, it2, _, _ = plan.pcg_solve(vd, fd, shift=sh, prec=prec, tol=1e-12)
+        assert it2 == it0 and torch.equal(u2, u0)
 
 
 class _Lines:
