@@ -113,6 +113,21 @@ sem_status sem_plan_set_workspace(sem_plan *p, void *dev_ptr, size_t bytes);
  * with S_a.  f and u are device arrays of n_x n_y n_z doubles; u may alias f. */
 sem_status sem_solve(sem_plan *p, const double *f, double *u);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, allocation-free harnesses): the solve of
+ * sem_solve, same kernels and same result bit for bit, with its intermediate
+ * array of N doubles in a fixed device array inside this library instead of the
+ * plan workspace.  Allocates nothing (no hipMalloc / hipFree, no library
+ * allocation); the first call on a device looks up that device's copy of the
+ * array, which the device holds until the process ends (SEM_NOALLOC_MAX_UNKNOWNS
+ * doubles, 64 MiB).  Every call on one device shares that array: calls that
+ * overlap on one device (concurrent streams or threads) race and must be
+ * serialised by the caller; each call leaves its last intermediate in it.
+ * f and u: device arrays of N doubles, u may alias f.  SEM_EINVAL: null
+ * arguments, or N > SEM_NOALLOC_MAX_UNKNOWNS. */
+#define SEM_NOALLOC_MAX_UNKNOWNS (8u * 1024u * 1024u)
+sem_status sem_solve_noalloc(sem_plan *p, const double *f, double *u);
+
 /* One FP64 mode product along `axis` (0 = x, 1 = y, 2 = z) with the forward
  * factor F_a (inverse = 0) or the backward factor S_a (inverse = 1):
  * out[.., l, ..] = sum_m A[l][m] in[.., m, ..].  in and out must not alias. */

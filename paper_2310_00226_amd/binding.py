@@ -43,6 +43,7 @@ def _load():
         "sem_plan_workspace_bytes": (c_int, [c_void_p, c_int, POINTER(c_size_t)]),
         "sem_plan_set_workspace": (c_int, [c_void_p, c_void_p, c_size_t]),
         "sem_solve": (c_int, [c_void_p, c_void_p, c_void_p]),
+        "sem_solve_noalloc": (c_int, [c_void_p, c_void_p, c_void_p]),
         "sem_mode_product": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
         "sem_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "sem_lift_boundary": (c_int, [c_void_p, ctypes.POINTER(c_void_p), c_void_p]),
@@ -181,6 +182,19 @@ class Plan:
         up = _dev_ptr(u, "u", self.numel, torch.float64)
         self._prepare(SEM_F64)
         check(lib.sem_solve(self._p, fp, up))
+        return u
+
+    def solve_noalloc(self, f, u=None):
+        """The FP64 solve with the library's fixed scratch array (sem_solve_noalloc):
+        binds torch's current stream, installs no workspace, allocates nothing
+        (except u when it is not given)."""
+        import torch
+        if u is None:
+            u = torch.empty_like(f)
+        fp = _dev_ptr(f, "f", self.numel, torch.float64)
+        up = _dev_ptr(u, "u", self.numel, torch.float64)
+        check(lib.sem_plan_set_stream(self._p, c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+        check(lib.sem_solve_noalloc(self._p, fp, up))
         return u
 
     def solve_refined(self, f, u=None, prec: str = "bf16", tol: float = 1e-11, max_iter: int = 30,
