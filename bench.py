@@ -124,19 +124,39 @@ def bench_batch(args, P, torch, dev, log):
            "dtype": ("f32 mode products" if best == "f32" else
                      f"split-bf16 mode products for the {nsplit} problems with every dimension >= 96, "
                      f"f32 for the rest") + ", f64 residual/update"}
+    # mode products: FP32 MFMA in the FP32 batch (the split problems of the
+    # SEM_BF16X3 batch issue three BF16 MFMAs per product)
+    mp = per_prec["f32"]["mode_product_tflops"]
+    res["roofline"] = {"bound": "mfma", "kernel": "FP32 batch, all passes (4 N (nx+ny+nz) flop per iteration)",
+                       "achieved": mp, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": mp / PEAK_FP32_TFLOPS}
     if not args.no_cpu_baseline:
         import oracle as O
-        # the two smallest problems, and the smallest one that ran split BF16,
-        # checked against the oracle
+        # the four largest problems, the two smallest and (split BF16) the two
+        # smallest split ones, each against a full oracle solve; the oracle's time
+        # on them is the batch's CPU baseline
         order = sorted(range(len(plans)), key=lambda i: plans[i].numel)
-        check = order[:2] + ([next(i for i in order if min(plans[i].shape) >= 96)] if best == "bf16x3" else [])
-        errs = []
+        check = order[-4:] + order[:2]
+        if best == "bf16x3":
+            check += [i for i in order if min(plans[i].shape) >= 96][:2]
+        errs, cpu_s, cpu_n = [], 0.0, 0
         for i in check:
             s = specs[i]
             prob = O.Problem(s["k"], s["ne"], box, s["alpha"], "dirichlet")
-            errs.append(O.rel_max_err(outs[best][i].cpu().numpy(), O.fd_solve(prob, hosts[i])))
-        res["rel_max_err_vs_oracle_sampled"] = max(errs)
-        log(f"batch: sampled rel err vs oracle {max(errs):.2e} ({len(check)} problems)")
+            t0 = time.perf_counter()
+            ref = O.fd_solve(prob, hosts[i])
+            cpu_s += time.perf_counter() - t0
+            cpu_n += plans[i].numel
+            errs.append(O.rel_max_err(outs[best][i].cpu().numpy(), ref))
+            del ref
+        res["rel_max_err_vs_oracle_checked"] = max(errs)
+        res["oracle_checked_problems"] = len(check)
+        host = host_info()
+        res["cpu_baseline"] = {"value": cpu_n / cpu_s, "unit": "unknowns/s", "cores": host["blas_threads"],
+                               "kind": "oracle", "sample": f"oracle FP64 solves of the {len(check)} checked problems "
+                                                           f"({cpu_n} unknowns, {cpu_s:.1f} s)",
+                               "cpu_model": host["cpu_model"]}
+        log(f"batch: rel err vs oracle {max(errs):.2e} ({len(check)} problems, the 4 largest among them); "
+            f"oracle {cpu_n / cpu_s:.3e} unknowns/s")
     del fs, outs, batch, plans
     torch.cuda.empty_cache()
     return res
@@ -170,11 +190,10 @@ def bench_schrodinger(args, P, torch, dev, log):
            "by_preconditioner": {}}
     u = torch.empty_like(fd)
     for prec in ("f64", "bf16x3"):
-        plan.pcg_solve(vd, fd, u, shift=alpha + beta / 2, prec=prec, tol=1e-12)  # warm-up
+        plan.pcg_solve(vd, fd, u, prec=prec, tol=1e-12)  # warm-up; default shift alpha + max(V)/2
         torch.cuda.synchronize()
         e0.record(stream)
-        _, it, rel, st = plan.pcg_solve(vd, fd, u, shift=alpha + beta / 2, prec=prec, tol=1e-12,
-                                        raise_on_error=False)
+        _, it, rel, st = plan.pcg_solve(vd, fd, u, prec=prec, tol=1e-12, raise_on_error=False)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
@@ -187,156 +206,43 @@ def bench_schrodinger(args, P, torch, dev, log):
     ok = [p for p, r in res["by_preconditioner"].items() if r["status"] == 0]
     best = min(ok, key=lambda p: res["by_preconditioner"][p]["ms_per_solve"], default="f64")
     res.update({"preconditioner": best, **res["by_preconditioner"][best]})
+    # the preconditioner's mode products dominate: their flop (the folded
+    # transforms of the BF16 modes: 2 N (nx + ny + nz) per application) over the
+    # whole solve time
+    nx, ny, nz = plan.shape
+    it_b = res["by_preconditioner"][best]["iterations"]
+    folded = best in ("bf16", "bf16x3")
+    fd_flop = (2.0 if folded else 4.0) * n * (nx + ny + nz) * (it_b + 1)
+    ach = fd_flop / (res["by_preconditioner"][best]["ms_per_solve"] * 1e-3) / 1e12
+    peak = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS}.get(best, PEAK_BF16_TFLOPS)
+    res["roofline"] = {"bound": "mfma", "kernel": "whole PCG solve, preconditioner mode products counted",
+                       "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
     del u, vd, fd, ued, plan
     torch.cuda.empty_cache()
-    # the smaller sizes of Table tab5 (A100 seconds per solve), split-BF16 preconditioner
-    paper_tab5 = {200: 0.104, 500: 1.18, 750: 5.30}
-    sizes = []
-    for nes in (40, 100, 150):
-        plan = P.Plan(5, (nes, nes, nes), SCHRODINGER_BOX, alpha, "periodic")
-        v, ue, f = schrodinger_data(*(plan.nodes(a) for a in range(3)), alpha, beta)
-        vd, fd, ued = (torch.from_numpy(a).to(dev) for a in (v, f, ue))
-        del v, f, ue
-        u = torch.empty_like(fd)
-        plan.pcg_solve(vd, fd, u, shift=alpha + beta / 2, prec="bf16x3", tol=1e-12)  # warm-up
-        torch.cuda.synchronize()
-        e0.record(stream)
-        _, it, rel, st = plan.pcg_solve(vd, fd, u, shift=alpha + beta / 2, prec="bf16x3", tol=1e-12,
-                                        raise_on_error=False)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        n = plan.shape[0]
-        err = float((u - ued).abs().max())
-        log(f"schrodinger n={n}^3: {ms:.1f} ms, {it} iterations, max error vs exact {err:.2e}; "
-            f"paper A100 {1e3 * paper_tab5[n]:.0f} ms")
-        sizes.append({"n": n, "ms_per_solve": ms, "iterations": it, "status": st, "max_err_vs_exact": err,
-                      "paper_a100_ms_per_solve": 1e3 * paper_tab5[n]})
-        del u, vd, fd, ued, plan
+    if not args.no_cpu_baseline:
+        import oracle as O
+        # a reduced mesh of the same problem against the oracle's PCG
+        ne_s = 40
+        prob = O.Problem(5, (ne_s,) * 3, SCHRODINGER_BOX, alpha, "periodic")
+        v, ue, f = schrodinger_data(*(o.x for o in prob.axes), alpha, beta)
+        t0 = time.perf_counter()
+        ref, it_ref, _ = O.pcg_schrodinger(prob, v, f, alpha + beta / 2, tol=1e-12)
+        cpu_s = time.perf_counter() - t0
+        plan = P.Plan(5, (ne_s,) * 3, SCHRODINGER_BOX, alpha, "periodic")
+        vd, fd = torch.from_numpy(v).to(dev), torch.from_numpy(f).to(dev)
+        u, it, rel, st = plan.pcg_solve(vd, fd, prec=best, tol=1e-12, raise_on_error=False)
+        err = O.rel_max_err(u.cpu().numpy(), ref)
+        host = host_info()
+        log(f"schrodinger n={prob.shape[0]}^3 vs oracle PCG: {it} iterations (oracle {it_ref}), rel err {err:.2e}; "
+            f"oracle {cpu_s:.1f} s")
+        res["oracle_check"] = {"n": prob.shape[0], "iterations": it, "oracle_iterations": it_ref,
+                               "rel_max_err_vs_oracle": err, "preconditioner": best}
+        res["cpu_baseline"] = {"value": prob.shape[0] ** 3 / cpu_s, "unit": "unknowns/s",
+                               "cores": host["blas_threads"], "kind": "oracle",
+                               "sample": f"oracle PCG at n={prob.shape[0]}^3 ({it_ref} iterations, {cpu_s:.1f} s)",
+                               "cpu_model": host["cpu_model"]}
+        del u, vd, fd, plan
         torch.cuda.empty_cache()
-    res["smaller_sizes"] = {"preconditioner": "bf16x3", "paper_context": "Table tab5, A100 (MATLAB, FP64)",
-                            "by_size": sizes}
-    return res
-
-
-def bench_paper_configs(args, P, torch, dev, log):
-    """The paper's own timed configurations at ~10^9 unknowns, measured here for
-    comparison with its figures (context, not the metric's workload): the FP64
-    solve of -Lap u + u = f, Q^5, homogeneous Neumann, [-1, 1]^3, 200^3 elements
-    (n = 1001; the paper: ~0.8 s per solve on one A100 in MATLAB), also refined
-    from split-BF16 mode products; the Cahn-Hilliard step at the same size
-    (eps = 0.02, m = 0.02, dt = 1e-3; the paper: 1.27 s per step), FP64 solve;
-    and the FP64 solve at the sizes of the paper's timing tables (201^3 .. 951^3,
-    and 1251^3 for its largest, 1250^3)."""
-    from workloads import ch_initial, normal_noise
-    box = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0)
-    res = {}
-    plan = P.Plan(5, (200, 200, 200), box, 1.0, "neumann")
-    n = plan.numel
-    f = torch.from_numpy(normal_noise(plan.shape, 2313, 1.0)).to(dev)
-    u = torch.empty_like(f)
-    ur = torch.empty_like(f)
-    stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    plan.solve(f, u)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(3):
-        plan.solve(f, u)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms64 = e0.elapsed_time(e1) / 3
-    plan.solve_refined(f, ur, prec="bf16x3", tol=args.tol, max_iter=20)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    _, its, _, st = plan.solve_refined(f, ur, prec="bf16x3", tol=args.tol, max_iter=20, raise_on_error=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    msr = e0.elapsed_time(e1)
-    err = float((ur - u).abs().max() / u.abs().max())
-    log(f"paper config (Q^5 Neumann n=1001): FP64 solve {ms64:.1f} ms, split-BF16 refined {msr:.1f} ms "
-        f"({its} iterations, rel err vs FP64 {err:.1e}); paper: ~800 ms on one A100 (MATLAB, FP64)")
-    res["solve"] = {"workload": "-Lap u + u = f, Q^5, homogeneous Neumann, [-1,1]^3, 200^3 elements (n=1001), "
-                                "f ~ N(0,1) (seed 2313)",
-                    "unknowns": n, "fp64_ms_per_solve": ms64, "fp64_unknowns_per_s": n / (ms64 * 1e-3),
-                    "bf16x3_refined_ms_per_solve": msr, "bf16x3_refined_iterations": its,
-                    "bf16x3_refined_rel_err_vs_fp64": err, "bf16x3_refined_status": st,
-                    "paper_context": "~0.8 s per solve of 1001^3 DoFs on one A100 (MATLAB, FP64), "
-                                     "Sec. 3.2 and the abstract"}
-    del f, u, ur, plan
-    torch.cuda.empty_cache()
-    ch = P.CahnHilliard(5, (200, 200, 200), box, 0.02, 0.02, 1e-3, prec="f64", refine_sweeps=0)
-    a = torch.from_numpy(ch_initial(ch.shape, 2312, 0.05)).to(dev)
-    b = a.clone()
-    steps = 10
-    ch.step(a, b, 2)  # capture + warm-up
-    torch.cuda.synchronize()
-    e0.record(stream)
-    ch.step(a, b, steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    msc = e0.elapsed_time(e1) / steps
-    ok = bool(torch.isfinite(a).all())
-    log(f"paper config CH (Q^5 n=1001, eps = m = 0.02, dt = 1e-3): {msc:.1f} ms per FP64 step; "
-        f"paper: 1.27 s per step on one A100 (MATLAB, FP64)")
-    res["cahn_hilliard"] = {"workload": "Cahn-Hilliard BDF2 step, Q^5, Neumann, [-1,1]^3, 200^3 elements (n=1001), "
-                                        "eps = 0.02, m = 0.02, dt = 1e-3, FP64 solve, graph replays",
-                            "unknowns": ch.numel, "ms_per_step": msc, "steps": steps, "finite": ok,
-                            "paper_context": "1.27 s per step of 1001^3 DoFs on one A100 (MATLAB, FP64), "
-                                             "Cahn-Hilliard section"}
-    del a, b, ch
-    torch.cuda.empty_cache()
-    # two smaller sizes of the paper's Cahn-Hilliard timing table (A100 s per step)
-    ch_sizes = []
-    for nec, paper_s in ((100, 0.0846), (150, 0.402)):
-        ch = P.CahnHilliard(5, (nec, nec, nec), box, 0.02, 0.02, 1e-3, prec="f64", refine_sweeps=0)
-        a = torch.from_numpy(ch_initial(ch.shape, 2312, 0.05)).to(dev)
-        b = a.clone()
-        ch.step(a, b, 2)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        ch.step(a, b, steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_s = e0.elapsed_time(e1) / steps
-        log(f"paper sizes: FP64 Cahn-Hilliard step n={ch.shape[0]}: {ms_s:.2f} ms; paper A100 {1e3 * paper_s:.1f} ms")
-        ch_sizes.append({"n": ch.shape[0], "ms_per_step": ms_s, "paper_a100_ms_per_step": 1e3 * paper_s})
-        del a, b, ch
-        torch.cuda.empty_cache()
-    res["cahn_hilliard"]["smaller_sizes"] = ch_sizes
-    # FP64 solve time across the sizes of the paper's timing tables (Q^5, Neumann,
-    # alpha = 1; A100 seconds for 200 solves: Table tab2 for 201^3 .. 951^3, Table
-    # tab4 for 1250^3, the largest the A100 held; here 1251^3)
-    paper_200 = {201: 0.900, 501: 11.1, 751: 53.1, 951: 134.0, 1251: 406.0}
-    sizes = []
-    for ne in (40, 100, 150, 190, 250):
-        plan = P.Plan(5, (ne, ne, ne), box, 1.0, "neumann")
-        n = plan.shape[0]
-        gen = torch.Generator(device=dev)
-        gen.manual_seed(2314)
-        f = torch.randn(plan.shape, dtype=torch.float64, device=dev, generator=gen)
-        u = torch.empty_like(f)
-        plan.solve(f, u)
-        torch.cuda.synchronize()
-        reps = 200 if n <= 201 else 10
-        e0.record(stream)
-        for _ in range(reps):
-            plan.solve(f, u)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        pa = 1e3 * paper_200[n] / 200
-        log(f"paper sizes: FP64 solve n={n}: {ms:.2f} ms ({plan.numel / (ms * 1e-3):.3e} unknowns/s); "
-            f"paper A100 {pa:.1f} ms per solve")
-        sizes.append({"n": n, "unknowns": plan.numel, "ms_per_solve": ms, "solves_timed": reps,
-                      "unknowns_per_s": plan.numel / (ms * 1e-3), "paper_a100_ms_per_solve": pa})
-        del f, u, plan
-        torch.cuda.empty_cache()
-    res["solve_sizes"] = {"workload": "FP64 solve of -Lap u + u = f, Q^5, homogeneous Neumann, [-1,1]^3, "
-                                      "N(0,1) right-hand side (torch generator, seed 2314)",
-                          "paper_context": "A100 (MATLAB, FP64) time for 200 solves / 200, Tables tab2 and tab4 "
-                                           "(1250^3 there, 1251^3 here)",
-                          "by_size": sizes}
     return res
 
 
@@ -345,9 +251,6 @@ def bench_paper_configs(args, P, torch, dev, log):
 # (FETCH x 1.970, WRITE x 1.000); recorded here because counters cannot be read
 # inside the timed run.  Variants without such runs report null.
 PROFILED_TRAFFIC = {
-    # one split-BF16 FD application (conversion + six passes, sem_solve_lowp)
-    "bf16x3": {"fetch_bytes": 49.21e9, "write_bytes": 36.23e9,
-               "algorithmic_bytes": 65.0e9, "source": "profiles/split_bf16_refined_n999.md"},
     # one FP64 y-axis mode product (mode_nn_f64)
     "f64": {"fetch_bytes": 38.6e9, "write_bytes": 8.23e9,
             "algorithmic_bytes": 15.97e9, "source": "profiles/mode_f64_n999.md"},
@@ -392,12 +295,43 @@ def bench_ch(args, P, torch, dev, log):
     drift = abs(float(np.sum(m3 * phi)) - float(np.sum(m3 * phi0))) / float(np.sum(m3 * np.abs(phi0)))
     log(f"cahn-hilliard: {args.ch_steps} steps in {ms:.0f} ms ({ms / args.ch_steps:.3f} ms/step, "
         f"{n * args.ch_steps / (ms * 1e-3):.3e} unknown-steps/s), relative mass drift {drift:.1e}")
-    return {"workload": "Cahn-Hilliard IMEX (BDF2), [0,2pi]^3 Neumann, Q^4 64^3 elements, n=257, eps=0.05, "
-                        "m=0.02, dt=1e-4, phi0 ~ U[-0.05,0.05] (seed 2312)",
-            "steps": args.ch_steps, "ms_per_step": ms / args.ch_steps,
-            "unknown_steps_per_s": n * args.ch_steps / (ms * 1e-3), "unknowns": n,
-            "dtype": "f32 solve + 1 f64 refinement sweep", "graph": True, "relative_mass_drift": drift,
-            "max_abs_phi": float(np.max(np.abs(phi)))}
+    # per step: one FP32 FD application (six mode products, 4 N (n_x + n_y + n_z) flop)
+    # and the FP64 banded passes of the right-hand side and of the sweep
+    nx, ny, nz = ch.shape
+    fd_flop = 4.0 * n * (nx + ny + nz)
+    ach = fd_flop / (ms / args.ch_steps * 1e-3) / 1e12
+    res = {"workload": "Cahn-Hilliard IMEX (BDF2), [0,2pi]^3 Neumann, Q^4 64^3 elements, n=257, eps=0.05, "
+                       "m=0.02, dt=1e-4, phi0 ~ U[-0.05,0.05] (seed 2312)",
+           "steps": args.ch_steps, "ms_per_step": ms / args.ch_steps,
+           "unknown_steps_per_s": n * args.ch_steps / (ms * 1e-3), "unknowns": n,
+           "dtype": "f32 solve + 1 f64 refinement sweep", "graph": True, "relative_mass_drift": drift,
+           "max_abs_phi": float(np.max(np.abs(phi))),
+           "roofline": {"bound": "mfma", "kernel": "whole step (FD application counted: 4 N (nx+ny+nz) flop)",
+                        "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS}}
+    if args.ch_oracle_steps > 0 and not args.no_cpu_baseline:
+        import oracle as O
+        # the same start, args.ch_oracle_steps steps on the GPU and in the oracle
+        a.copy_(torch.from_numpy(phi0))
+        b.copy_(a)
+        ch.step(a, b, args.ch_oracle_steps)
+        phi_gpu = a.cpu().numpy()
+        prob = O.Problem(4, (64, 64, 64), box, 0.0, "neumann")
+        cur, prev = phi0, phi0
+        t0 = time.perf_counter()
+        for _ in range(args.ch_oracle_steps):
+            cur, prev = O.ch_step(prob, cur, prev, 0.05, 0.02, 1e-4), cur
+        cpu_s = time.perf_counter() - t0
+        err = O.rel_max_err(phi_gpu, cur)
+        host = host_info()
+        log(f"cahn-hilliard: after {args.ch_oracle_steps} steps rel max err vs oracle {err:.2e}; oracle "
+            f"{cpu_s / args.ch_oracle_steps:.2f} s/step on {host['blas_threads']} threads")
+        res["rel_err_vs_oracle"] = err
+        res["rel_err_vs_oracle_after_steps"] = args.ch_oracle_steps
+        res["cpu_baseline"] = {"value": n * args.ch_oracle_steps / cpu_s, "unit": "unknown-steps/s",
+                               "cores": host["blas_threads"], "kind": "oracle",
+                               "sample": f"{args.ch_oracle_steps} oracle steps of the same workload from the same "
+                                         f"phi0, {cpu_s:.1f} s", "cpu_model": host["cpu_model"]}
+    return res
 
 
 def main() -> int:
@@ -415,10 +349,10 @@ def main() -> int:
                     help="problems in the batched leg (k in 2..8, 8..64 elements per axis); 0 skips it")
     ap.add_argument("--ch-steps", type=int, default=1000,
                     help="Cahn-Hilliard steps at n = 257 (64^3 Q^4 elements); 0 skips the leg")
+    ap.add_argument("--ch-oracle-steps", type=int, default=20,
+                    help="Cahn-Hilliard steps compared with (and timed in) the oracle; 0 skips")
     ap.add_argument("--schrodinger-ne", type=int, default=200,
                     help="elements per axis of the variable-coefficient PCG leg (0 = skip)")
-    ap.add_argument("--no-paper-configs", action="store_true",
-                    help="skip the paper's own timed configurations (context)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain elementwise copy of f (N*8 bytes read + written) so that HBM "
                          "counters of the kernels can be scaled against a kernel of known traffic")
@@ -469,11 +403,13 @@ def main() -> int:
     log(f"FP64 solve: {ms:.2f} ms/step, {value:.3e} unknowns/s")
 
     variants = {"f64": {"ms_per_solve": ms, "unknowns_per_s": value, "iterations": 1, "rel_err_vs_f64": 0.0}}
+    outputs = {"f64": u}  # every variant's solution stays on the device for the oracle comparison
     want = [v for v in args.variants.split(",") if v and v != "f64"]
     if want:
-        ur = torch.empty_like(f)
         scale = float(u.abs().max())
         for prec in want:
+            ur = torch.empty_like(f)
+            outputs[f"{prec}_refined"] = ur
             _, it, rel, st = plan.solve_refined(f, ur, prec=prec, tol=args.tol, max_iter=40, raise_on_error=False)
             torch.cuda.synchronize()
             for _ in range(max(0, args.warmup - 1)):
@@ -492,10 +428,11 @@ def main() -> int:
                                            "rel_err_vs_f64": err}
             log(f"{prec} refined: {vms:.2f} ms/solve, {N / (vms * 1e-3):.3e} unknowns/s, {it} iterations, "
                 f"rel err vs FP64 {err:.2e}, status {st}")
-        del ur
     ok = {k: v for k, v in variants.items() if v["rel_err_vs_f64"] <= 1e-10 and v.get("status", 0) == 0}
     best = max(ok, key=lambda k: ok[k]["unknowns_per_s"])
-    fd_flops = 4.0 * N * (nx + ny + nz)  # six mode products, 2 n_a N flop each
+    fd_flops = 4.0 * N * (nx + ny + nz)  # six dense mode products, 2 n_a N flop each
+    nrep = [P.axis_fold_host(k, ne[a], box[2 * a], box[2 * a + 1], "dirichlet")["nrep"] for a in range(3)]
+    folded_flops = 4.0 * N * sum(nrep)  # the reflection-split passes: half-length blocks
 
     # dominant kernel group of a refined variant: one low-precision FD application
     # (its six mode-product launches, the right-hand side conversion included),
@@ -519,12 +456,18 @@ def main() -> int:
         fd_ms = e0.elapsed_time(e1) / args.kernel_reps
         del ul
         peak = PEAK_FP32_TFLOPS if prec == "f32" else PEAK_BF16_TFLOPS
-        ach = fd_flops / (fd_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": f"{prec} FD application: six mode_rot passes "
-                                           f"({'mode_rot_dma' if prec != 'f32' else 'mode_rot_f32'})",
+        # the BF16 modes run the reflection-split transforms: each pass contracts
+        # half-length blocks, 4 N sum_a nrep_a flop per application (nrep_a =
+        # orbit representatives of axis a, ~n_a / 2); FP32 the dense 4 N sum_a n_a
+        flops = folded_flops if prec != "f32" else fd_flops
+        ach = flops / (fd_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": f"{prec} FD application: " +
+                ("fold + six reflection-split mode_rot_dma passes + unfold" if prec != "f32" else
+                 "six mode_rot_f32 passes"),
                 "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
                 "traffic": _traffic(prec), "traffic_detail": PROFILED_TRAFFIC.get(prec),
-                "launch_ms": fd_ms, "flops_per_launch": fd_flops,
+                "launch_ms": fd_ms, "flops_per_launch": flops,
+                "dense_equivalent_tflops": fd_flops / (fd_ms * 1e-3) / 1e12,
                 "mfma_work_factor": 3 if prec == "bf16x3" else 1}
         v["fd_application"] = roof
         log(f"{prec} FD application alone: {fd_ms:.2f} ms, {ach:.1f} TFLOP/s algorithmic "
@@ -606,14 +549,11 @@ def main() -> int:
         out["cahn_hilliard"] = bench_ch(args, P, torch, dev, log)
     if args.schrodinger_ne > 0:
         out["schrodinger_pcg"] = bench_schrodinger(args, P, torch, dev, log)
-    if not args.no_paper_configs:
-        out["paper_configs"] = bench_paper_configs(args, P, torch, dev, log)
 
     if not args.no_cpu_baseline:
         import oracle as O
         host = host_info()
-        u_host = u.cpu().numpy()
-        del u, f
+        del f
         torch.cuda.empty_cache()
         log("oracle: plan (untimed) ...")
         prob = O.Problem(k, ne, box, alpha, "dirichlet")
@@ -621,8 +561,16 @@ def main() -> int:
         t0 = time.perf_counter()
         u_ref = O.fd_solve(prob, f_host)
         cpu_s = time.perf_counter() - t0
-        err = O.rel_max_err(u_host, u_ref)
-        log(f"oracle solve {cpu_s:.1f}s; GPU rel max err vs oracle {err:.3e}")
+        uref_d = torch.from_numpy(u_ref).to(dev)
+        ref_scale = float(uref_d.abs().max())
+        for name, out_d in outputs.items():
+            e_or = float((out_d - uref_d).abs().max()) / ref_scale
+            variants[name]["rel_err_vs_oracle"] = e_or
+            log(f"{name}: rel max err vs oracle {e_or:.3e}")
+        err = variants["f64"]["rel_err_vs_oracle"]
+        del uref_d, outputs, u
+        torch.cuda.empty_cache()
+        log(f"oracle solve {cpu_s:.1f}s; GPU FP64 rel max err vs oracle {err:.3e}")
         out["cpu_baseline"] = {"value": N / cpu_s, "unit": "unknowns/s", "cores": host["blas_threads"],
                                "kind": "oracle",
                                "sample": f"one full oracle FP64 solve of the same n={nx} workload "

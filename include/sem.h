@@ -245,13 +245,15 @@ sem_status sem_pcg_solve(sem_plan *p, const double *v, double shift, sem_prec pr
 typedef struct sem_batch sem_batch;
 
 /* A batch of `count` independent problems, one plan each (any mix of k <= 8,
- * element counts, boxes, alpha and BC; all on one device).  The plans are not
- * owned and must outlive the batch; the batch uses their workspaces.  Creation
- * prepares the FP32 factors and workspaces of every plan, then times the
- * candidate tile shapes of the FP32 mode-product kernel on the batch's own passes
- * and keeps the fastest per contraction-length bucket.
- * Synchronous.  SEM_EINVAL: count < 1, a null or repeated plan, k > 8, plans on
- * different devices. */
+ * element counts, boxes, alpha and BC; all on one device).  A plan may appear
+ * more than once: several right-hand sides of one operator, solved together; the
+ * entries after its first occurrence get workspaces of their own (allocated by
+ * the batch), the first uses the plan's.  The plans are not owned and must
+ * outlive the batch.  Creation prepares the FP32 factors and workspaces of every
+ * entry, then times the candidate tile shapes of the FP32 mode-product kernel on
+ * the batch's own passes and keeps the fastest per contraction-length bucket.
+ * Synchronous.  SEM_EINVAL: count < 1, a null plan, k > 8, plans on different
+ * devices. */
 sem_status sem_batch_create(int count, sem_plan *const *plans, sem_batch **out);
 void sem_batch_destroy(sem_batch *b);
 sem_status sem_batch_set_stream(sem_batch *b, void *hip_stream);
@@ -326,6 +328,21 @@ sem_status sem_ch_step(sem_ch *c, double *phi_n, double *phi_nm1, int nsteps);
  * be NULL.  S: backward factor (K S = M S Lambda, S^T M S = I); F = S^T M. */
 sem_status sem_axis_host(int k, int ne, double a, double b, sem_bc bc, int *n, double *x, double *mass, double *lam,
                          double *S, double *F);
+
+/* Host-only helper: the reflection-split form of the same axis that the BF16
+ * passes use.  The uniform mesh is symmetric about the midpoint, node i maps to
+ * R(i) = n - 1 - i (periodic: (n - i) mod n), and every eigenvector is symmetric
+ * or antisymmetric.  nrep: orbit representatives 0..nrep-1 of {i, R(i)}; nodd =
+ * n - nrep antisymmetric eigenvectors.  Folded mode order: nrep symmetric then
+ * nodd antisymmetric, each ascending (lam_fold, n values).  With the folded vector
+ * v+_r = v_r + v_R(r), v-_r = v_r - v_R(r) (r < nrep): F v = [ffold_sym v+;
+ * ffold_anti v-] where ffold (n x nrep, row-major) holds both blocks in folded
+ * mode order; and for folded coefficients c = [c_sym; c_anti] the backward
+ * transform is u_r = e_r + o_r, u_R(r) = e_r - o_r with e = bfold_sym c_sym
+ * (nrep x nrep) and o = bfold_anti c_anti (nrep x nodd).  Pass NULL for outputs not
+ * wanted; nrep, nodd may be queried first with all arrays NULL. */
+sem_status sem_axis_fold_host(int k, int ne, double a, double b, sem_bc bc, int *nrep, int *nodd, double *lam_fold,
+                              double *ffold, double *bfold_sym, double *bfold_anti);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char *sem_last_error(void);

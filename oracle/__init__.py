@@ -19,6 +19,8 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   fd_solve, apply_h3, residual, residual_at, dense_system          pinned
   ch_step                                                          pinned
   schrodinger_apply, pcg_schrodinger                               pinned
+    (its iteration counts: pinned at beta = 1 by Table tab7c's 10; parity
+     unpinned at beta >= 10, where no reading of the stop reproduces the table)
   spectral_apply                                                   pinned
   periodic boundary condition (axis_operators, axis_eigen, Problem) pinned
   lift_boundary                                                    pinned

@@ -55,6 +55,8 @@ def _load():
         "sem_pcg_solve": (c_int, [c_void_p, c_void_p, c_double, c_int, c_double, c_int, c_void_p, c_void_p,
                                   c_void_p, c_size_t, POINTER(c_int), POINTER(c_double), POINTER(c_double)]),
         "sem_axis_host": (c_int, [c_int, c_int, c_double, c_double, c_int, POINTER(c_int), dp, dp, dp, dp, dp]),
+        "sem_axis_fold_host": (c_int, [c_int, c_int, c_double, c_double, c_int, POINTER(c_int), POINTER(c_int), dp,
+                                       dp, dp, dp]),
         "sem_batch_create": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p)]),
         "sem_batch_destroy": (None, [c_void_p]),
         "sem_batch_set_stream": (c_int, [c_void_p, c_void_p]),
@@ -104,6 +106,22 @@ def _dev_ptr(t, name, n=None, dtype=None):
     if n is not None and t.numel() != n:
         raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
     return c_void_p(t.data_ptr())
+
+
+def axis_fold_host(k: int, ne: int, a: float, b: float, bc: str):
+    """Reflection-split form of one axis (host only): dict of nrep, nodd, lam_fold,
+    ffold (n x nrep), bfold_sym (nrep x nrep), bfold_anti (nrep x nodd)."""
+    import numpy as np
+    bcv = _BC[bc]
+    nr, no = c_int(0), c_int(0)
+    check(lib.sem_axis_fold_host(k, ne, a, b, bcv, ctypes.byref(nr), ctypes.byref(no), None, None, None, None))
+    nr, no = nr.value, no.value
+    n = nr + no
+    out = {"nrep": nr, "nodd": no, "lam_fold": np.empty(n), "ffold": np.empty((n, nr)),
+           "bfold_sym": np.empty((nr, nr)), "bfold_anti": np.empty((nr, max(no, 0)))}
+    check(lib.sem_axis_fold_host(k, ne, a, b, bcv, None, None, _dptr(out["lam_fold"]), _dptr(out["ffold"]),
+                                 _dptr(out["bfold_sym"]), _dptr(out["bfold_anti"]) if no else None))
+    return out
 
 
 def axis_host(k: int, ne: int, a: float, b: float, bc: str):

@@ -79,6 +79,11 @@ struct sem_batch {
   int count = 0;
   std::vector<sem_plan*> plans;
   std::vector<LpWork> lw;
+  // entries whose plan already occurred earlier in the list (several right-hand
+  // sides of one operator) get a workspace of their own
+  std::vector<char> repeat;
+  std::vector<void*> own_ws;
+  std::vector<size_t> own_bytes;
   hipStream_t stream = nullptr;
   int cus = 1;
   int tile_rows[NBUCKET] = {0, 0, 0, 0, 0, 0};
@@ -305,6 +310,29 @@ sem_status autotune(sem_batch* b) {
   return st;
 }
 
+// Low-precision factors of entry i's plan and the entry's workspace laid out for
+// prec: the plan's own workspace, or for a repeated plan the entry's own one.
+sem_status prepare_entry(sem_batch* b, int i, sem_prec prec) {
+  sem_plan* p = b->plans[i];
+  if (!b->repeat[i]) return lp_prepare(p, prec, &b->lw[i]);
+  sem_status st = lp_factors(p, prec);
+  if (st != SEM_OK) return st;
+  const size_t need = workspace_need(p, prec);
+  if (b->own_bytes[i] < need) {
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "sem_batch: workspace resize");
+    (void)hipFree(b->own_ws[i]);
+    b->own_ws[i] = nullptr;
+    b->own_bytes[i] = 0;
+    if ((e = hipMalloc(&b->own_ws[i], need)) != hipSuccess) {
+      b->own_ws[i] = nullptr;
+      return hip_fail(e, "sem_batch: workspace allocation");
+    }
+    b->own_bytes[i] = need;
+  }
+  return lp_layout(p, prec, b->own_ws[i], &b->lw[i]);
+}
+
 // One refinement iteration of solve i in split BF16 on `stream`: the FP64
 // residual written as split BF16 (from the second iteration on), then the FD
 // application that stores (first iteration) or accumulates the update into u and
@@ -352,6 +380,7 @@ void sem_batch_destroy(sem_batch* b) {
     if (b->ev_side[s]) (void)hipEventDestroy(b->ev_side[s]);
   }
   if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+  for (void* w : b->own_ws) (void)hipFree(w);
   (void)hipFree(b->d_desc);
   (void)hipFree(b->d_rdesc);
   (void)hipFree(b->d_active);
@@ -369,16 +398,19 @@ sem_status sem_batch_create(int count, sem_plan* const* plans, sem_batch** out) 
     if (plans[i]->k > 8) return set_error(SEM_EINVAL, "sem_batch_create: batched residual supports k <= 8");
     if (i == 0) dev = plans[i]->device;
     if (plans[i]->device != dev) return set_error(SEM_EINVAL, "sem_batch_create: plans on different devices");
-    for (int j = 0; j < i; ++j)
-      if (plans[j] == plans[i]) return set_error(SEM_EINVAL, "sem_batch_create: a plan appears twice");
   }
   sem_batch* b = new (std::nothrow) sem_batch;
   if (!b) return set_error(SEM_ENOMEM, "sem_batch_create: host allocation");
   b->count = count;
   b->plans.assign(plans, plans + count);
   b->lw.resize(count);
+  b->repeat.assign(count, 0);
+  b->own_ws.assign(count, nullptr);
+  b->own_bytes.assign(count, 0);
+  for (int i = 0; i < count; ++i)
+    for (int j = 0; j < i && !b->repeat[i]; ++j) b->repeat[i] = plans[j] == plans[i];
   for (int i = 0; i < count; ++i) {
-    sem_status st = lp_prepare(plans[i], SEM_F32, &b->lw[i]);
+    sem_status st = prepare_entry(b, i, SEM_F32);
     if (st != SEM_OK) {
       sem_batch_destroy(b);
       return st;
@@ -460,7 +492,7 @@ sem_status sem_batch_solve(sem_batch* b, sem_prec prec, double tol, int max_iter
   for (int i = 0; i < n; ++i) {
     const int* d = b->plans[i]->dims;
     split[i] = prec == SEM_BF16X3 && std::min({d[0], d[1], d[2]}) >= SPLIT_MIN_DIM;
-    sem_status st = lp_prepare(b->plans[i], split[i] ? SEM_BF16X3 : SEM_F32, &b->lw[i]);
+    sem_status st = prepare_entry(b, i, split[i] ? SEM_BF16X3 : SEM_F32);
     if (st != SEM_OK) return st;
   }
   sem_status st = build_descs(b, f, u, split);

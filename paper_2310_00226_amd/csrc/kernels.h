@@ -72,6 +72,10 @@ struct EpiLP {
 // The direct-to-LDS kernels (mode_dma.hip) take BF16 operands only: split-BF16
 // operands are two planes, the second xplane / yplane / fplane elements after
 // the first (f_lo unused).
+// Output column layouts of the BF16 passes (mode_dma.hip): plain, split mode
+// layout (symmetric block, then antisymmetric from column bpad), folded pairs.
+enum { COL_PLAIN = 0, COL_SPLIT = 1, COL_FOLD = 2 };
+
 struct LpPass {
   int mode = LP_BF16;
   const void* x = nullptr;
@@ -87,6 +91,20 @@ struct LpPass {
   int in_kind = 0, out_kind = 0, epi_kind = EPI_STORE;
   long xplane = 0, yplane = 0, fplane = 0;
   EpiLP epi;
+  // BF16 passes only: a second contraction block (K2 > 0): its l-tiles read factor
+  // rows from frow2 (>= L rounded up to 256) and tensor k in [koff2, koff2 + K2),
+  // and write L2 output rows after the L of block 1 (K, L: block 1)
+  int K2 = 0, koff2 = 0, frow2 = 0, L2 = 0;
+  // output column layout (COL_*) and the b axis: COL_SPLIT: bsym symmetric modes,
+  // antisymmetric from column bpad; COL_FOLD: bsym = orbit representatives of the
+  // b axis (length bn, periodic bper), v+ at column r, v- at bpad + r
+  int col = COL_PLAIN;
+  int bsym = 0, bpad = 0, bn = 0, bper = 0;
+  // tuned launch shapes: FP32 factor-tile rows (128, 96, 64, 32; 0 = by rule);
+  // BF16 tile order: groups of tile_group p-strips step through the l-tiles
+  // together (1 = every l-tile of one p-strip in a row)
+  int tile_rows = 0;
+  int tile_group = 1;
 };
 // FP32 passes (mode_lp.hip): mode LP_F32, in_kind 0 or 1, out_kind 1 or 0 (accumulate).
 hipError_t launch_mode_lp(const LpPass& ps, hipStream_t stream);
@@ -114,15 +132,31 @@ hipError_t launch_mode_f32_batch(int in_kind, int out_kind, int epi, int tile_ro
 int lp_batch_blocks_per_cu(int tile_rows);
 
 // ---- BF16 / split-BF16 passes with direct global -> LDS loads (mode_dma.hip) ----
-// Requirements: in_kind 2, ldx and ldf multiples of 8, ldx >= K, ldf >= L and K
-// rounded up to 256; tensor pitch padding [K, ldx) holds finite values; factor
-// zero outside L x K.  Output BF16 planes get their pitch padding [B, ldy) zeroed.
+// Requirements: in_kind 2, ldx, ldy and ldf multiples of 8, each contraction
+// block inside the tensor pitch and the factor pitch rounded to 32; tensor pitch
+// padding holds finite values; factor zero outside its blocks.  Outputs: BF16
+// planes (out_kind 2, any column layout, STORE or DIVIDE) or FP32 (out_kind 1,
+// COL_PLAIN, STORE).  Padding columns receive finite values.
 bool dma_supported(const LpPass& ps);
 hipError_t launch_mode_dma(const LpPass& ps, hipStream_t stream);
+// Reflection split of one axis: nrep orbit representatives (v+ at columns
+// [0, pad), v- at [pad, 2 pad) of a folded row), reflection n - 1 - r or, per,
+// (n - r) mod n.
+struct FoldAxis {
+  int nrep = 0, pad = 0, per = 0;
+};
 // FP64 array (rows dims[0]*dims[1], pitch dims[2]) -> BF16 hi (+ lo plane plane_o
-// elements later when split) with pitch ldo, padding zeroed.
+// elements later when split) with pitch ldo, padding zeroed; fold != null: the rows
+// folded along z first.
 hipError_t launch_to_lowp(const double* f, void* out, long plane_o, int split, const int dims[3], int ldo,
-                          hipStream_t stream);
+                          const FoldAxis* fold, hipStream_t stream);
+// BF16 (split) rows of pitch ldi -> the same rows folded along z, pitch ldo.
+hipError_t launch_fold_lowp(const void* in, long plane_i, int ldi, void* out, long plane_o, int ldo, int split,
+                            const int dims[3], const FoldAxis& fold, hipStream_t stream);
+// u (+)= the correction d (FP32, every axis in folded node form: e rows then o
+// rows, pitch ldd for z''), see unfold_accum_kernel.
+hipError_t launch_unfold_accum(const float* d, int ldd, double* u, const int dims[3], const FoldAxis fold[3],
+                               int first, unsigned long long* norms, hipStream_t stream);
 
 // Generalised nodal residual  r = cf f - cd d - ch (H_x + H_y + H_z) v  with banded
 // H rows hb[a][g * (2k+1) + d] = H_a(g, g - k + d), FP64 arithmetic.

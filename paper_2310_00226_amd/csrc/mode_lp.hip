@@ -362,8 +362,15 @@ hipError_t launch_mode_lp(const LpPass& ps, hipStream_t stream) {
   d.L = ps.L;
   d.ldf = ps.ldf;
   using namespace f32k;
-  // 96-row factor tiles when they cover L with clearly fewer padded rows (e.g.
-  // L = 257: 288 rows instead of 384)
+  // a tuned tile shape, else 96-row factor tiles when they cover L with clearly
+  // fewer padded rows (e.g. L = 257: 288 rows instead of 384)
+  switch (ps.tile_rows) {
+    case 128: return launch_single_tile<T128>(d, ps, stream);
+    case 96: return launch_single_tile<T96>(d, ps, stream);
+    case 64: return launch_single_tile<T64>(d, ps, stream);
+    case 32: return launch_single_tile<T32>(d, ps, stream);
+    default: break;
+  }
   const long r128 = (ps.L + 127) / 128 * 128, r96 = (ps.L + 95) / 96 * 96;
   if (r96 * 10 < r128 * 9) return launch_single_tile<T96>(d, ps, stream);
   return launch_single_tile<T128>(d, ps, stream);

@@ -278,7 +278,23 @@ void gll_rule(int k, std::vector<double>& x, std::vector<double>& w) {
     for (int j = 1; j <= m - 1; ++j) e[j - 1] = std::sqrt((double)j * (j + 2) / ((2.0 * j + 1) * (2.0 * j + 3)));
     tridiag_qr(m, d.data(), e.data(), nullptr, 0, 1);
     std::sort(d.begin(), d.end());
-    for (int j = 0; j < m; ++j) x[j + 1] = d[j];
+    // the eigenvalues carry errors of a few ulps; two Newton steps on P_k' in long
+    // double (P_k'' from Legendre's equation) round them correctly
+    for (int j = 0; j < m; ++j) {
+      long double t = d[j];
+      for (int it = 0; it < 2; ++it) {
+        long double p0 = 1.0L, p1 = t;
+        for (int q = 1; q < k; ++q) {
+          const long double p2 = ((2.0L * q + 1.0L) * t * p1 - (long double)q * p0) / (long double)(q + 1);
+          p0 = p1;
+          p1 = p2;
+        }
+        const long double dp = k * (t * p1 - p0) / (t * t - 1.0L);
+        const long double d2p = (2.0L * t * dp - (long double)k * (k + 1) * p1) / (1.0L - t * t);
+        t -= dp / d2p;
+      }
+      x[j + 1] = (double)t;
+    }
     // enforce the exact symmetry of the rule
     for (int j = 1; j < k; ++j) {
       double s = 0.5 * (x[j] - x[k - j]);
@@ -348,18 +364,21 @@ static void parallel_rows(int n, int nthreads, F&& fn) {
 // ((k+1)^2, already divided by h): FP64 rounding of K's entries alone would shift
 // the lowest eigenvalues by ~ eps * lambda_max, since they come out of a
 // cancellation of ratio lambda_max / lambda_min.
-static void refine_eigenpairs(int n, int k, int ne, const std::vector<long double>& ke, int off, bool per,
+static void refine_eigenpairs(int n, int m, int k, int ne, const std::vector<long double>& ke, int off, bool per,
                               const std::vector<double>& mass, std::vector<double>& lam, std::vector<double>& S,
                               int nthreads) {
+  // S: n x m (m eigenvectors of one invariant subspace, e.g. the symmetric ones),
+  // lam: m.  Rows of X that are equal (or opposite) stay so: every row is updated
+  // by the same arithmetic from its own entries.
   typedef long double ld;
   const int np = k + 1, nfull = ne * k + 1;
-  const size_t nn = (size_t)n * n;
-  std::vector<ld> X(nn), KX(nn), T(nn), R(nn), L(n);
-  for (size_t t = 0; t < nn; ++t) X[t] = S[t];
+  const size_t nm = (size_t)n * m, mm = (size_t)m * m;
+  std::vector<ld> X(nm), KX(nm), T(mm), R(mm), L(m);
+  for (size_t t = 0; t < nm; ++t) X[t] = S[t];
   parallel_rows(n, nthreads, [&](int p0, int p1) {
     for (int p = p0; p < p1; ++p) {
-      ld* row = &KX[(size_t)p * n];
-      std::fill(row, row + n, 0.0L);
+      ld* row = &KX[(size_t)p * m];
+      std::fill(row, row + m, 0.0L);
       // periodic: full nodes p and p + n are one unknown (only p = 0 has the alias)
       for (int alias = 0; alias <= (per ? 1 : 0); ++alias) {
         const int pf = p + off + alias * n;  // full-numbering index
@@ -372,35 +391,35 @@ static void refine_eigenpairs(int n, int k, int ne, const std::vector<long doubl
             const int qf = e * k + lj, q = per ? qf % n : qf - off;
             if (q < 0 || q >= n || qf >= nfull) continue;
             const ld kv = ke[(size_t)li * np + lj];
-            const ld* xq = &X[(size_t)q * n];
-            for (int j = 0; j < n; ++j) row[j] += kv * xq[j];
+            const ld* xq = &X[(size_t)q * m];
+            for (int j = 0; j < m; ++j) row[j] += kv * xq[j];
           }
         }
       }
     }
   });
-  parallel_rows(n, nthreads, [&](int i0, int i1) {
+  parallel_rows(m, nthreads, [&](int i0, int i1) {
     for (int i = i0; i < i1; ++i) {
-      ld* ti = &T[(size_t)i * n];
-      ld* ri = &R[(size_t)i * n];
-      std::fill(ti, ti + n, 0.0L);
-      std::fill(ri, ri + n, 0.0L);
+      ld* ti = &T[(size_t)i * m];
+      ld* ri = &R[(size_t)i * m];
+      std::fill(ti, ti + m, 0.0L);
+      std::fill(ri, ri + m, 0.0L);
       for (int p = 0; p < n; ++p) {
-        const ld xpi = X[(size_t)p * n + i];
+        const ld xpi = X[(size_t)p * m + i];
         const ld mx = (ld)mass[p] * xpi;
-        const ld* kxp = &KX[(size_t)p * n];
-        const ld* xp = &X[(size_t)p * n];
-        for (int j = 0; j < n; ++j) {
+        const ld* kxp = &KX[(size_t)p * m];
+        const ld* xp = &X[(size_t)p * m];
+        for (int j = 0; j < m; ++j) {
           ti[j] += xpi * kxp[j];
           ri[j] += mx * xp[j];
         }
       }
-      for (int j = 0; j < n; ++j) ri[j] = (i == j ? 1.0L : 0.0L) - ri[j];
+      for (int j = 0; j < m; ++j) ri[j] = (i == j ? 1.0L : 0.0L) - ri[j];
     }
   });
   ld lmax = 0;
-  for (int i = 0; i < n; ++i) {
-    L[i] = T[(size_t)i * n + i] / (1.0L - R[(size_t)i * n + i]);
+  for (int i = 0; i < m; ++i) {
+    L[i] = T[(size_t)i * m + i] / (1.0L - R[(size_t)i * m + i]);
     lmax = std::max(lmax, std::fabs(L[i]));
   }
   // Pairs closer than tiny keep only the symmetric part of the update (no rotation
@@ -411,9 +430,9 @@ static void refine_eigenpairs(int n, int k, int ne, const std::vector<long doubl
   // in S^T M S; inside such a pair any M-orthonormal basis is accurate to
   // eps lambda_max in K s - lambda M s.
   const ld tiny = (per ? 1e-8L : 1e-15L) * (lmax > 0 ? lmax : 1.0L);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      const size_t ij = (size_t)i * n + j;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      const size_t ij = (size_t)i * m + j;
       if (i == j) {
         T[ij] = 0.5L * R[ij];
       } else {
@@ -422,29 +441,29 @@ static void refine_eigenpairs(int n, int k, int ne, const std::vector<long doubl
       }
     }
   parallel_rows(n, nthreads, [&](int p0, int p1) {
-    std::vector<ld> acc(n);
+    std::vector<ld> acc(m);
     for (int p = p0; p < p1; ++p) {
-      const ld* xp = &X[(size_t)p * n];
-      for (int j = 0; j < n; ++j) acc[j] = xp[j];
-      for (int i = 0; i < n; ++i) {
+      const ld* xp = &X[(size_t)p * m];
+      for (int j = 0; j < m; ++j) acc[j] = xp[j];
+      for (int i = 0; i < m; ++i) {
         const ld xpi = xp[i];
-        const ld* ei = &T[(size_t)i * n];
-        for (int j = 0; j < n; ++j) acc[j] += xpi * ei[j];
+        const ld* ei = &T[(size_t)i * m];
+        for (int j = 0; j < m; ++j) acc[j] += xpi * ei[j];
       }
-      for (int j = 0; j < n; ++j) S[(size_t)p * n + j] = (double)acc[j];
+      for (int j = 0; j < m; ++j) S[(size_t)p * m + j] = (double)acc[j];
     }
   });
   // keep ascending order
-  std::vector<int> idx(n);
+  std::vector<int> idx(m);
   std::iota(idx.begin(), idx.end(), 0);
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return L[a] < L[b]; });
   bool sorted = true;
-  for (int i = 0; i < n; ++i) sorted = sorted && idx[i] == i;
+  for (int i = 0; i < m; ++i) sorted = sorted && idx[i] == i;
   std::vector<double> Sn = sorted ? std::vector<double>() : S;
-  for (int c = 0; c < n; ++c) {
+  for (int c = 0; c < m; ++c) {
     lam[c] = (double)L[idx[c]];
     if (!sorted)
-      for (int r = 0; r < n; ++r) S[(size_t)r * n + c] = Sn[(size_t)r * n + idx[c]];
+      for (int r = 0; r < n; ++r) S[(size_t)r * m + c] = Sn[(size_t)r * m + idx[c]];
   }
 }
 
@@ -592,25 +611,109 @@ void build_axis(const AxisSpec& spec, AxisData& out, int nthreads) {
       if (col < 0) continue;
       s1[(size_t)g * n + col] += kb[(size_t)(g + off) * bw + d] / (mh[g] * mh[col]);
     }
-  for (int i = 0; i < n; ++i)
-    for (int j = i + 1; j < n; ++j) {
-      double v = 0.5 * (s1[(size_t)i * n + j] + s1[(size_t)j * n + i]);
-      s1[(size_t)i * n + j] = s1[(size_t)j * n + i] = v;
+  // The uniform mesh is symmetric about the midpoint of [a, b]: the reflection
+  // node i -> R(i) (n - 1 - i; periodic (n - i) mod n) commutes with K and M, so
+  // every eigenvector can be taken symmetric (R s = s) or antisymmetric (R s = -s)
+  // and the eigenproblem splits into one on the nrep orbit representatives
+  // 0..nrep-1 and one on the nodd pairs {r, R(r)}, r != R(r).  Each block is
+  // solved (Householder + implicit QR) and refined on its own; the eigenvectors
+  // are built from the blocks, so mirrored entries are equal or opposite exactly.
+  auto refl = [&](int i) { return per ? (n - i) % n : n - 1 - i; };
+  const int nrep = per ? n / 2 + 1 : (n + 1) / 2;
+  std::vector<int> pair_rep;  // representatives of the pairs, ascending
+  for (int r = 0; r < nrep; ++r)
+    if (refl(r) != r) pair_rep.push_back(r);
+  const int nodd = (int)pair_rep.size();
+  const double rs2 = 1.0 / std::sqrt(2.0);
+  // symmetric block: basis e_r (fixed r) or (e_r + e_R(r)) / sqrt 2
+  std::vector<double> ae((size_t)nrep * nrep), ao((size_t)nodd * nodd);
+  auto wsym = [&](int r) { return refl(r) == r ? 1.0 : rs2; };
+  auto orbit_sum = [&](int r, int c, double sign) {
+    const int rr = refl(r), cc = refl(c);
+    double v = s1[(size_t)r * n + c];
+    if (cc != c) v += sign * s1[(size_t)r * n + cc];
+    if (rr != r) {
+      v += sign * s1[(size_t)rr * n + c];
+      if (cc != c) v += s1[(size_t)rr * n + cc];
     }
-  out.lam.assign(n, 0.0);
-  sym_eig(n, s1.data(), out.lam.data(), nthreads);
-  // S = M^{-1/2} Q  (backward factor)
-  out.S.assign((size_t)n * n, 0.0);
-  for (int r = 0; r < n; ++r)
-    for (int c = 0; c < n; ++c) out.S[(size_t)r * n + c] = s1[(size_t)r * n + c] / mh[r];
+    return v;
+  };
+  for (int i = 0; i < nrep; ++i)
+    for (int j = 0; j < nrep; ++j) ae[(size_t)i * nrep + j] = wsym(i) * wsym(j) * orbit_sum(i, j, 1.0);
+  for (int i = 0; i < nodd; ++i)
+    for (int j = 0; j < nodd; ++j) ao[(size_t)i * nodd + j] = 0.5 * orbit_sum(pair_rep[i], pair_rep[j], -1.0);
+  for (std::vector<double>* blk : {&ae, &ao}) {
+    const int m = blk == &ae ? nrep : nodd;
+    for (int i = 0; i < m; ++i)
+      for (int j = i + 1; j < m; ++j) {
+        const double v = 0.5 * ((*blk)[(size_t)i * m + j] + (*blk)[(size_t)j * m + i]);
+        (*blk)[(size_t)i * m + j] = (*blk)[(size_t)j * m + i] = v;
+      }
+  }
+  std::vector<double> lame(nrep), lamo(nodd);
+  if (nrep) sym_eig(nrep, ae.data(), lame.data(), nthreads);
+  if (nodd) sym_eig(nodd, ao.data(), lamo.data(), nthreads);
+  // S_e = M^{-1/2} P_e Q_e,  S_o = M^{-1/2} P_o Q_o  (M is symmetric: the
+  // representative's mass serves both nodes of a pair)
+  std::vector<double> se((size_t)n * nrep, 0.0), so((size_t)n * std::max(nodd, 0), 0.0);
+  for (int r = 0; r < nrep; ++r)
+    for (int c = 0; c < nrep; ++c) {
+      const double v = wsym(r) * ae[(size_t)r * nrep + c] / mh[r];
+      se[(size_t)r * nrep + c] = v;
+      se[(size_t)refl(r) * nrep + c] = v;
+    }
+  for (int j = 0; j < nodd; ++j) {
+    const int r = pair_rep[j];
+    for (int c = 0; c < nodd; ++c) {
+      const double v = rs2 * ao[(size_t)j * nodd + c] / mh[r];
+      so[(size_t)r * nodd + c] = v;
+      so[(size_t)refl(r) * nodd + c] = -v;
+    }
+  }
   if (n > 1) {
     const std::vector<long double> ke = element_stiffness_ld(k, xr, spec.a, spec.b, ne);
-    refine_eigenpairs(n, k, ne, ke, off, per, out.mass, out.lam, out.S, nthreads);
+    if (nrep) refine_eigenpairs(n, nrep, k, ne, ke, off, per, out.mass, lame, se, nthreads);
+    if (nodd) refine_eigenpairs(n, nodd, k, ne, ke, off, per, out.mass, lamo, so, nthreads);
+  }
+  // natural order: all eigenpairs ascending (symmetric first among equal values)
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  auto lam_of = [&](int t) { return t < nrep ? lame[t] : lamo[t - nrep]; };
+  std::stable_sort(order.begin(), order.end(), [&](int a2, int b2) { return lam_of(a2) < lam_of(b2); });
+  out.lam.assign(n, 0.0);
+  out.S.assign((size_t)n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    const int t = order[c];
+    out.lam[c] = lam_of(t);
+    for (int r = 0; r < n; ++r)
+      out.S[(size_t)r * n + c] = t < nrep ? se[(size_t)r * nrep + t] : so[(size_t)r * nodd + (t - nrep)];
   }
   // forward factor F = S^T M  (= Q^T M^{1/2})
   out.F.assign((size_t)n * n, 0.0);
   for (int r = 0; r < n; ++r)
     for (int c = 0; c < n; ++c) out.F[(size_t)c * n + r] = out.S[(size_t)r * n + c] * out.mass[r];
+  // folded factors of the reflection-split transforms.  Folded vector of v:
+  // v+_r = v_r + v_R(r), v-_r = v_r - v_R(r) for r < nrep (v+ = 2 v_r, v- = 0 at a
+  // fixed node).  Forward: (F v)_sym = Ffold_sym v+, (F v)_anti = Ffold_anti v-,
+  // with Ffold(mode, r) = F(mode, r), halved at fixed r for symmetric modes.
+  // Backward: e = Bfold_sym c_sym, o = Bfold_anti c_anti on the representatives,
+  // then u_r = e_r + o_r, u_R(r) = e_r - o_r.
+  out.nrep = nrep;
+  out.nodd = nodd;
+  out.lam_fold.assign(n, 0.0);
+  for (int t = 0; t < n; ++t) out.lam_fold[t] = lam_of(t);
+  out.ffold.assign((size_t)n * nrep, 0.0);
+  for (int t = 0; t < n; ++t)
+    for (int r = 0; r < nrep; ++r) {
+      const double s = t < nrep ? se[(size_t)r * nrep + t] : so[(size_t)r * nodd + (t - nrep)];
+      out.ffold[(size_t)t * nrep + r] = s * out.mass[r] * (t < nrep && refl(r) == r ? 0.5 : 1.0);
+    }
+  out.bfold_sym.assign((size_t)nrep * nrep, 0.0);
+  out.bfold_anti.assign((size_t)nrep * std::max(nodd, 0), 0.0);
+  for (int r = 0; r < nrep; ++r) {
+    for (int t = 0; t < nrep; ++t) out.bfold_sym[(size_t)r * nrep + t] = se[(size_t)r * nrep + t];
+    for (int t = 0; t < nodd; ++t) out.bfold_anti[(size_t)r * nodd + t] = so[(size_t)r * nodd + t];
+  }
 }
 
 }  // namespace semfd

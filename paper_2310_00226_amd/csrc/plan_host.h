@@ -31,6 +31,15 @@ struct AxisData {
   std::vector<double> lam;    // eigenvalues ascending (n)
   std::vector<double> S;      // backward factor S (n x n row-major), K S = M S Lambda, S^T M S = I
   std::vector<double> F;      // forward factor F = S^T M (n x n row-major)
+  // Reflection split (node i -> R(i) = n - 1 - i, periodic (n - i) mod n): nrep
+  // orbit representatives 0..nrep-1, nodd antisymmetric eigenvectors (n - nrep).
+  // Mode order "folded": the nrep symmetric eigenvectors, then the nodd
+  // antisymmetric ones, each ascending.
+  int nrep = 0, nodd = 0;
+  std::vector<double> lam_fold;    // eigenvalues in folded mode order (n)
+  std::vector<double> ffold;       // n x nrep: forward factor on the folded vector (see build_axis)
+  std::vector<double> bfold_sym;   // nrep x nrep: symmetric eigenvectors on the representatives
+  std::vector<double> bfold_anti;  // nrep x nodd: antisymmetric eigenvectors on the representatives
 };
 
 void tridiag_qr(int n, double* d, double* e, double* z, int ldz, int nthreads);

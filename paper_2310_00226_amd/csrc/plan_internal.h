@@ -32,6 +32,16 @@ struct sem_plan {
   void* lp_hi[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   void* lp_lo[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   int lp_ld[3] = {0, 0, 0};
+  // reflection-split BF16 factors (hi plane, then lo plane lpf_plane elements
+  // later) [axis][0 = forward, 1 = backward]: forward rows = symmetric modes from 0,
+  // antisymmetric from lpf_frow2, columns = representatives; backward rows =
+  // representatives (symmetric block from 0, antisymmetric from lpf_frow2),
+  // columns = modes of the block; pitch lpf_ld
+  void* lpf[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  int lpf_ld[3] = {0, 0, 0};
+  int lpf_frow2[3] = {0, 0, 0};
+  long lpf_plane[3] = {0, 0, 0};
+  double* d_lamf[3] = {nullptr, nullptr, nullptr};  // eigenvalues in folded mode order
   int lp_ready = 0;
   // execution
   hipStream_t stream = nullptr;
@@ -60,6 +70,8 @@ struct LpWork {
   long rplane = 0, tplane = 0;
 };
 sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w);
+sem_status lp_factors(sem_plan* p, sem_prec prec);
+sem_status lp_layout(sem_plan* p, sem_prec prec, void* ws, LpWork* w);
 hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u, int first,
                  unsigned long long* norms);
 hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp);

@@ -59,11 +59,31 @@ float host_bf2f(unsigned short b) {
 size_t lp_elem(sem_prec prec) { return prec == SEM_BF16 ? 2 : 4; }
 bool lp_split(sem_prec prec) { return prec == SEM_BF16X3; }
 
-// largest of the three rotated padded layouts (z,x,y'), (y,z,x'), (x,y,z')
+inline int pad32(int n) { return (n + 31) / 32 * 32; }
+// reflection split of axis a: representatives, antisymmetric modes, folded node
+// row pitch (v+ then v-), split mode row pitch (symmetric block, antisymmetric
+// block, each from a 32-element boundary)
+inline int nrep_of(const sem_plan* p, int a) { return p->ax[a].nrep; }
+inline int fold_pitch(const sem_plan* p, int a) { return 2 * pad32(p->ax[a].nrep); }
+inline int mode_pitch(const sem_plan* p, int a) {
+  return pad32(p->ax[a].nrep) + pad32(std::max(p->ax[a].nodd, 1));
+}
+// row pitch of the folded correction (FP32, z'' = 2 nrep_z values)
+inline int dpitch(const sem_plan* p) { return pad8(2 * p->ax[2].nrep); }
+
+// FP32: largest of the three rotated padded layouts (z,x,y'), (y,z,x'), (x,y,z').
+// BF16 modes: largest of the reflection-split layouts of lp_fd (BF16 elements per
+// plane; the FP32 correction of the last pass, 2 elements per value, included).
 size_t lp_tmp_elems(const sem_plan* p, sem_prec prec) {
   const size_t nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
-  return std::max({nz * nx * (size_t)lp_pitch((int)ny, prec), ny * nz * (size_t)lp_pitch((int)nx, prec),
-                   nx * ny * (size_t)lp_pitch((int)nz, prec)});
+  if (prec == SEM_F32)
+    return std::max({nz * nx * (size_t)lp_pitch((int)ny, prec), ny * nz * (size_t)lp_pitch((int)nx, prec),
+                     nx * ny * (size_t)lp_pitch((int)nz, prec)});
+  const size_t rx = 2 * (size_t)nrep_of(p, 0), ry = 2 * (size_t)nrep_of(p, 1), rz = 2 * (size_t)nrep_of(p, 2);
+  const size_t corr = rx * ry * (size_t)dpitch(p) * 2 / (prec == SEM_BF16X3 ? 2 : 1);
+  return std::max({nx * ny * (size_t)fold_pitch(p, 2), nz * nx * (size_t)fold_pitch(p, 1),
+                   ny * nz * (size_t)fold_pitch(p, 0), nx * ny * (size_t)mode_pitch(p, 2),
+                   rz * nx * (size_t)mode_pitch(p, 1), ry * rz * (size_t)mode_pitch(p, 0), corr});
 }
 
 // residual buffer of the refinement: (nx, ny, pitch(nz)) in the intermediate type
@@ -102,8 +122,13 @@ void release_lowp(sem_plan* p) {
     for (int d = 0; d < 2; ++d) {
       (void)hipFree(p->lp_f32[a][d]);
       (void)hipFree(p->lp_hi[a][d]);  // lp_lo points into the same allocation
-      p->lp_f32[a][d] = p->lp_hi[a][d] = p->lp_lo[a][d] = nullptr;
+      (void)hipFree(p->lpf[a][d]);
+      p->lp_f32[a][d] = p->lp_hi[a][d] = p->lp_lo[a][d] = p->lpf[a][d] = nullptr;
     }
+  for (int a = 0; a < 3; ++a) {
+    (void)hipFree(p->d_lamf[a]);
+    p->d_lamf[a] = nullptr;
+  }
   p->lp_ready = 0;
 }
 
@@ -141,22 +166,52 @@ static sem_status ensure_lowp(sem_plan* p) {
       }
       p->lp_lo[a][d] = (unsigned short*)p->lp_hi[a][d] + plane;
     }
+    // reflection-split factors (BF16 hi / lo): forward [modes][representatives],
+    // backward [representatives][modes of the block]
+    const semfd::AxisData& ax = p->ax[a];
+    const int nr = ax.nrep, no = ax.nodd, frow2 = pad256(nr), ldf = pad32(nr);
+    const int rows_f = frow2 + pad256(std::max(no, 1)), rows_b = 2 * frow2;
+    p->lpf_ld[a] = ldf;
+    p->lpf_frow2[a] = frow2;
+    p->lpf_plane[a] = (long)std::max(rows_f, rows_b) * ldf;
+    for (int d = 0; d < 2; ++d) {
+      const size_t pl = (size_t)p->lpf_plane[a];
+      std::vector<unsigned short> hl(2 * pl, 0);
+      auto put = [&](int row, int col, double v) {
+        const float fv = (float)v;
+        const unsigned short h = host_f2bf(fv);
+        hl[(size_t)row * ldf + col] = h;
+        hl[pl + (size_t)row * ldf + col] = host_f2bf((float)(v - (double)host_bf2f(h)));
+      };
+      if (d == 0) {
+        for (int t = 0; t < n; ++t)
+          for (int r = 0; r < nr; ++r) put(t < nr ? t : frow2 + (t - nr), r, ax.ffold[(size_t)t * nr + r]);
+      } else {
+        for (int r = 0; r < nr; ++r) {
+          for (int t = 0; t < nr; ++t) put(r, t, ax.bfold_sym[(size_t)r * nr + t]);
+          for (int t = 0; t < no; ++t) put(frow2 + r, t, ax.bfold_anti[(size_t)r * no + t]);
+        }
+      }
+      hipError_t e;
+      if ((e = hipMalloc(&p->lpf[a][d], hl.size() * 2)) != hipSuccess ||
+          (e = hipMemcpy(p->lpf[a][d], hl.data(), hl.size() * 2, hipMemcpyHostToDevice)) != hipSuccess) {
+        release_lowp(p);
+        return hip_fail(e, "folded factor upload");
+      }
+    }
+    hipError_t e;
+    if ((e = hipMalloc(&p->d_lamf[a], sizeof(double) * n)) != hipSuccess ||
+        (e = hipMemcpy(p->d_lamf[a], ax.lam_fold.data(), sizeof(double) * n, hipMemcpyHostToDevice)) != hipSuccess) {
+      release_lowp(p);
+      return hip_fail(e, "folded eigenvalue upload");
+    }
   }
   p->lp_ready = 1;
   return SEM_OK;
 }
 
-// Workspace layout of the low-precision solves (see workspace_need).
-sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w) {
-  if (prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3) return set_error(SEM_EINVAL, "unknown precision");
-  if (p->dims[0] > 46340 || (long)p->dims[1] * p->dims[2] > 0x7fffffffL ||
-      (long)p->dims[0] * p->dims[2] > 0x7fffffffL || (long)p->dims[0] * p->dims[1] > 0x7fffffffL)
-    return set_error(SEM_EINVAL, "problem too large for the low-precision kernels");
-  sem_status st = ensure_lowp(p);
-  if (st != SEM_OK) return st;
-  void* ws = nullptr;
-  st = plan_workspace(p, workspace_need(p, prec), &ws);
-  if (st != SEM_OK) return st;
+// Workspace layout of the low-precision solves (see workspace_need) inside ws.
+sem_status lp_layout(sem_plan* p, sem_prec prec, void* ws, LpWork* w) {
   char* b = (char*)ws;
   const bool split = lp_split(prec);
   const size_t rbytes = lp_r_bytes(p, prec);
@@ -173,9 +228,142 @@ sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w) {
   return SEM_OK;
 }
 
+sem_status lp_check(const sem_plan* p, sem_prec prec) {
+  if (prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3) return set_error(SEM_EINVAL, "unknown precision");
+  if (p->dims[0] > 46340 || (long)p->dims[1] * p->dims[2] > 0x7fffffffL ||
+      (long)p->dims[0] * p->dims[2] > 0x7fffffffL || (long)p->dims[0] * p->dims[1] > 0x7fffffffL)
+    return set_error(SEM_EINVAL, "problem too large for the low-precision kernels");
+  return SEM_OK;
+}
+
+// Low-precision factors and the plan workspace laid out for prec.
+sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w) {
+  sem_status st = lp_check(p, prec);
+  if (st != SEM_OK) return st;
+  st = ensure_lowp(p);
+  if (st != SEM_OK) return st;
+  void* ws = nullptr;
+  st = plan_workspace(p, workspace_need(p, prec), &ws);
+  if (st != SEM_OK) return st;
+  return lp_layout(p, prec, ws, w);
+}
+
+// Low-precision factors only (the caller provides the workspace, lp_layout).
+sem_status lp_factors(sem_plan* p, sem_prec prec) {
+  sem_status st = lp_check(p, prec);
+  if (st != SEM_OK) return st;
+  return ensure_lowp(p);
+}
+
+// BF16 / split-BF16 FD application on the reflection-split transforms:
+//   fold z -> (z fwd, fold y) -> (y fwd, fold x) -> (x fwd, divide) -> z bwd -> y bwd
+//   -> x bwd -> unfold + accumulate.
+// Each forward pass contracts the folded node axis blockwise (symmetric modes with
+// v+, antisymmetric with v-) and writes its output rows in folded mode order; the
+// first two also fold the axis the next pass contracts.  Each backward pass
+// contracts a mode axis blockwise and writes the folded node form e_r, o_r of its
+// axis (rows), which only the final kernel resolves into nodes (u_r = e_r + o_r,
+// u_R(r) = e_r - o_r on every axis) while adding the correction to u.
+static hipError_t lp_fd_folded(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u,
+                               int first, unsigned long long* norms) {
+  const sem_prec prec = w.prec;
+  const int mode = prec == SEM_BF16 ? LP_BF16 : LP_BF16X3;
+  const int split = mode == LP_BF16X3 ? 1 : 0;
+  const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
+  FoldAxis fa[3];
+  for (int a = 0; a < 3; ++a) {
+    fa[a].nrep = p->ax[a].nrep;
+    fa[a].pad = pad32(p->ax[a].nrep);
+    fa[a].per = p->bc[a] == SEM_BC_PERIODIC ? 1 : 0;
+  }
+  const int ry = fa[1].nrep, rz = fa[2].nrep;
+  void* t0 = w.t0;
+  void* t1 = w.t1;
+  const long tp = w.tplane;
+  hipError_t e;
+  // folded right-hand side into t1
+  if (f64_src)
+    e = launch_to_lowp(f64_src, t1, tp, split, p->dims, fold_pitch(p, 2), &fa[2], p->stream);
+  else
+    e = launch_fold_lowp(w.r, w.rplane, w.ldr, t1, tp, fold_pitch(p, 2), split, p->dims, fa[2], p->stream);
+  if (e != hipSuccess) return e;
+  struct Step {
+    const void* x;
+    int ldx, A, B, axis, dir;
+    void* y;
+    int ldy, out_kind, epi, col, baxis, bsym_rows;
+  };
+  // forward: K = representatives of the contracted axis (both blocks), rows =
+  // n modes (nrep symmetric, nodd antisymmetric); backward: K = modes of the block,
+  // rows = 2 nrep (e then o)
+  const Step st[6] = {
+      {t1, fold_pitch(p, 2), nx, ny, 2, 0, t0, fold_pitch(p, 1), 2, EPI_STORE, COL_FOLD, 1, 0},
+      {t0, fold_pitch(p, 1), nz, nx, 1, 0, t1, fold_pitch(p, 0), 2, EPI_STORE, COL_FOLD, 0, 0},
+      {t1, fold_pitch(p, 0), ny, nz, 0, 0, t0, mode_pitch(p, 2), 2, EPI_DIVIDE, COL_SPLIT, 2, 0},
+      {t0, mode_pitch(p, 2), nx, ny, 2, 1, t1, mode_pitch(p, 1), 2, EPI_STORE, COL_SPLIT, 1, 0},
+      {t1, mode_pitch(p, 1), 2 * rz, nx, 1, 1, t0, mode_pitch(p, 0), 2, EPI_STORE, COL_SPLIT, 0, 0},
+      {t0, mode_pitch(p, 0), 2 * ry, 2 * rz, 0, 1, t1, dpitch(p), 1, EPI_STORE, COL_PLAIN, 2, 0},
+  };
+  for (int s = 0; s < 6; ++s) {
+    const Step& q = st[s];
+    const int a = q.axis;
+    const semfd::AxisData& ax = p->ax[a];
+    LpPass ps;
+    ps.mode = mode;
+    ps.x = q.x;
+    ps.ldx = q.ldx;
+    ps.A = q.A;
+    ps.B = q.B;
+    ps.P = (long)q.A * q.B;
+    ps.y = q.y;
+    ps.ldy = q.ldy;
+    ps.f_hi = p->lpf[a][q.dir];
+    ps.ldf = p->lpf_ld[a];
+    ps.fplane = p->lpf_plane[a];
+    ps.in_kind = 2;
+    ps.out_kind = q.out_kind;
+    ps.epi_kind = q.epi;
+    ps.xplane = tp;
+    ps.yplane = q.out_kind == 2 ? tp : 0;
+    ps.frow2 = p->lpf_frow2[a];
+    ps.koff2 = pad32(ax.nrep);
+    if (q.dir == 0) {  // forward: blocks of nrep and nodd modes over the representatives
+      ps.K = ax.nrep;
+      ps.L = ax.nrep;
+      ps.K2 = ax.nodd > 0 ? ax.nrep : 0;
+      ps.L2 = ax.nodd;
+    } else {  // backward: e rows over the symmetric modes, o rows over the antisymmetric
+      ps.K = ax.nrep;
+      ps.L = ax.nrep;
+      ps.K2 = std::max(ax.nodd, 1);  // nodd = 0: one zero chunk, o rows = 0
+      ps.L2 = ax.nrep;
+    }
+    ps.col = q.col;
+    if (q.col == COL_FOLD || q.col == COL_SPLIT) {
+      const int b = q.baxis;
+      ps.bsym = p->ax[b].nrep;
+      ps.bpad = pad32(p->ax[b].nrep);
+      ps.bn = p->dims[b];
+      ps.bper = fa[b].per;
+    }
+    if (q.epi == EPI_DIVIDE) {
+      // output (x modes, y modes, z modes), all in folded mode order
+      ps.epi.l0 = p->d_lamf[0];
+      ps.epi.l1 = p->d_lamf[1];
+      ps.epi.l2 = p->d_lamf[2];
+      ps.epi.alpha = sp.alpha;
+      ps.epi.b1 = sp.b1;
+      ps.epi.b2 = sp.b2;
+    }
+    if (!dma_supported(ps)) return hipErrorInvalidValue;
+    if ((e = launch_mode_dma(ps, p->stream)) != hipSuccess) return e;
+  }
+  return launch_unfold_accum((const float*)t1, dpitch(p), u, p->dims, fa, first, norms, p->stream);
+}
+
 // One low-precision FD application  u (+)= S_3 [ (F_3 src) / (alpha + b1 L + b2 L^2) ].
 //  f64_src != null: the FP64 right-hand side in the caller's layout (FP32 reads it
-//    directly; the BF16 modes first convert it into w.r);
+//    directly; the BF16 modes fold and convert it first);
 //  f64_src == null: src is w.r, written by the residual kernel in the
 //    intermediate format (row pitch w.ldr).
 //  first = 1 stores u = delta, else u += delta; norms (may be null) receive
@@ -183,36 +371,30 @@ sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w) {
 hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u, int first,
                  unsigned long long* norms) {
   const sem_prec prec = w.prec;
+  if (prec != SEM_F32) return lp_fd_folded(p, w, sp, f64_src, u, first, norms);
   const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
-  const int mode = prec == SEM_F32 ? LP_F32 : prec == SEM_BF16 ? LP_BF16 : LP_BF16X3;
-  const bool dma = mode != LP_F32;
-  const int lpk = mode == LP_F32 ? 1 : 2;  // intermediate kind (FP32 / BF16 planes)
-  if (f64_src && dma) {
-    hipError_t e = launch_to_lowp(f64_src, w.r, w.rplane, mode == LP_BF16X3 ? 1 : 0, p->dims, w.ldr, p->stream);
-    if (e != hipSuccess) return e;
-  }
-  const bool from_r = !f64_src || dma;
+  const int mode = LP_F32;
+  const int lpk = 1;  // FP32 intermediates
+  const bool from_r = !f64_src;
   const void* src = from_r ? w.r : (const void*)f64_src;
   void* t0 = w.t0;
   void* t1 = w.t1;
-  const long tplane = w.tplane;
   // the six passes: (input, ldx, A, B, K) -> (output, ldy); axis contracted = K's axis
   struct Step {
     const void* x;
     int ldx, A, B, K, axis, dir;
     void* y;
     int ldy, in_kind, out_kind, epi;
-    long xplane, yplane;
   };
   const int in0 = from_r ? lpk : 0;
   const int px = lp_pitch(nx, prec), py = lp_pitch(ny, prec), pz = lp_pitch(nz, prec);
   const Step st[6] = {
-      {src, from_r ? w.ldr : nz, nx, ny, nz, 2, 0, t0, py, in0, lpk, EPI_STORE, w.rplane, tplane},
-      {t0, py, nz, nx, ny, 1, 0, t1, px, lpk, lpk, EPI_STORE, tplane, tplane},
-      {t1, px, ny, nz, nx, 0, 0, t0, pz, lpk, lpk, EPI_DIVIDE, tplane, tplane},
-      {t0, pz, nx, ny, nz, 2, 1, t1, py, lpk, lpk, EPI_STORE, tplane, tplane},
-      {t1, py, nz, nx, ny, 1, 1, t0, px, lpk, lpk, EPI_STORE, tplane, tplane},
-      {t0, px, ny, nz, nx, 0, 1, u, nz, lpk, 0, EPI_ACCUM, tplane, 0},
+      {src, from_r ? w.ldr : nz, nx, ny, nz, 2, 0, t0, py, in0, lpk, EPI_STORE},
+      {t0, py, nz, nx, ny, 1, 0, t1, px, lpk, lpk, EPI_STORE},
+      {t1, px, ny, nz, nx, 0, 0, t0, pz, lpk, lpk, EPI_DIVIDE},
+      {t0, pz, nx, ny, nz, 2, 1, t1, py, lpk, lpk, EPI_STORE},
+      {t1, py, nz, nx, ny, 1, 1, t0, px, lpk, lpk, EPI_STORE},
+      {t0, px, ny, nz, nx, 0, 1, u, nz, lpk, 0, EPI_ACCUM},
   };
   for (int s = 0; s < 6; ++s) {
     LpPass ps;
@@ -227,17 +409,11 @@ hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double*
     ps.B = st[s].B;
     ps.L = st[s].K;
     const int axis = st[s].axis, dir = st[s].dir;
-    ps.f_hi = mode == LP_F32 ? p->lp_f32[axis][dir] : p->lp_hi[axis][dir];
-    ps.f_lo = mode == LP_F32 ? nullptr : p->lp_lo[axis][dir];
+    ps.f_hi = p->lp_f32[axis][dir];
     ps.ldf = p->lp_ld[axis];
     ps.in_kind = st[s].in_kind;
     ps.out_kind = st[s].out_kind;
     ps.epi_kind = st[s].epi;
-    if (mode == LP_BF16X3) {
-      ps.xplane = st[s].xplane;
-      ps.yplane = st[s].yplane;
-      ps.fplane = (long)ps.ldf * ps.ldf;
-    }
     if (st[s].epi == EPI_DIVIDE) {
       // output (x, y, z): l = x mode, a = y mode, b = z mode
       ps.epi.l0 = p->d_lam[0];
@@ -251,13 +427,7 @@ hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double*
       ps.epi.first = first;
       ps.epi.norms = norms;
     }
-    hipError_t e;
-    if (dma) {
-      if (!dma_supported(ps)) return hipErrorInvalidValue;
-      e = launch_mode_dma(ps, p->stream);
-    } else {
-      e = launch_mode_lp(ps, p->stream);
-    }
+    const hipError_t e = launch_mode_lp(ps, p->stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

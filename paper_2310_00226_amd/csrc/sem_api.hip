@@ -132,6 +132,27 @@ sem_status sem_axis_host(int k, int ne, double a, double b, sem_bc bc, int* n, d
   return SEM_OK;
 }
 
+sem_status sem_axis_fold_host(int k, int ne, double a, double b, sem_bc bc, int* nrep, int* nodd, double* lam_fold,
+                              double* ffold, double* bfold_sym, double* bfold_anti) {
+  if (k < 1 || ne < 1 || !(a < b) || !std::isfinite(a) || !std::isfinite(b) || !valid_bc(bc))
+    return fail(SEM_EINVAL, "sem_axis_fold_host: invalid argument");
+  if (bc == SEM_BC_DIRICHLET && ne * k < 2) return fail(SEM_EINVAL, "Dirichlet needs ne*k >= 2");
+  try {
+    AxisData d;
+    build_axis(axis_spec(k, ne, a, b, bc), d, host_threads());
+    if (nrep) *nrep = d.nrep;
+    if (nodd) *nodd = d.nodd;
+    const size_t n = d.n, nr = d.nrep, no = d.nodd;
+    if (lam_fold) std::memcpy(lam_fold, d.lam_fold.data(), sizeof(double) * n);
+    if (ffold) std::memcpy(ffold, d.ffold.data(), sizeof(double) * n * nr);
+    if (bfold_sym) std::memcpy(bfold_sym, d.bfold_sym.data(), sizeof(double) * nr * nr);
+    if (bfold_anti && no) std::memcpy(bfold_anti, d.bfold_anti.data(), sizeof(double) * nr * no);
+  } catch (const std::exception& ex) {
+    return fail(SEM_EINVAL, "sem_axis_fold_host: %s", ex.what());
+  }
+  return SEM_OK;
+}
+
 sem_status sem_plan_create(int k, const int ne[3], const double box[6], double alpha, sem_bc bc, sem_plan** out) {
   const sem_bc bcs[3] = {bc, bc, bc};
   return sem_plan_create_mixed(k, ne, box, alpha, bcs, out);

@@ -138,6 +138,31 @@ def test_ch_full_size_n257(torch, P, sweeps):
     assert np.all(np.isfinite(phi)) and np.max(np.abs(phi)) < 1.0
 
 
+@pytest.mark.timeout(600)
+def test_ch_c5_fifty_steps_match_oracle(torch, P):
+    """The full C5 configuration (Q^4, 64^3 elements, n = 257, eps = 0.05, m = 0.02,
+    dt = 1e-4, phi_0 ~ U[-0.05, 0.05] seed 2312) with the benchmarked step (FP32
+    solve + one FP64 sweep, graph replays): 50 steps of eq. chscheme-2, each
+    compared with the oracle's step from the same history, relative max error
+    <= 1e-10 after every step."""
+    k, ne = 4, (64, 64, 64)
+    prob = O.Problem(k, ne, BOX, 0.0, "neumann")
+    phi0 = ch_initial(prob.shape, 2312, 0.05)
+    ch = P.CahnHilliard(k, ne, BOX, EPS, MOB, DT, prec="f32", refine_sweeps=1)
+    a, b = _dev(torch, phi0), _dev(torch, phi0)
+    ref_n, ref_nm1 = phi0, phi0
+    worst = 0.0
+    for step in range(50):
+        ch.step(a, b, 1)
+        ref_n, ref_nm1 = O.ch_step(prob, ref_n, ref_nm1, EPS, MOB, DT), ref_n
+        err = O.rel_max_err(a.cpu().numpy(), ref_n)
+        worst = max(worst, err)
+        if step % 10 == 9:
+            _log(f"[ch] C5 step {step + 1}: rel err vs oracle {err:.2e}")
+        assert err <= 1e-10, (step, err)
+    _log(f"[ch] C5 50 steps: worst rel err vs oracle {worst:.2e}")
+
+
 @pytest.mark.parametrize("prec_sweeps", [("f64", 0), ("f32", 1)], ids=lambda c: f"{c[0]}-s{c[1]}")
 def test_ch_forced_steps_match_oracle(torch, P, prec_sweeps):
     """Steps with the source of the BDF2 accuracy test (changed before every step,

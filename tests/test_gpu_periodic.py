@@ -141,24 +141,38 @@ def test_periodic_pcg_matches_oracle(torch, P, beta):
         assert st == 0 and abs(it - it_ref) <= 1 and err <= 1e-10
 
 
+@pytest.mark.timeout(900)
 def test_periodic_pcg_table_tab7c_mesh(torch, P):
-    """Table tab7c's first mesh, 250^3 DoFs (Q^5, 50 elements per axis, periodic):
-    beta = 1 takes the paper's 10 iterations (+-1) and the error against the exact
-    solution is the discretisation error (~1.3e-13 in the oracle at this mesh).
-    For beta = 10, 100 this reading of the iteration (M-inner product, stop at
-    ||r||_M <= 1e-12 ||f||_M) takes 21 and 52 iterations against the paper's 35
-    and 85; the error left at the stop then grows with the condition number
-    (2.3e-12 at beta = 100)."""
+    """Table tab7c's first mesh, 250^3 DoFs (Q^5, 50 elements per axis, periodic).
+    beta = 1 takes the paper's 10 iterations (+-1).  For beta = 10 and 100 no
+    reading of the paper's stop reproduces its 35 and 85 (parity unpinned: this
+    PCG takes 19-24 and 48-64 iterations for every stop from 1e-12 to round-off,
+    the paper's finest meshes print 25 and 72), so there the GPU iteration is
+    held to the oracle's PCG on the same mesh: the same iteration count (+-1,
+    FP64 preconditioner) and the same solution (1e-10); the split-BF16
+    preconditioner within +-2 iterations or 10% (52 against 48 at beta = 100).  Errors against the exact solution are
+    the discretisation error at beta = 1 (~1.3e-13) and grow with the condition
+    number at the 1e-12 stop (2.3e-12 at beta = 100)."""
     plan = P.Plan(5, (50, 50, 50), SCHRODINGER_BOX, 1.0, "periodic")
     assert plan.shape == (250, 250, 250)
+    prob = O.Problem(5, (50, 50, 50), SCHRODINGER_BOX, 1.0, "periodic")
     xs = [plan.nodes(a) for a in range(3)]
-    for beta, lo, hi, ebound in ((1.0, 9, 11, 1e-12), (10.0, 15, 40, 1e-11), (100.0, 35, 100, 1e-11)):
+    for beta, ebound in ((1.0, 1e-12), (10.0, 1e-11), (100.0, 1e-11)):
         v, ue, f = schrodinger_data(*xs, 1.0, beta)
-        u, it, rel, st = plan.pcg_solve(_dev(torch, v), _dev(torch, f), shift=1.0 + beta / 2, prec="bf16x3",
-                                        tol=1e-12, max_iter=300)
-        err = float((u - _dev(torch, ue)).abs().max())
-        _log(f"[periodic] 250^3 beta={beta:g}: {it} iterations (paper: 10 / 35 / 85), max error {err:.2e}")
-        assert st == 0 and lo <= it <= hi and err <= ebound, (beta, it, err)
+        shift = 1.0 + beta / 2
+        ref, it_ref, _ = O.pcg_schrodinger(prob, v, f, shift, tol=1e-12, max_iter=300)
+        vd, fd = _dev(torch, v), _dev(torch, f)
+        u, it, rel, st = plan.pcg_solve(vd, fd, shift=shift, prec="f64", tol=1e-12, max_iter=300)
+        err_ref = O.rel_max_err(u.cpu().numpy(), ref)
+        u2, it2, _, st2 = plan.pcg_solve(vd, fd, shift=shift, prec="bf16x3", tol=1e-12, max_iter=300)
+        err = float((u2 - _dev(torch, ue)).abs().max())
+        _log(f"[periodic] 250^3 beta={beta:g}: {it} iterations FP64 preconditioner, {it2} split BF16, oracle "
+             f"{it_ref} (paper: 10 / 35 / 85); rel err vs oracle {err_ref:.2e}, max error vs exact {err:.2e}")
+        assert st == 0 and st2 == 0 and abs(it - it_ref) <= 1, (beta, it, it_ref)
+        assert abs(it2 - it_ref) <= max(2, it_ref // 10), (beta, it2, it_ref)
+        assert err_ref <= 1e-10 and err <= ebound, (beta, err_ref, err)
+        if beta == 1.0:
+            assert 9 <= it <= 11 and 9 <= it2 <= 11  # Table tab7c: 10 on every mesh
 
 
 def test_periodic_q20_table_tab8(torch, P):
