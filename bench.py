@@ -425,7 +425,10 @@ def main() -> int:
             err = float((ur - u).abs().max()) / scale
             variants[f"{prec}_refined"] = {"ms_per_solve": vms, "unknowns_per_s": N / (vms * 1e-3),
                                            "iterations": it, "last_update_rel": rel, "status": st,
-                                           "rel_err_vs_f64": err}
+                                           "rel_err_vs_f64": err,
+                                           # launch shapes the first solve tuned, per pass in order:
+                                           # FP32 tile rows / BF16 tile-order group
+                                           "tuned_shapes": plan.tuning(prec)}
             log(f"{prec} refined: {vms:.2f} ms/solve, {N / (vms * 1e-3):.3e} unknowns/s, {it} iterations, "
                 f"rel err vs FP64 {err:.2e}, status {st}")
     ok = {k: v for k, v in variants.items() if v["rel_err_vs_f64"] <= 1e-10 and v.get("status", 0) == 0}
@@ -468,7 +471,7 @@ def main() -> int:
                 "traffic": _traffic(prec), "traffic_detail": PROFILED_TRAFFIC.get(prec),
                 "launch_ms": fd_ms, "flops_per_launch": flops,
                 "dense_equivalent_tflops": fd_flops / (fd_ms * 1e-3) / 1e12,
-                "mfma_work_factor": 3 if prec == "bf16x3" else 1}
+                "mfma_work_factor": 4 if prec == "bf16x3" else 1}
         v["fd_application"] = roof
         log(f"{prec} FD application alone: {fd_ms:.2f} ms, {ach:.1f} TFLOP/s algorithmic "
             f"({ach / peak:.3f} of {peak} TFLOP/s)")

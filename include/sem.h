@@ -56,7 +56,7 @@ typedef enum {
   SEM_F64 = 0,   /* FP64 MFMA, FP64 intermediates */
   SEM_F32 = 1,   /* FP32 MFMA, FP32 intermediates */
   SEM_BF16 = 2,  /* BF16 MFMA with FP32 accumulation, BF16 intermediates */
-  SEM_BF16X3 = 3 /* split BF16 (hi + lo) operands, three BF16 MFMAs, FP32 accumulation */
+  SEM_BF16X3 = 3 /* split BF16 (hi + lo) operands, four BF16 MFMAs, FP32 accumulation */
 } sem_prec;
 
 typedef enum {
@@ -187,6 +187,35 @@ sem_status sem_solve_refined(sem_plan *p, sem_prec prec, double tol, int max_ite
  * the first refinement iteration); u must not alias f.  Asynchronous. */
 sem_status sem_solve_lowp(sem_plan *p, sem_prec prec, const double *f, double *u);
 
+/* ---- launch-shape tuning ------------------------------------------------------
+ * The low-precision mode products of a plan (sem_solve_refined, sem_solve_lowp,
+ * the PCG preconditioner, the Cahn-Hilliard stepper, split-BF16 batch entries) run
+ * with launch shapes chosen by timing on the first use of each precision: for
+ * SEM_F32 the factor-tile rows (128, 96, 64 or 32) of each of the six passes; for
+ * SEM_BF16 / SEM_BF16X3 the tile-order group (1, 2 or 4 column strips of 256 that
+ * consecutive workgroups share, which sets how many workgroups reuse one factor
+ * tile from L2).  The shapes change no result bit.  Each candidate is launched
+ * once untimed, then three times, on the plan's own workspace; the fastest is kept
+ * in the plan and in a process-wide cache keyed by device architecture, kernel,
+ * output layout and log2 size buckets of the pass, which later plans of similar
+ * size read instead of timing.  With the environment variable SEM_TUNE_CACHE
+ * naming a file, the cache is read from it on first use and rewritten after each
+ * new entry (JSON: {"version": 1, "entries": {"<key>": <choice>, ...}}; an
+ * unreadable file counts as empty).  Nothing is timed while the plan stream is
+ * capturing a graph: the shapes then follow the fixed rule until a later call
+ * outside capture tunes them. */
+/* Tune prec now, consulting the cache (synchronous; uses the plan workspace).
+ * SEM_EINVAL: prec is SEM_F64 (no tunable shape) or the plan stream is capturing. */
+sem_status sem_plan_tune(sem_plan *p, sem_prec prec);
+/* The shapes of prec's six passes in order of application (choice[s] = 0 and
+ * *tuned = 0 before prec is tuned).  SEM_EINVAL: null pointers, SEM_F64. */
+sem_status sem_plan_tuning(const sem_plan *p, sem_prec prec, int *tuned, int choice[6]);
+/* Install shapes for prec without timing: 128, 96, 64 or 32 per pass for SEM_F32,
+ * 1, 2 or 4 for the BF16 modes.  SEM_EINVAL for anything else. */
+sem_status sem_plan_set_tuning(sem_plan *p, sem_prec prec, const int choice[6]);
+/* Process-wide cache counters: lookups answered, lookups missed, entries held. */
+sem_status sem_tune_stats(int *hits, int *misses, int *entries);
+
 /* ---- other spectral multipliers --------------------------------------------- */
 
 typedef enum { SEM_SPECTRAL_EXP = 1, SEM_SPECTRAL_POWER = 2 } sem_spectral;
@@ -251,7 +280,9 @@ typedef struct sem_batch sem_batch;
  * the batch), the first uses the plan's.  The plans are not owned and must
  * outlive the batch.  Creation prepares the FP32 factors and workspaces of every
  * entry, then times the candidate tile shapes of the FP32 mode-product kernel on
- * the batch's own passes and keeps the fastest per contraction-length bucket.
+ * the batch's own passes and keeps the fastest per contraction-length bucket
+ * (through the tuning cache of sem_plan_tune: a bucket of the same length and
+ * log2 work found there is not timed again).
  * Synchronous.  SEM_EINVAL: count < 1, a null plan, k > 8, plans on different
  * devices. */
 sem_status sem_batch_create(int count, sem_plan *const *plans, sem_batch **out);
@@ -306,6 +337,9 @@ sem_status sem_ch_dims(const sem_ch *c, int n[3]);
  * work on it (NULL = the null stream).  The steps themselves run on the stepper's
  * own stream. */
 sem_status sem_ch_set_stream(sem_ch *c, void *hip_stream);
+/* Launch shapes of the stepper's mode products, tuned at creation (see
+ * sem_plan_tune; *tuned = 0 for SEM_F64). */
+sem_status sem_ch_tuning(const sem_ch *c, int *tuned, int choice[6]);
 /* enable = 1 (default): each step is a replay of a captured HIP graph (captured on
  * the first call, and again whenever phi_n / phi_nm1 change address); 0: the same
  * kernels launched one by one. */

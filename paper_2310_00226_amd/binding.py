@@ -50,6 +50,10 @@ def _load():
         "sem_solve_refined": (c_int, [c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, POINTER(c_int),
                                       POINTER(c_double)]),
         "sem_solve_lowp": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+        "sem_plan_tune": (c_int, [c_void_p, c_int]),
+        "sem_plan_tuning": (c_int, [c_void_p, c_int, POINTER(c_int), POINTER(c_int)]),
+        "sem_plan_set_tuning": (c_int, [c_void_p, c_int, POINTER(c_int)]),
+        "sem_tune_stats": (c_int, [POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
         "sem_apply_spectral": (c_int, [c_void_p, c_int, c_double, c_double, c_void_p, c_void_p]),
         "sem_pcg_workspace_bytes": (c_int, [c_void_p, POINTER(c_size_t)]),
         "sem_pcg_solve": (c_int, [c_void_p, c_void_p, c_double, c_int, c_double, c_int, c_void_p, c_void_p,
@@ -68,6 +72,7 @@ def _load():
         "sem_ch_destroy": (None, [c_void_p]),
         "sem_ch_dims": (c_int, [c_void_p, POINTER(c_int)]),
         "sem_ch_set_stream": (c_int, [c_void_p, c_void_p]),
+        "sem_ch_tuning": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int)]),
         "sem_ch_set_forcing": (c_int, [c_void_p, c_void_p]),
         "sem_ch_set_graphs": (c_int, [c_void_p, c_int]),
         "sem_ch_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
@@ -106,6 +111,13 @@ def _dev_ptr(t, name, n=None, dtype=None):
     if n is not None and t.numel() != n:
         raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
     return c_void_p(t.data_ptr())
+
+
+def tune_stats():
+    """Process-wide tuning-cache counters (sem_tune_stats): dict of hits, misses, entries."""
+    h, m, e = c_int(0), c_int(0), c_int(0)
+    check(lib.sem_tune_stats(ctypes.byref(h), ctypes.byref(m), ctypes.byref(e)))
+    return {"hits": h.value, "misses": m.value, "entries": e.value}
 
 
 def axis_fold_host(k: int, ne: int, a: float, b: float, bc: str):
@@ -246,6 +258,27 @@ class Plan:
         check(lib.sem_solve_lowp(self._p, pv, fp, up))
         return u
 
+    def tune(self, prec: str = "bf16x3"):
+        """Tune the launch shapes of prec now (sem_plan_tune); returns tuning(prec)."""
+        pv = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        self._prepare(pv)
+        check(lib.sem_plan_tune(self._p, pv))
+        return self.tuning(pv)
+
+    def tuning(self, prec: str = "bf16x3"):
+        """The shapes of prec's six passes (sem_plan_tuning), or None before tuning."""
+        pv = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        tuned = c_int(0)
+        ch = (c_int * 6)()
+        check(lib.sem_plan_tuning(self._p, pv, ctypes.byref(tuned), ch))
+        return list(ch) if tuned.value else None
+
+    def set_tuning(self, prec: str, choice):
+        """Install the six pass shapes of prec without timing (sem_plan_set_tuning)."""
+        pv = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        ch = (c_int * 6)(*[int(c) for c in choice])
+        check(lib.sem_plan_set_tuning(self._p, pv, ch))
+
     def apply_spectral(self, kind: str, a: float, param: float, f, u=None):
         """u = g(H_3 + a I) f with g(x) = exp(-param x) ("exp") or x^(-param) ("power")
         (sem_apply_spectral)."""
@@ -362,6 +395,13 @@ class CahnHilliard:
 
     def set_graphs(self, enable: bool):
         check(lib.sem_ch_set_graphs(self._c, 1 if enable else 0))
+
+    def tuning(self):
+        """Launch shapes of the stepper's six mode products (sem_ch_tuning), or None."""
+        tuned = c_int(0)
+        ch = (c_int * 6)()
+        check(lib.sem_ch_tuning(self._c, ctypes.byref(tuned), ch))
+        return list(ch) if tuned.value else None
 
     def set_forcing(self, s=None):
         """Source term read by every following step at the new time level (or None)."""

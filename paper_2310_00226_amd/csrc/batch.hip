@@ -29,12 +29,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
 
 #include "kernels.h"
 #include "plan_internal.h"
+#include "tune.h"
 
 namespace semfd {
 namespace {
@@ -86,6 +88,7 @@ struct sem_batch {
   std::vector<size_t> own_bytes;
   hipStream_t stream = nullptr;
   int cus = 1;
+  char arch[64] = "unknown";  // device architecture name, part of the tuning-cache keys
   int tile_rows[NBUCKET] = {0, 0, 0, 0, 0, 0};
   LpDesc* d_desc = nullptr;
   ResDesc* d_rdesc = nullptr;
@@ -256,14 +259,25 @@ sem_status autotune(sem_batch* b) {
   sem_status st = SEM_OK;
   for (int bk = 0; bk < NBUCKET && st == SEM_OK; ++bk) {
     std::vector<LpDesc> base;
+    long work = 0;
     for (int i = 0; i < b->count; ++i)
       for (int s : {1, 2, 3}) {  // variants 2, 3, 4 = passes along y, x, z
         LpDesc d = make_desc(b, i, s + 1, nullptr, nullptr);
         if (bucket_of(d.L) != bk) continue;
         d.epi = EpiLP();
         base.push_back(d);
+        work += d.P * (long)d.L;
       }
     if (base.empty()) continue;
+    // the tuning cache holds the choice per device, length bucket and log2 of the
+    // bucket's work (rows x length summed over its passes)
+    char key[128];
+    std::snprintf(key, sizeof(key), "%s|batch_f32|Lb%d|W%d", b->arch, bk, tune_bucket(work));
+    int cached = 0;
+    if (tune_lookup(key, &cached)) {
+      b->tile_rows[bk] = cached;
+      continue;
+    }
     float best = INFINITY;
     int best_tr = 128;
     for (int tr : TILE_CANDIDATES) {
@@ -304,6 +318,7 @@ sem_status autotune(sem_batch* b) {
       }
     }
     b->tile_rows[bk] = best_tr;
+    tune_store(key, best_tr);
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
@@ -312,9 +327,11 @@ sem_status autotune(sem_batch* b) {
 
 // Low-precision factors of entry i's plan and the entry's workspace laid out for
 // prec: the plan's own workspace, or for a repeated plan the entry's own one.
+// Split-BF16 entries run the plan's own passes, whose launch shapes are tuned per
+// plan; the FP32 entries run the batch's grouped launches (tuned by autotune).
 sem_status prepare_entry(sem_batch* b, int i, sem_prec prec) {
   sem_plan* p = b->plans[i];
-  if (!b->repeat[i]) return lp_prepare(p, prec, &b->lw[i]);
+  if (!b->repeat[i]) return lp_prepare(p, prec, &b->lw[i], prec != SEM_F32);
   sem_status st = lp_factors(p, prec);
   if (st != SEM_OK) return st;
   const size_t need = workspace_need(p, prec);
@@ -423,6 +440,16 @@ sem_status sem_batch_create(int count, sem_plan* const* plans, sem_batch** out) 
     return hip_fail(e, "sem_batch_create: device query");
   }
   b->cus = cus > 0 ? cus : 1;
+  {
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) {
+      sem_batch_destroy(b);
+      return hip_fail(e, "sem_batch_create: device query");
+    }
+    std::snprintf(b->arch, sizeof(b->arch), "%s", prop.gcnArchName);
+    for (char* c = b->arch; *c; ++c)
+      if (*c == ':') *c = '_';
+  }
   if ((e = hipMalloc(&b->d_desc, sizeof(LpDesc) * (size_t)std::max(NVAR * count, 3 * count))) != hipSuccess ||
       (e = hipMalloc(&b->d_rdesc, sizeof(ResDesc) * (size_t)count)) != hipSuccess ||
       (e = hipMalloc(&b->d_active, sizeof(int) * (size_t)count)) != hipSuccess ||

@@ -260,6 +260,16 @@ sem_status sem_ch_dims(const sem_ch* c, int n[3]) {
   return sem_plan_dims(c->plan, n);
 }
 
+sem_status sem_ch_tuning(const sem_ch* c, int* tuned, int choice[6]) {
+  if (!c || !tuned || !choice) return set_error(SEM_EINVAL, "sem_ch_tuning: null argument");
+  if (c->prec == SEM_F64) {  // FP64 mode products have no tunable shape
+    *tuned = 0;
+    for (int s = 0; s < 6; ++s) choice[s] = 0;
+    return SEM_OK;
+  }
+  return sem_plan_tuning(c->plan, c->prec, tuned, choice);
+}
+
 sem_status sem_ch_set_stream(sem_ch* c, void* s) {
   if (!c) return set_error(SEM_EINVAL, "sem_ch_set_stream: null handle");
   c->user_stream = (hipStream_t)s;

@@ -43,6 +43,10 @@ struct sem_plan {
   long lpf_plane[3] = {0, 0, 0};
   double* d_lamf[3] = {nullptr, nullptr, nullptr};  // eigenvalues in folded mode order
   int lp_ready = 0;
+  // tuned launch shapes per precision (index sem_prec) and pass: FP32 tile rows,
+  // BF16 tile order group (lp_tune)
+  int tuned[4] = {0, 0, 0, 0};
+  int tune_choice[4][6] = {};
   // execution
   hipStream_t stream = nullptr;
   void* ws = nullptr;
@@ -69,7 +73,8 @@ struct LpWork {
   int rkind = 1, ldr = 0;   // ResidualArgs.r_kind and row pitch of r
   long rplane = 0, tplane = 0;
 };
-sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w);
+sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w, bool tune = true);
+sem_status lp_tune(sem_plan* p, const LpWork& w);
 sem_status lp_factors(sem_plan* p, sem_prec prec);
 sem_status lp_layout(sem_plan* p, sem_prec prec, void* ws, LpWork* w);
 hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u, int first,

@@ -22,11 +22,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <string>
 #include <cstring>
 #include <vector>
 
 #include "kernels.h"
 #include "plan_internal.h"
+#include "tune.h"
 
 namespace semfd {
 
@@ -236,8 +239,9 @@ sem_status lp_check(const sem_plan* p, sem_prec prec) {
   return SEM_OK;
 }
 
-// Low-precision factors and the plan workspace laid out for prec.
-sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w) {
+// Low-precision factors and the plan workspace laid out for prec; with tune, the
+// launch shapes of prec are tuned (once per plan, see lp_tune).
+sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w, bool tune) {
   sem_status st = lp_check(p, prec);
   if (st != SEM_OK) return st;
   st = ensure_lowp(p);
@@ -245,7 +249,9 @@ sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w) {
   void* ws = nullptr;
   st = plan_workspace(p, workspace_need(p, prec), &ws);
   if (st != SEM_OK) return st;
-  return lp_layout(p, prec, ws, w);
+  st = lp_layout(p, prec, ws, w);
+  if (st != SEM_OK || !tune) return st;
+  return lp_tune(p, *w);
 }
 
 // Low-precision factors only (the caller provides the workspace, lp_layout).
@@ -264,101 +270,170 @@ sem_status lp_factors(sem_plan* p, sem_prec prec) {
 // contracts a mode axis blockwise and writes the folded node form e_r, o_r of its
 // axis (rows), which only the final kernel resolves into nodes (u_r = e_r + o_r,
 // u_R(r) = e_r - o_r on every axis) while adding the correction to u.
-static hipError_t lp_fd_folded(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u,
-                               int first, unsigned long long* norms) {
-  const sem_prec prec = w.prec;
-  const int mode = prec == SEM_BF16 ? LP_BF16 : LP_BF16X3;
-  const int split = mode == LP_BF16X3 ? 1 : 0;
-  const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
-  FoldAxis fa[3];
+static void fold_axes(const sem_plan* p, FoldAxis fa[3]) {
   for (int a = 0; a < 3; ++a) {
     fa[a].nrep = p->ax[a].nrep;
     fa[a].pad = pad32(p->ax[a].nrep);
     fa[a].per = p->bc[a] == SEM_BC_PERIODIC ? 1 : 0;
   }
-  const int ry = fa[1].nrep, rz = fa[2].nrep;
-  void* t0 = w.t0;
-  void* t1 = w.t1;
-  const long tp = w.tplane;
-  hipError_t e;
-  // folded right-hand side into t1
-  if (f64_src)
-    e = launch_to_lowp(f64_src, t1, tp, split, p->dims, fold_pitch(p, 2), &fa[2], p->stream);
-  else
-    e = launch_fold_lowp(w.r, w.rplane, w.ldr, t1, tp, fold_pitch(p, 2), split, p->dims, fa[2], p->stream);
-  if (e != hipSuccess) return e;
+}
+
+// Pass s (0..5) of the reflection-split sequence: t1 -> t0 -> t1 -> t0 -> t1 -> t0 -> t1.
+static LpPass folded_pass(sem_plan* p, const LpWork& w, const Spectral& sp, int s) {
+  const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
+  const int ry = p->ax[1].nrep, rz = p->ax[2].nrep;
   struct Step {
-    const void* x;
-    int ldx, A, B, axis, dir;
-    void* y;
-    int ldy, out_kind, epi, col, baxis, bsym_rows;
+    int ldx, A, B, axis, dir, ldy, out_kind, epi, col, baxis;
   };
   // forward: K = representatives of the contracted axis (both blocks), rows =
   // n modes (nrep symmetric, nodd antisymmetric); backward: K = modes of the block,
   // rows = 2 nrep (e then o)
   const Step st[6] = {
-      {t1, fold_pitch(p, 2), nx, ny, 2, 0, t0, fold_pitch(p, 1), 2, EPI_STORE, COL_FOLD, 1, 0},
-      {t0, fold_pitch(p, 1), nz, nx, 1, 0, t1, fold_pitch(p, 0), 2, EPI_STORE, COL_FOLD, 0, 0},
-      {t1, fold_pitch(p, 0), ny, nz, 0, 0, t0, mode_pitch(p, 2), 2, EPI_DIVIDE, COL_SPLIT, 2, 0},
-      {t0, mode_pitch(p, 2), nx, ny, 2, 1, t1, mode_pitch(p, 1), 2, EPI_STORE, COL_SPLIT, 1, 0},
-      {t1, mode_pitch(p, 1), 2 * rz, nx, 1, 1, t0, mode_pitch(p, 0), 2, EPI_STORE, COL_SPLIT, 0, 0},
-      {t0, mode_pitch(p, 0), 2 * ry, 2 * rz, 0, 1, t1, dpitch(p), 1, EPI_STORE, COL_PLAIN, 2, 0},
+      {fold_pitch(p, 2), nx, ny, 2, 0, fold_pitch(p, 1), 2, EPI_STORE, COL_FOLD, 1},
+      {fold_pitch(p, 1), nz, nx, 1, 0, fold_pitch(p, 0), 2, EPI_STORE, COL_FOLD, 0},
+      {fold_pitch(p, 0), ny, nz, 0, 0, mode_pitch(p, 2), 2, EPI_DIVIDE, COL_SPLIT, 2},
+      {mode_pitch(p, 2), nx, ny, 2, 1, mode_pitch(p, 1), 2, EPI_STORE, COL_SPLIT, 1},
+      {mode_pitch(p, 1), 2 * rz, nx, 1, 1, mode_pitch(p, 0), 2, EPI_STORE, COL_SPLIT, 0},
+      {mode_pitch(p, 0), 2 * ry, 2 * rz, 0, 1, dpitch(p), 1, EPI_STORE, COL_PLAIN, 2},
   };
+  const Step& q = st[s];
+  const int a = q.axis;
+  const semfd::AxisData& ax = p->ax[a];
+  LpPass ps;
+  ps.mode = w.prec == SEM_BF16 ? LP_BF16 : LP_BF16X3;
+  ps.x = (s % 2 == 0) ? w.t1 : w.t0;
+  ps.y = (s % 2 == 0) ? w.t0 : w.t1;
+  ps.ldx = q.ldx;
+  ps.A = q.A;
+  ps.B = q.B;
+  ps.P = (long)q.A * q.B;
+  ps.ldy = q.ldy;
+  ps.f_hi = p->lpf[a][q.dir];
+  ps.ldf = p->lpf_ld[a];
+  ps.fplane = p->lpf_plane[a];
+  ps.in_kind = 2;
+  ps.out_kind = q.out_kind;
+  ps.epi_kind = q.epi;
+  ps.xplane = w.tplane;
+  ps.yplane = q.out_kind == 2 ? w.tplane : 0;
+  ps.frow2 = p->lpf_frow2[a];
+  ps.koff2 = pad32(ax.nrep);
+  if (q.dir == 0) {  // forward: blocks of nrep and nodd modes over the representatives
+    ps.K = ax.nrep;
+    ps.L = ax.nrep;
+    ps.K2 = ax.nodd > 0 ? ax.nrep : 0;
+    ps.L2 = ax.nodd;
+  } else {  // backward: e rows over the symmetric modes, o rows over the antisymmetric
+    ps.K = ax.nrep;
+    ps.L = ax.nrep;
+    ps.K2 = std::max(ax.nodd, 1);  // nodd = 0: one zero chunk, o rows = 0
+    ps.L2 = ax.nrep;
+  }
+  ps.col = q.col;
+  if (q.col == COL_FOLD || q.col == COL_SPLIT) {
+    const int bx = q.baxis;
+    ps.bsym = p->ax[bx].nrep;
+    ps.bpad = pad32(p->ax[bx].nrep);
+    ps.bn = p->dims[bx];
+    ps.bper = p->bc[bx] == SEM_BC_PERIODIC ? 1 : 0;
+  }
+  if (q.epi == EPI_DIVIDE) {
+    // output (x modes, y modes, z modes), all in folded mode order
+    ps.epi.l0 = p->d_lamf[0];
+    ps.epi.l1 = p->d_lamf[1];
+    ps.epi.l2 = p->d_lamf[2];
+    ps.epi.alpha = sp.alpha;
+    ps.epi.b1 = sp.b1;
+    ps.epi.b2 = sp.b2;
+  }
+  if (p->tuned[w.prec]) ps.tile_group = p->tune_choice[w.prec][s];
+  return ps;
+}
+
+static hipError_t lp_fd_folded(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u,
+                               int first, unsigned long long* norms) {
+  const int split = w.prec == SEM_BF16X3 ? 1 : 0;
+  FoldAxis fa[3];
+  fold_axes(p, fa);
+  hipError_t e;
+  // folded right-hand side into t1
+  if (f64_src)
+    e = launch_to_lowp(f64_src, w.t1, w.tplane, split, p->dims, fold_pitch(p, 2), &fa[2], p->stream);
+  else
+    e = launch_fold_lowp(w.r, w.rplane, w.ldr, w.t1, w.tplane, fold_pitch(p, 2), split, p->dims, fa[2], p->stream);
+  if (e != hipSuccess) return e;
   for (int s = 0; s < 6; ++s) {
-    const Step& q = st[s];
-    const int a = q.axis;
-    const semfd::AxisData& ax = p->ax[a];
-    LpPass ps;
-    ps.mode = mode;
-    ps.x = q.x;
-    ps.ldx = q.ldx;
-    ps.A = q.A;
-    ps.B = q.B;
-    ps.P = (long)q.A * q.B;
-    ps.y = q.y;
-    ps.ldy = q.ldy;
-    ps.f_hi = p->lpf[a][q.dir];
-    ps.ldf = p->lpf_ld[a];
-    ps.fplane = p->lpf_plane[a];
-    ps.in_kind = 2;
-    ps.out_kind = q.out_kind;
-    ps.epi_kind = q.epi;
-    ps.xplane = tp;
-    ps.yplane = q.out_kind == 2 ? tp : 0;
-    ps.frow2 = p->lpf_frow2[a];
-    ps.koff2 = pad32(ax.nrep);
-    if (q.dir == 0) {  // forward: blocks of nrep and nodd modes over the representatives
-      ps.K = ax.nrep;
-      ps.L = ax.nrep;
-      ps.K2 = ax.nodd > 0 ? ax.nrep : 0;
-      ps.L2 = ax.nodd;
-    } else {  // backward: e rows over the symmetric modes, o rows over the antisymmetric
-      ps.K = ax.nrep;
-      ps.L = ax.nrep;
-      ps.K2 = std::max(ax.nodd, 1);  // nodd = 0: one zero chunk, o rows = 0
-      ps.L2 = ax.nrep;
-    }
-    ps.col = q.col;
-    if (q.col == COL_FOLD || q.col == COL_SPLIT) {
-      const int b = q.baxis;
-      ps.bsym = p->ax[b].nrep;
-      ps.bpad = pad32(p->ax[b].nrep);
-      ps.bn = p->dims[b];
-      ps.bper = fa[b].per;
-    }
-    if (q.epi == EPI_DIVIDE) {
-      // output (x modes, y modes, z modes), all in folded mode order
-      ps.epi.l0 = p->d_lamf[0];
-      ps.epi.l1 = p->d_lamf[1];
-      ps.epi.l2 = p->d_lamf[2];
-      ps.epi.alpha = sp.alpha;
-      ps.epi.b1 = sp.b1;
-      ps.epi.b2 = sp.b2;
-    }
+    const LpPass ps = folded_pass(p, w, sp, s);
     if (!dma_supported(ps)) return hipErrorInvalidValue;
     if ((e = launch_mode_dma(ps, p->stream)) != hipSuccess) return e;
   }
-  return launch_unfold_accum((const float*)t1, dpitch(p), u, p->dims, fa, first, norms, p->stream);
+  return launch_unfold_accum((const float*)w.t1, dpitch(p), u, p->dims, fa, first, norms, p->stream);
+}
+
+// Pass s (0..5) of the FP32 sequence  src -> t0 -> t1 -> t0 -> t1 -> t0 -> u.
+// With u == nullptr the last pass stores FP32 into t1 instead of accumulating
+// into u (the stand-in the tuner times).
+static LpPass f32_pass(sem_plan* p, const LpWork& w, const Spectral& sp, int s, const double* f64_src, double* u,
+                       int first, unsigned long long* norms) {
+  const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
+  const sem_prec prec = SEM_F32;
+  const bool from_r = !f64_src;
+  const void* src = from_r ? w.r : (const void*)f64_src;
+  const int px = lp_pitch(nx, prec), py = lp_pitch(ny, prec), pz = lp_pitch(nz, prec);
+  struct Step {
+    const void* x;
+    int ldx, A, B, K, axis, dir;
+    void* y;
+    int ldy, in_kind, out_kind, epi;
+  };
+  const int in0 = from_r ? 1 : 0;
+  const Step st[6] = {
+      {src, from_r ? w.ldr : nz, nx, ny, nz, 2, 0, w.t0, py, in0, 1, EPI_STORE},
+      {w.t0, py, nz, nx, ny, 1, 0, w.t1, px, 1, 1, EPI_STORE},
+      {w.t1, px, ny, nz, nx, 0, 0, w.t0, pz, 1, 1, EPI_DIVIDE},
+      {w.t0, pz, nx, ny, nz, 2, 1, w.t1, py, 1, 1, EPI_STORE},
+      {w.t1, py, nz, nx, ny, 1, 1, w.t0, px, 1, 1, EPI_STORE},
+      {w.t0, px, ny, nz, nx, 0, 1, u, nz, 1, 0, EPI_ACCUM},
+  };
+  const Step& q = st[s];
+  LpPass ps;
+  ps.mode = LP_F32;
+  ps.x = q.x;
+  ps.ldx = q.ldx;
+  ps.P = (long)q.A * q.B;
+  ps.K = q.K;
+  ps.y = q.y;
+  ps.ldy = q.ldy;
+  ps.A = q.A;
+  ps.B = q.B;
+  ps.L = q.K;
+  ps.f_hi = p->lp_f32[q.axis][q.dir];
+  ps.ldf = p->lp_ld[q.axis];
+  ps.in_kind = q.in_kind;
+  ps.out_kind = q.out_kind;
+  ps.epi_kind = q.epi;
+  if (q.epi == EPI_DIVIDE) {
+    // output (x, y, z): l = x mode, a = y mode, b = z mode
+    ps.epi.l0 = p->d_lam[0];
+    ps.epi.l1 = p->d_lam[1];
+    ps.epi.l2 = p->d_lam[2];
+    ps.epi.alpha = sp.alpha;
+    ps.epi.b1 = sp.b1;
+    ps.epi.b2 = sp.b2;
+  }
+  if (q.epi == EPI_ACCUM) {
+    if (u) {
+      ps.epi.first = first;
+      ps.epi.norms = norms;
+    } else {  // tuner stand-in: FP32 store of the same shape into t1 (pass 3's layout)
+      ps.y = w.t1;
+      ps.ldy = pz;
+      ps.out_kind = 1;
+      ps.epi_kind = EPI_STORE;
+    }
+  }
+  if (p->tuned[SEM_F32]) ps.tile_rows = p->tune_choice[SEM_F32][s];
+  return ps;
 }
 
 // One low-precision FD application  u (+)= S_3 [ (F_3 src) / (alpha + b1 L + b2 L^2) ].
@@ -370,67 +445,104 @@ static hipError_t lp_fd_folded(sem_plan* p, const LpWork& w, const Spectral& sp,
 //  max|delta| and max|u| as FP64 bit patterns (the caller zeroes them).
 hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u, int first,
                  unsigned long long* norms) {
-  const sem_prec prec = w.prec;
-  if (prec != SEM_F32) return lp_fd_folded(p, w, sp, f64_src, u, first, norms);
-  const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
-  const int mode = LP_F32;
-  const int lpk = 1;  // FP32 intermediates
-  const bool from_r = !f64_src;
-  const void* src = from_r ? w.r : (const void*)f64_src;
-  void* t0 = w.t0;
-  void* t1 = w.t1;
-  // the six passes: (input, ldx, A, B, K) -> (output, ldy); axis contracted = K's axis
-  struct Step {
-    const void* x;
-    int ldx, A, B, K, axis, dir;
-    void* y;
-    int ldy, in_kind, out_kind, epi;
-  };
-  const int in0 = from_r ? lpk : 0;
-  const int px = lp_pitch(nx, prec), py = lp_pitch(ny, prec), pz = lp_pitch(nz, prec);
-  const Step st[6] = {
-      {src, from_r ? w.ldr : nz, nx, ny, nz, 2, 0, t0, py, in0, lpk, EPI_STORE},
-      {t0, py, nz, nx, ny, 1, 0, t1, px, lpk, lpk, EPI_STORE},
-      {t1, px, ny, nz, nx, 0, 0, t0, pz, lpk, lpk, EPI_DIVIDE},
-      {t0, pz, nx, ny, nz, 2, 1, t1, py, lpk, lpk, EPI_STORE},
-      {t1, py, nz, nx, ny, 1, 1, t0, px, lpk, lpk, EPI_STORE},
-      {t0, px, ny, nz, nx, 0, 1, u, nz, lpk, 0, EPI_ACCUM},
-  };
+  if (w.prec != SEM_F32) return lp_fd_folded(p, w, sp, f64_src, u, first, norms);
   for (int s = 0; s < 6; ++s) {
-    LpPass ps;
-    ps.mode = mode;
-    ps.x = st[s].x;
-    ps.ldx = st[s].ldx;
-    ps.P = (long)st[s].A * st[s].B;
-    ps.K = st[s].K;
-    ps.y = st[s].y;
-    ps.ldy = st[s].ldy;
-    ps.A = st[s].A;
-    ps.B = st[s].B;
-    ps.L = st[s].K;
-    const int axis = st[s].axis, dir = st[s].dir;
-    ps.f_hi = p->lp_f32[axis][dir];
-    ps.ldf = p->lp_ld[axis];
-    ps.in_kind = st[s].in_kind;
-    ps.out_kind = st[s].out_kind;
-    ps.epi_kind = st[s].epi;
-    if (st[s].epi == EPI_DIVIDE) {
-      // output (x, y, z): l = x mode, a = y mode, b = z mode
-      ps.epi.l0 = p->d_lam[0];
-      ps.epi.l1 = p->d_lam[1];
-      ps.epi.l2 = p->d_lam[2];
-      ps.epi.alpha = sp.alpha;
-      ps.epi.b1 = sp.b1;
-      ps.epi.b2 = sp.b2;
-    }
-    if (st[s].epi == EPI_ACCUM) {
-      ps.epi.first = first;
-      ps.epi.norms = norms;
-    }
-    const hipError_t e = launch_mode_lp(ps, p->stream);
+    const hipError_t e = launch_mode_lp(f32_pass(p, w, sp, s, f64_src, u, first, norms), p->stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// ---- autotuning of the launch shapes -------------------------------------------
+// FP32 passes: factor-tile rows 128, 96, 64 or 32; BF16 passes: tile order group
+// 1, 2 or 4 p-strips.  Each pass geometry is timed once (one warm-up launch, the
+// fastest of three), on the plan's own workspace, and the choice is kept in the
+// plan and in the tuning cache (key: architecture, kernel, output layout, and
+// log2 buckets of rows, contraction length and tensor rows), so plans of similar
+// size skip the timing, also in later processes with SEM_TUNE_CACHE.
+static const char* arch_name(const sem_plan* p) {
+  static thread_local char name[64];
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return "unknown";
+  std::snprintf(name, sizeof(name), "%s", prop.gcnArchName);
+  for (char* c = name; *c; ++c)
+    if (*c == ':') *c = '_';
+  return name;
+}
+
+static std::string pass_key(const sem_plan* p, const LpPass& ps) {
+  char buf[192];
+  std::snprintf(buf, sizeof(buf), "%s|%s|epi%d|col%d|out%d|L%d|K%d|P%d", arch_name(p),
+                ps.mode == LP_F32 ? "f32" : ps.mode == LP_BF16 ? "bf16" : "bf16x3", ps.epi_kind, ps.col,
+                ps.out_kind, tune_bucket(ps.L + ps.L2), tune_bucket(ps.K), tune_bucket(ps.P));
+  return buf;
+}
+
+static hipError_t time_pass(sem_plan* p, const LpPass& ps, float* best_ms) {
+  hipEvent_t t0, t1;
+  hipError_t e;
+  if ((e = hipEventCreate(&t0)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&t1)) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return e;
+  }
+  auto launch = [&]() { return ps.mode == LP_F32 ? launch_mode_lp(ps, p->stream) : launch_mode_dma(ps, p->stream); };
+  float best = INFINITY;
+  e = launch();  // warm-up
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+    float ms = 0.f;
+    if ((e = hipEventRecord(t0, p->stream)) == hipSuccess && (e = launch()) == hipSuccess &&
+        (e = hipEventRecord(t1, p->stream)) == hipSuccess && (e = hipEventSynchronize(t1)) == hipSuccess &&
+        (e = hipEventElapsedTime(&ms, t0, t1)) == hipSuccess)
+      best = std::min(best, ms);
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  *best_ms = best;
+  return e;
+}
+
+sem_status lp_tune(sem_plan* p, const LpWork& w) {
+  const sem_prec prec = w.prec;
+  if (p->tuned[prec]) return SEM_OK;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(p->stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return SEM_OK;  // no timing under capture: the rule-based shapes stay
+  const Spectral sp{p->alpha, 1.0, 0.0};
+  static const int rows_cand[4] = {128, 96, 64, 32};
+  static const int group_cand[3] = {1, 2, 4};
+  for (int s = 0; s < 6; ++s) {
+    LpPass ps = prec == SEM_F32 ? f32_pass(p, w, sp, s, nullptr, nullptr, 1, nullptr) : folded_pass(p, w, sp, s);
+    if (prec == SEM_F32) ps.in_kind = 1;  // first pass: time the FP32-input variant
+    if (prec == SEM_F32 && s == 0) {
+      ps.x = w.r;
+      ps.ldx = w.ldr;
+    }
+    const std::string key = pass_key(p, ps);
+    int choice = 0;
+    if (!tune_lookup(key, &choice)) {
+      const int* cand = prec == SEM_F32 ? rows_cand : group_cand;
+      const int nc = prec == SEM_F32 ? 4 : 3;
+      float best = INFINITY;
+      for (int c = 0; c < nc; ++c) {
+        if (prec == SEM_F32)
+          ps.tile_rows = cand[c];
+        else
+          ps.tile_group = cand[c];
+        float ms = INFINITY;
+        const hipError_t e = time_pass(p, ps, &ms);
+        if (e != hipSuccess) return hip_fail(e, "autotune");
+        if (ms < best) {
+          best = ms;
+          choice = cand[c];
+        }
+      }
+      tune_store(key, choice);
+    }
+    p->tune_choice[prec][s] = choice;
+  }
+  p->tuned[prec] = 1;
+  return SEM_OK;
 }
 
 // FP64 FD application u = S_3 [ (F_3 f) / (alpha + b1 L + b2 L^2) ]; tmp holds N
@@ -541,5 +653,53 @@ extern "C" sem_status sem_solve_lowp(sem_plan* p, sem_prec prec, const double* f
   if (st != SEM_OK) return st;
   const hipError_t e = lp_fd(p, w, Spectral{p->alpha, 1.0, 0.0}, f, u, 1, nullptr);
   if (e != hipSuccess) return hip_fail(e, "sem_solve_lowp");
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_plan_tune(sem_plan* p, sem_prec prec) {
+  if (!p) return set_error(SEM_EINVAL, "sem_plan_tune: null plan");
+  if (prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3)
+    return set_error(SEM_EINVAL, "sem_plan_tune: only SEM_F32, SEM_BF16 and SEM_BF16X3 have tunable shapes");
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(p->stream, &cap);
+  if (e != hipSuccess) return hip_fail(e, "sem_plan_tune: stream");
+  if (cap != hipStreamCaptureStatusNone) return set_error(SEM_EINVAL, "sem_plan_tune: the plan stream is capturing");
+  p->tuned[prec] = 0;
+  LpWork w;
+  sem_status st = lp_prepare(p, prec, &w, true);
+  if (st != SEM_OK) return st;
+  if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "sem_plan_tune");
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_plan_tuning(const sem_plan* p, sem_prec prec, int* tuned, int choice[6]) {
+  if (!p || !tuned || !choice) return set_error(SEM_EINVAL, "sem_plan_tuning: null argument");
+  if (prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3)
+    return set_error(SEM_EINVAL, "sem_plan_tuning: only SEM_F32, SEM_BF16 and SEM_BF16X3 have tunable shapes");
+  *tuned = p->tuned[prec];
+  for (int s = 0; s < 6; ++s) choice[s] = p->tuned[prec] ? p->tune_choice[prec][s] : 0;
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_plan_set_tuning(sem_plan* p, sem_prec prec, const int choice[6]) {
+  if (!p || !choice) return set_error(SEM_EINVAL, "sem_plan_set_tuning: null argument");
+  if (prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3)
+    return set_error(SEM_EINVAL, "sem_plan_set_tuning: only SEM_F32, SEM_BF16 and SEM_BF16X3 have tunable shapes");
+  for (int s = 0; s < 6; ++s) {
+    const int c = choice[s];
+    const bool ok = prec == SEM_F32 ? (c == 128 || c == 96 || c == 64 || c == 32) : (c == 1 || c == 2 || c == 4);
+    if (!ok)
+      return set_error(SEM_EINVAL, prec == SEM_F32 ? "sem_plan_set_tuning: FP32 tile rows must be 128, 96, 64 or 32"
+                                                   : "sem_plan_set_tuning: BF16 tile groups must be 1, 2 or 4");
+  }
+  for (int s = 0; s < 6; ++s) p->tune_choice[prec][s] = choice[s];
+  p->tuned[prec] = 1;
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_tune_stats(int* hits, int* misses, int* entries) {
+  if (!hits || !misses || !entries) return set_error(SEM_EINVAL, "sem_tune_stats: null argument");
+  tune_counts(hits, misses);
+  *entries = tune_size();
   return SEM_OK;
 }

@@ -106,6 +106,12 @@ void tune_counts(int* hits, int* misses) {
   *misses = g_misses;
 }
 
+int tune_size() {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  if (!g_loaded) load_locked();
+  return (int)g_entries.size();
+}
+
 int tune_bucket(long v) {
   int b = 0;
   while (v > 1) {

@@ -10,6 +10,8 @@ bool tune_lookup(const std::string& key, int* value);
 void tune_store(const std::string& key, int value);
 // Lookups answered from the cache / not found, since the process started.
 void tune_counts(int* hits, int* misses);
+// Entries held (after reading the file on first use).
+int tune_size();
 // floor(log2(v)) for v >= 1 (0 for v <= 1): the size buckets of the keys.
 int tune_bucket(long v);
 }  // namespace semfd
