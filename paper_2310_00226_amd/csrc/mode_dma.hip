@@ -146,7 +146,10 @@ template <int MODE, class TOut, int EPI, int COL>
 __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(DmaArgs g) {
   typedef KCfg<MODE> C;
   constexpr int NS = C::NS, S = C::STAGES;
-  __shared__ __attribute__((aligned(1024))) unsigned char smem[C::SMEM];
+  // DIVIDE keeps the tile's 256 column and 256 row parts of the denominators
+  // behind the staging area
+  constexpr int SMEM_ALL = C::SMEM + (EPI == EPI_DIVIDE ? 2 * 256 * 4 : 0);
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[SMEM_ALL];
   unsigned char* const st0 = smem;
   unsigned char* const st1 = smem + C::STAGEB;
   unsigned char* const st2 = smem + (S > 2 ? 2 : 0) * C::STAGEB;
@@ -255,40 +258,46 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(DmaArgs g) {
     boff[j] = row * ROWB + ((fg ^ swz(row)) << 4);
   }
   auto compute = [&](const unsigned char* stage) {
-    bf8_t a[FL], b[FP];
-#pragma unroll
-    for (int i = 0; i < FL; ++i) a[i] = *reinterpret_cast<const bf8_t*>(stage + aoff[i]);
-#pragma unroll
-    for (int j = 0; j < FP; ++j) b[j] = *reinterpret_cast<const bf8_t*>(stage + TILEB + boff[j]);
     if constexpr (NS == 2) {
-      bf8_t alo[FL], blo[FP];
+      // split BF16: the tensor fragments (hi, lo) of all 4 column blocks stay in
+      // registers; the factor fragments are read one 16-row block at a time, and the
+      // block's 4 x 4 MFMAs (products lo*hi, hi*lo, lo*lo, hi*hi, each over the 4
+      // column blocks, so that consecutive MFMAs write different accumulators)
+      // cover the reads of the next block.  Holding all 24 fragments at once needs
+      // more than the 256 registers a wave has at two waves per SIMD.  The tensor
+      // fragment is the first operand, so that acc[i][j] holds D[p][l]: a lane
+      // keeps 4 consecutive output columns p of one row l (see the epilogue).
+      bf8_t bh[FP], bl[FP];
 #pragma unroll
-      for (int i = 0; i < FL; ++i) alo[i] = *reinterpret_cast<const bf8_t*>(stage + 2 * TILEB + aoff[i]);
+      for (int j = 0; j < FP; ++j) {
+        bh[j] = *reinterpret_cast<const bf8_t*>(stage + TILEB + boff[j]);
+        bl[j] = *reinterpret_cast<const bf8_t*>(stage + 3 * TILEB + boff[j]);
+      }
 #pragma unroll
-      for (int j = 0; j < FP; ++j) blo[j] = *reinterpret_cast<const bf8_t*>(stage + 3 * TILEB + boff[j]);
-      __builtin_amdgcn_sched_barrier(0);  // all fragment reads in flight before the first MFMA
-      // products outermost: consecutive MFMAs write different accumulators.  The
-      // tensor fragment is the first operand, so that acc[i][j] holds D[p][l]: a
-      // lane keeps 4 consecutive output columns p of one row l (see the epilogue)
+      for (int i = 0; i < FL; ++i) {
+        const bf8_t ah = *reinterpret_cast<const bf8_t*>(stage + aoff[i]);
+        const bf8_t al = *reinterpret_cast<const bf8_t*>(stage + 2 * TILEB + aoff[i]);
 #pragma unroll
-      for (int i = 0; i < FL; ++i)
+        for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], al, acc[i][j], 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], alo[i], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], ah, acc[i][j], 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < FL; ++i)
+        for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[j], al, acc[i][j], 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(blo[j], a[i], acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < FL; ++i)
-#pragma unroll
-        for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(blo[j], alo[i], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[j], ah, acc[i][j], 0, 0, 0);
+      }
     } else {
+      bf8_t a[FL], b[FP];
+#pragma unroll
+      for (int i = 0; i < FL; ++i) a[i] = *reinterpret_cast<const bf8_t*>(stage + aoff[i]);
+#pragma unroll
+      for (int j = 0; j < FP; ++j) b[j] = *reinterpret_cast<const bf8_t*>(stage + TILEB + boff[j]);
       __builtin_amdgcn_sched_barrier(0);  // all fragment reads in flight before the first MFMA
+#pragma unroll
+      for (int i = 0; i < FL; ++i)
+#pragma unroll
+        for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
     }
-#pragma unroll
-    for (int i = 0; i < FL; ++i)
-#pragma unroll
-      for (int j = 0; j < FP; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
   };
 
   // ---- pipeline -----------------------------------------------------------------
@@ -361,36 +370,39 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(DmaArgs g) {
   } else {
     if constexpr (EPI == EPI_DIVIDE) {
       // denominators alpha + b1 L + b2 L^2, L = lam_l + lam_a + lam_b, in FP32 (the
-      // quotient is rounded to split BF16 anyway): the a and b parts per column,
-      // found from one division for the tile's first column
-      float dab[FP][4];
-      const long a0 = p0 / g.ldy;
-      const long b0 = p0 - a0 * g.ldy;
-#pragma unroll
-      for (int j = 0; j < FP; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const long c = pl0 + 16 * j + r;
-          long a = a0, bo = b0 + c;
-          while (bo >= g.ldy) {  // the tile spans 256 columns: a few rows of ldy >= 32 at most
-            bo -= g.ldy;
-            ++a;
-          }
-          const bool in = p0 + c < Pp;
-          dab[j][r] = in ? (float)(g.epi.l1[a] + g.epi.l2[in_col(bo, g)]) : 0.0f;
+      // quotient is rounded to split BF16 anyway): one thread per tile column forms
+      // lam_a + lam_b (in FP64, then rounded) and one per tile row fetches lam_l,
+      // both into LDS behind the staging area
+      float* const dcol = reinterpret_cast<float*>(smem + C::SMEM);
+      float* const drow = dcol + BN;
+      if (tid < BN) {
+        const long c = p0 + tid;
+        float v = 0.0f;
+        if (c < Pp) {
+          const long a = c / g.ldy;
+          const long bo = c - a * g.ldy;
+          v = (float)(g.epi.l1[a] + g.epi.l2[in_col(bo, g)]);
         }
+        dcol[tid] = v;
+      } else {
+        const int lr = tid - BN;
+        drow[lr] = (float)g.epi.l0[orow0 + (lr < lrows ? lr : lrows - 1)];
+      }
+      __syncthreads();
       const float al = (float)g.epi.alpha, b1 = (float)g.epi.b1, b2 = (float)g.epi.b2;
 #pragma unroll
       for (int i = 0; i < FL; ++i) {
-        const int lr = wm + 16 * i + fr;
-        const float dl = (float)g.epi.l0[orow0 + (lr < lrows ? lr : lrows - 1)];
+        const float dl = drow[wm + 16 * i + fr];
 #pragma unroll
-        for (int j = 0; j < FP; ++j)
+        for (int j = 0; j < FP; ++j) {
+          const f4_t dab = *reinterpret_cast<const f4_t*>(dcol + pl0 + 16 * j);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const float L = dl + dab[j][r];
-            acc[i][j][r] = __fdividef(acc[i][j][r], al + L * (b1 + b2 * L));
+            // hardware reciprocal (1 ulp): the quotient is rounded to BF16 next
+            const float L = dl + dab[r];
+            acc[i][j][r] *= __builtin_amdgcn_rcpf(al + L * (b1 + b2 * L));
           }
+        }
       }
     }
     if constexpr (COL == COL_FOLD) {
@@ -408,7 +420,15 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(DmaArgs g) {
     unsigned short* __restrict__ yh = reinterpret_cast<unsigned short*>(g.y);
 #pragma unroll
     for (int pl = 0; pl < NS; ++pl) {
-      if (pl) __syncthreads();  // the previous round's readers are done
+      if (pl) {
+        __syncthreads();  // the previous round's readers are done
+        // the lo round converts again instead of keeping the hi round's 128 BF16
+        // values live next to the accumulators (which would spill)
+#pragma unroll
+        for (int i = 0; i < FL; ++i)
+#pragma unroll
+          for (int j = 0; j < FP; ++j) asm volatile("" : "+v"(acc[i][j]));
+      }
 #pragma unroll
       for (int i = 0; i < FL; ++i)
 #pragma unroll
@@ -465,24 +485,28 @@ template <int NS>
 __global__ __launch_bounds__(256) void to_lowp_kernel(const double* __restrict__ f, unsigned short* __restrict__ o,
                                                       long plane_o, long rows, int nz, int ldo, int fold, int nrep,
                                                       int fpad, int per) {
-  // a wave owns a row: FP64 values into LDS (16-byte loads where the row start
-  // allows, which an even nz guarantees), folded in FP64, 16-byte BF16 stores;
-  // dynamic LDS of 4 nz doubles
+  // a wave owns a row: FP64 values into LDS, folded in FP64, 16-byte BF16
+  // stores; dynamic LDS of 4 nz doubles
   extern __shared__ double lowp_rows[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long row = (long)blockIdx.x * (blockDim.x >> 6) + wave;
   if (row >= rows) return;  // wave-uniform; no block-wide barrier below
   double* rv = lowp_rows + (size_t)wave * nz;
   const double* src = f + (size_t)row * nz;
-  if ((((uintptr_t)src) & 15) == 0) {
-    for (int c = lane; c < nz / 2; c += 64) {
-      const double2 v = *reinterpret_cast<const double2*>(src + 2 * c);
-      rv[2 * c] = v.x;
-      rv[2 * c + 1] = v.y;
+  // 1024 values per round: all 16 loads of a lane in flight before the first
+  // LDS store (a loop that stored each value as it arrived would wait on every load)
+  for (int base = 0; base < nz; base += 1024) {
+    double tv[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = base + 64 * t + lane;
+      tv[t] = e < nz ? src[e] : 0.0;
     }
-    if ((nz & 1) && lane == 0) rv[nz - 1] = src[nz - 1];
-  } else {
-    for (int e = lane; e < nz; e += 64) rv[e] = src[e];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int e = base + 64 * t + lane;
+      if (e < nz) rv[e] = tv[t];
+    }
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -541,18 +565,31 @@ __global__ __launch_bounds__(256) void fold_lowp_kernel(const unsigned short* __
   if (row >= rows) return;  // wave-uniform; no block-wide barrier below
   float* rv = fold_rows + (size_t)wave * ldi;
   const unsigned short* src = in + row * ldi;
-  for (int c = lane; c < ldi / 8; c += 64) {
-    const u4_t hv = *reinterpret_cast<const u4_t*>(src + 8 * c);
-    u4_t lv = u4_t{0u, 0u, 0u, 0u};
-    if (NS == 2) lv = *reinterpret_cast<const u4_t*>(src + plane_i + 8 * c);
+  // 4 x 512 values per round, every load of a lane in flight before the LDS stores
+  for (int base = 0; base < ldi / 8; base += 256) {
+    u4_t hv[4], lv[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int hlf = 0; hlf < 2; ++hlf) {
-        float v = __uint_as_float((hv[t] >> (16 * hlf)) << 16);
-        if (NS == 2) v += __uint_as_float((lv[t] >> (16 * hlf)) << 16);
-        rv[8 * c + 2 * t + hlf] = v;
+    for (int q = 0; q < 4; ++q) {
+      const int c = base + 64 * q + lane;
+      hv[q] = lv[q] = u4_t{0u, 0u, 0u, 0u};
+      if (c < ldi / 8) {
+        hv[q] = *reinterpret_cast<const u4_t*>(src + 8 * c);
+        if (NS == 2) lv[q] = *reinterpret_cast<const u4_t*>(src + plane_i + 8 * c);
       }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = base + 64 * q + lane;
+      if (c >= ldi / 8) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int hlf = 0; hlf < 2; ++hlf) {
+          float v = __uint_as_float((hv[q][t] >> (16 * hlf)) << 16);
+          if (NS == 2) v += __uint_as_float((lv[q][t] >> (16 * hlf)) << 16);
+          rv[8 * c + 2 * t + hlf] = v;
+        }
+    }
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
