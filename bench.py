@@ -125,7 +125,7 @@ def bench_batch(args, P, torch, dev, log):
                      f"split-bf16 mode products for the {nsplit} problems with every dimension >= 96, "
                      f"f32 for the rest") + ", f64 residual/update"}
     # mode products: FP32 MFMA in the FP32 batch (the split problems of the
-    # SEM_BF16X3 batch issue three BF16 MFMAs per product)
+    # SEM_BF16X3 batch issue four BF16 MFMAs per product)
     mp = per_prec["f32"]["mode_product_tflops"]
     res["roofline"] = {"bound": "mfma", "kernel": "FP32 batch, all passes (4 N (nx+ny+nz) flop per iteration)",
                        "achieved": mp, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": mp / PEAK_FP32_TFLOPS}
@@ -206,17 +206,19 @@ def bench_schrodinger(args, P, torch, dev, log):
     ok = [p for p, r in res["by_preconditioner"].items() if r["status"] == 0]
     best = min(ok, key=lambda p: res["by_preconditioner"][p]["ms_per_solve"], default="f64")
     res.update({"preconditioner": best, **res["by_preconditioner"][best]})
-    # the preconditioner's mode products dominate: their flop (the folded
-    # transforms of the BF16 modes: 2 N (nx + ny + nz) per application) over the
-    # whole solve time
+    # the preconditioner's mode products dominate: their flop, 4 N (nx + ny + nz)
+    # per application (the products as defined; the reflection-split BF16 passes
+    # execute half of it), over the whole solve time
     nx, ny, nz = plan.shape
     it_b = res["by_preconditioner"][best]["iterations"]
     folded = best in ("bf16", "bf16x3")
-    fd_flop = (2.0 if folded else 4.0) * n * (nx + ny + nz) * (it_b + 1)
+    fd_flop = 4.0 * n * (nx + ny + nz) * (it_b + 1)
     ach = fd_flop / (res["by_preconditioner"][best]["ms_per_solve"] * 1e-3) / 1e12
     peak = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS}.get(best, PEAK_BF16_TFLOPS)
     res["roofline"] = {"bound": "mfma", "kernel": "whole PCG solve, preconditioner mode products counted",
-                       "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
+                       "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                       "executed_frac": ach / peak / (2.0 if folded else 1.0)}
+    res["tuned_shapes"] = plan.tuning(best) if best != "f64" else None
     del u, vd, fd, ued, plan
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
@@ -247,13 +249,30 @@ def bench_schrodinger(args, P, torch, dev, log):
 
 
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of the
-# current kernels at n = 999, scaled by a streaming kernel of known traffic
-# (FETCH x 1.970, WRITE x 1.000); recorded here because counters cannot be read
-# inside the timed run.  Variants without such runs report null.
+# current kernels at n = 999, scaled by a device copy of known size (FETCH x 2.000,
+# WRITE x 1.000); recorded here because counters cannot be read inside the timed
+# run.  Variants without such runs report null.
 PROFILED_TRAFFIC = {
     # one FP64 y-axis mode product (mode_nn_f64)
-    "f64": {"fetch_bytes": 38.6e9, "write_bytes": 8.23e9,
-            "algorithmic_bytes": 15.97e9, "source": "profiles/mode_f64_n999.md"},
+    "f64": {"fetch_bytes": 41.7e9, "write_bytes": 8.22e9, "algorithmic_bytes": 15.97e9,
+            "mfma_flops_counted": 2.097e12, "mfma_busy": 0.784, "source": "profiles/mode_f64_n999.md"},
+    # one split-BF16 FD application (conversion, six passes, unfold)
+    "bf16x3": {"fetch_bytes": 43.6e9, "write_bytes": 36.8e9, "source": "profiles/split_bf16_refined_n999.md"},
+}
+
+# The kernel whose launch the headline roofline times, per low-precision variant.
+KERNEL_NAME = {
+    "bf16x3": "mode_rot_dma<BF16X3, bf16, STORE, COL_FOLD> (z forward, y fold)",
+    "bf16": "mode_rot_dma<BF16, bf16, STORE, COL_FOLD> (z forward, y fold)",
+    "f32": "mode_rot_f32<f32, f32, STORE> (z forward)",
+}
+# rocprofv3 counters of that kernel at n = 999 (per launch; HBM bytes scaled as
+# above; MFMA ops = SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512; busy = SQ_VALU_MFMA_BUSY_CYCLES
+# / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs)).  Variants without such runs: null.
+PROFILED_KERNEL = {
+    "bf16x3": {"fetch_bytes": 5.21e9, "write_bytes": 4.09e9, "algorithmic_bytes": 7.98e9,
+               "mfma_flops_counted": 4.291e12, "mfma_busy": 0.544, "clock_ghz": 1.90,
+               "source": "profiles/split_bf16_refined_n999.md"},
 }
 
 
@@ -307,7 +326,8 @@ def bench_ch(args, P, torch, dev, log):
            "dtype": "f32 solve + 1 f64 refinement sweep", "graph": True, "relative_mass_drift": drift,
            "max_abs_phi": float(np.max(np.abs(phi))),
            "roofline": {"bound": "mfma", "kernel": "whole step (FD application counted: 4 N (nx+ny+nz) flop)",
-                        "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS}}
+                        "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS},
+           "tuned_shapes": ch.tuning()}
     if args.ch_oracle_steps > 0 and not args.no_cpu_baseline:
         import oracle as O
         # the same start, args.ch_oracle_steps steps on the GPU and in the oracle
@@ -459,26 +479,58 @@ def main() -> int:
         fd_ms = e0.elapsed_time(e1) / args.kernel_reps
         del ul
         peak = PEAK_FP32_TFLOPS if prec == "f32" else PEAK_BF16_TFLOPS
-        # the BF16 modes run the reflection-split transforms: each pass contracts
-        # half-length blocks, 4 N sum_a nrep_a flop per application (nrep_a =
-        # orbit representatives of axis a, ~n_a / 2); FP32 the dense 4 N sum_a n_a
-        flops = folded_flops if prec != "f32" else fd_flops
-        ach = flops / (fd_ms * 1e-3) / 1e12
+        # achieved counts the six mode products as defined, 4 N sum_a n_a flop per
+        # application; the BF16 modes run the reflection-split transforms, whose
+        # passes contract half-length blocks and execute 4 N sum_a nrep_a (nrep_a =
+        # orbit representatives of axis a, ~n_a / 2)
+        executed = folded_flops if prec != "f32" else fd_flops
+        ach = fd_flops / (fd_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": f"{prec} FD application: " +
                 ("fold + six reflection-split mode_rot_dma passes + unfold" if prec != "f32" else
                  "six mode_rot_f32 passes"),
                 "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
                 "traffic": _traffic(prec), "traffic_detail": PROFILED_TRAFFIC.get(prec),
-                "launch_ms": fd_ms, "flops_per_launch": flops,
-                "dense_equivalent_tflops": fd_flops / (fd_ms * 1e-3) / 1e12,
-                "mfma_work_factor": 4 if prec == "bf16x3" else 1}
+                "launch_ms": fd_ms, "flops_per_launch": fd_flops, "executed_flops_per_launch": executed,
+                "executed_frac": executed / (fd_ms * 1e-3) / 1e12 / peak,
+                "mfma_products_per_flop": 4 if prec == "bf16x3" else 1}
         v["fd_application"] = roof
-        log(f"{prec} FD application alone: {fd_ms:.2f} ms, {ach:.1f} TFLOP/s algorithmic "
-            f"({ach / peak:.3f} of {peak} TFLOP/s)")
+        log(f"{prec} FD application alone: {fd_ms:.2f} ms, {ach:.1f} TFLOP/s of the dense products "
+            f"({ach / peak:.3f} of {peak} TFLOP/s), executed {executed / (fd_ms * 1e-3) / 1e12:.1f}")
         if name == best:
             lowp_roof = roof
 
-    # dominant kernel: the batched NN mode product (y axis), timed alone per launch
+    # dominant kernel of the winning low-precision variant: the pass that takes the
+    # largest share of its solve, z forward with the y fold in its store (pass 1 of
+    # the reflection-split sequence; for FP32 the z-forward mode_rot_f32),
+    # launched alone through sem_lowp_pass and timed with HIP events on the plan's
+    # stream (torch's current stream).  achieved counts 2 n flop per unknown, the
+    # mode product as defined (the per-unit work of the measurement plan); the
+    # reflection-split kernel executes 2 nrep of them, reported beside it.
+    kernel_roof = None
+    bprec = best.split("_")[0]
+    if best != "f64":
+        plan.lowp_pass(bprec, 0, 1)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        plan.lowp_pass(bprec, 0, args.kernel_reps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pass_ms = e0.elapsed_time(e1) / args.kernel_reps
+        alg = 2.0 * N * nz
+        executed = 2.0 * N * nrep[2] if bprec != "f32" else alg
+        peak = PEAK_FP32_TFLOPS if bprec == "f32" else PEAK_BF16_TFLOPS
+        ach = alg / (pass_ms * 1e-3) / 1e12
+        prof = PROFILED_KERNEL.get(bprec)
+        kernel_roof = {
+            "bound": "mfma", "kernel": KERNEL_NAME[bprec], "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": ach / peak, "traffic": None if prof is None else prof["fetch_bytes"] + prof["write_bytes"],
+            "launch_ms": pass_ms, "flops_per_launch": alg, "executed_flops_per_launch": executed,
+            "executed_frac": executed / (pass_ms * 1e-3) / 1e12 / peak,
+            "counters": prof}
+        log(f"{bprec} pass 1 alone ({KERNEL_NAME[bprec]}): {pass_ms:.3f} ms, {ach:.1f} TFLOP/s of the dense "
+            f"product ({ach / peak:.3f} of {peak}), executed {executed / (pass_ms * 1e-3) / 1e12:.1f} TFLOP/s")
+
+    # the batched NN mode product (y axis) of the FP64 solve, timed alone per launch
     tmp = torch.empty_like(f)
     plan.mode_product(1, False, f, tmp)
     torch.cuda.synchronize()
@@ -544,7 +596,8 @@ def main() -> int:
                          "traffic_detail": PROFILED_TRAFFIC["f64"],
                          "launch_ms": launch_ms, "flops_per_launch": flops_launch},
     }
-    out["roofline"] = lowp_roof if lowp_roof is not None else out["roofline_f64"]
+    out["roofline"] = kernel_roof if kernel_roof is not None else out["roofline_f64"]
+    out["roofline_fd_application"] = lowp_roof
 
     if args.batch > 0:
         out["batched"] = bench_batch(args, P, torch, dev, log)

@@ -192,9 +192,10 @@ sem_status sem_solve_lowp(sem_plan *p, sem_prec prec, const double *f, double *u
  * the PCG preconditioner, the Cahn-Hilliard stepper, split-BF16 batch entries) run
  * with launch shapes chosen by timing on the first use of each precision: for
  * SEM_F32 the factor-tile rows (128, 96, 64 or 32) of each of the six passes; for
- * SEM_BF16 / SEM_BF16X3 the tile-order group (1, 2 or 4 column strips of 256 that
- * consecutive workgroups share, which sets how many workgroups reuse one factor
- * tile from L2).  The shapes change no result bit.  Each candidate is launched
+ * SEM_BF16 / SEM_BF16X3 the tile order, g = 1, 2 or 4 column strips of 256 that
+ * consecutive workgroups share, and the launch: one workgroup per tile (value g)
+ * or one workgroup per compute unit looping over the tiles (value 16 + g).  The
+ * timed candidates are 1, 4, 17 and 20.  The shapes change no result bit.  Each candidate is launched
  * once untimed, then three times, on the plan's own workspace; the fastest is kept
  * in the plan and in a process-wide cache keyed by device architecture, kernel,
  * output layout and log2 size buckets of the pass, which later plans of similar
@@ -211,10 +212,20 @@ sem_status sem_plan_tune(sem_plan *p, sem_prec prec);
  * *tuned = 0 before prec is tuned).  SEM_EINVAL: null pointers, SEM_F64. */
 sem_status sem_plan_tuning(const sem_plan *p, sem_prec prec, int *tuned, int choice[6]);
 /* Install shapes for prec without timing: 128, 96, 64 or 32 per pass for SEM_F32,
- * 1, 2 or 4 for the BF16 modes.  SEM_EINVAL for anything else. */
+ * 1, 2, 4, 17, 18 or 20 for the BF16 modes.  SEM_EINVAL for anything else. */
 sem_status sem_plan_set_tuning(sem_plan *p, sem_prec prec, const int choice[6]);
 /* Process-wide cache counters: lookups answered, lookups missed, entries held. */
 sem_status sem_tune_stats(int *hits, int *misses, int *entries);
+/* Launch pass `pass` (0..5, order of application; for the BF16 modes the passes
+ * of the reflection-split sequence) of prec's FD application `reps` times on the
+ * plan stream, with the plan's tuned shapes, on whatever the plan workspace holds:
+ * a way to time the mode-product kernels one by one (events around the call).
+ * The result is not meaningful by itself; run a solve of prec first for
+ * realistic data. Every access stays inside the workspace and the factors
+ * whatever they hold. SEM_F32's last pass runs as an FP32 store of the same
+ * shape instead of its accumulation into u. SEM_EINVAL: SEM_F64, pass outside
+ * 0..5, reps < 1. */
+sem_status sem_lowp_pass(sem_plan *p, sem_prec prec, int pass, int reps);
 
 /* ---- other spectral multipliers --------------------------------------------- */
 

@@ -54,6 +54,7 @@ def _load():
         "sem_plan_tuning": (c_int, [c_void_p, c_int, POINTER(c_int), POINTER(c_int)]),
         "sem_plan_set_tuning": (c_int, [c_void_p, c_int, POINTER(c_int)]),
         "sem_tune_stats": (c_int, [POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
+        "sem_lowp_pass": (c_int, [c_void_p, c_int, c_int, c_int]),
         "sem_apply_spectral": (c_int, [c_void_p, c_int, c_double, c_double, c_void_p, c_void_p]),
         "sem_pcg_workspace_bytes": (c_int, [c_void_p, POINTER(c_size_t)]),
         "sem_pcg_solve": (c_int, [c_void_p, c_void_p, c_double, c_int, c_double, c_int, c_void_p, c_void_p,
@@ -278,6 +279,12 @@ class Plan:
         pv = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
         ch = (c_int * 6)(*[int(c) for c in choice])
         check(lib.sem_plan_set_tuning(self._p, pv, ch))
+
+    def lowp_pass(self, prec: str, pass_index: int, reps: int = 1):
+        """Launch one pass of prec's FD application reps times (sem_lowp_pass), for timing."""
+        pv = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        self._prepare(pv)
+        check(lib.sem_lowp_pass(self._p, pv, int(pass_index), int(reps)))
 
     def apply_spectral(self, kind: str, a: float, param: float, f, u=None):
         """u = g(H_3 + a I) f with g(x) = exp(-param x) ("exp") or x^(-param) ("power")

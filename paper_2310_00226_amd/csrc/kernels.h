@@ -101,11 +101,13 @@ struct LpPass {
   int col = COL_PLAIN;
   int bsym = 0, bpad = 0, bn = 0, bper = 0;
   // tuned launch shapes: FP32 factor-tile rows (128, 96, 64, 32; 0 = by rule);
-  // BF16 tile order: groups of tile_group p-strips step through the l-tiles
-  // together (1 = every l-tile of one p-strip in a row)
+  // BF16 tile order: groups of g p-strips step through the l-tiles together
+  // (g = 1: every l-tile of one p-strip in a row); tile_group = g launches one
+  // block per tile, DMA_PERSIST + g one block per CU looping over the tiles
   int tile_rows = 0;
   int tile_group = 1;
 };
+constexpr int DMA_PERSIST = 16;
 // FP32 passes (mode_lp.hip): mode LP_F32, in_kind 0 or 1, out_kind 1 or 0 (accumulate).
 hipError_t launch_mode_lp(const LpPass& ps, hipStream_t stream);
 

@@ -112,6 +112,7 @@ struct DmaArgs {
   int K1 = 0, K2 = 0, koff2 = 0, frow2 = 0, L1 = 0, L2 = 0;
   long tl1 = 0, tiles_l = 0, tiles_p = 0, ntiles = 0, nbp = 0;
   int group = 1;
+  int persist = 0;
   int col = COL_PLAIN, bsym = 0, bpad = 0, bn = 0, bper = 0;
   EpiLP epi;
 };
@@ -142,21 +143,16 @@ struct KCfg {
   static constexpr int SMEM = STAGES * STAGEB > EPIB ? STAGES * STAGEB : EPIB;
 };
 
+// One 256 x 256 output tile t of a pass: DMA ring over the contraction, MFMAs,
+// epilogue.  Every thread of the block calls it with the same t.
 template <int MODE, class TOut, int EPI, int COL>
-__global__ __launch_bounds__(NTHREADS) void mode_rot_dma(DmaArgs g) {
+__device__ __forceinline__ void dma_tile(const DmaArgs& g, const long t, unsigned char* const smem) {
   typedef KCfg<MODE> C;
   constexpr int NS = C::NS, S = C::STAGES;
-  // DIVIDE keeps the tile's 256 column and 256 row parts of the denominators
-  // behind the staging area
-  constexpr int SMEM_ALL = C::SMEM + (EPI == EPI_DIVIDE ? 2 * 256 * 4 : 0);
-  __shared__ __attribute__((aligned(1024))) unsigned char smem[SMEM_ALL];
   unsigned char* const st0 = smem;
   unsigned char* const st1 = smem + C::STAGEB;
   unsigned char* const st2 = smem + (S > 2 ? 2 : 0) * C::STAGEB;
   unsigned char* const st3 = smem + (S > 3 ? 3 : 0) * C::STAGEB;
-
-  const long t = xcd_tile(g.nbp);
-  if (t >= g.ntiles) return;  // whole block leaves together, before any barrier
   // tile order: groups of `group` p-strips (the last one possibly shorter) step
   // through the l-tiles together, the strips of a group fastest
   const long per_group = g.tiles_l * g.group;
@@ -477,6 +473,32 @@ __global__ __launch_bounds__(NTHREADS) void mode_rot_dma(DmaArgs g) {
   }
 }
 
+// A pass: one block per tile (persist = 0, blocks numbered XCD-aware), or one
+// block per CU looping over tiles (persist = 1): each XCD takes a contiguous range
+// of the tile numbering and its blocks stride through it, so that the stores of
+// one tile drain while the next tile's first chunks stream in.
+template <int MODE, class TOut, int EPI, int COL>
+__global__ __launch_bounds__(NTHREADS) void mode_rot_dma(DmaArgs g) {
+  typedef KCfg<MODE> C;
+  // DIVIDE keeps the tile's 256 column and 256 row parts of the denominators
+  // behind the staging area
+  constexpr int SMEM_ALL = C::SMEM + (EPI == EPI_DIVIDE ? 2 * 256 * 4 : 0);
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[SMEM_ALL];
+  if (!g.persist) {
+    const long t = xcd_tile(g.nbp);
+    if (t >= g.ntiles) return;  // whole block leaves together, before any barrier
+    dma_tile<MODE, TOut, EPI, COL>(g, t, smem);
+    return;
+  }
+  const long xcd = blockIdx.x & 7, j = blockIdx.x >> 3, nper = gridDim.x >> 3;
+  const long per = (g.ntiles + 7) / 8;
+  const long t_end = min((xcd + 1) * per, g.ntiles);
+  for (long t = xcd * per + j; t < t_end; t += nper) {  // uniform over the block
+    dma_tile<MODE, TOut, EPI, COL>(g, t, smem);
+    __syncthreads();  // the next tile's DMAs overwrite the staging area
+  }
+}
+
 // FP64 caller-layout array (rows of nz) -> BF16 hi (+ lo) planes with pitch ldo,
 // padding zeroed; with fold, the rows are folded along z first (v+ at column r,
 // v- at fpad + r, r < nrep; reflection n - 1 - r, or (n - r) mod n periodic),
@@ -767,11 +789,24 @@ static hipError_t launch_dma_t(const LpPass& ps, hipStream_t stream) {
       COL == COL_FOLD ? (long)ps.A * ((ps.bsym + 127) / 128) : ((long)ps.A * ps.ldy + BN - 1) / BN;
   g.tiles_p = tiles_p;
   g.ntiles = g.tiles_l * tiles_p;
-  g.group = ps.tile_group >= 1 ? ps.tile_group : 1;
+  // tile_group: g in {1, 2, 4} (one block per tile) or DMA_PERSIST + g (one block
+  // per CU looping over the tiles)
+  const int tg = ps.tile_group >= 1 ? ps.tile_group : 1;
+  g.persist = tg > DMA_PERSIST ? 1 : 0;
+  g.group = g.persist ? tg - DMA_PERSIST : tg;
   g.nbp = ((g.ntiles + 7) / 8) * 8;
   if (g.ntiles == 0) return hipSuccess;
   if (g.nbp > 0x7fffffffL) return hipErrorInvalidValue;
-  mode_rot_dma<MODE, TOut, EPI, COL><<<dim3((unsigned)g.nbp), dim3(NTHREADS), 0, stream>>>(g);
+  long grid = g.nbp;
+  if (g.persist) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const long full = (long)(cus > 8 ? cus : 8) / 8 * 8;  // one block per CU, every XCD alike
+    grid = full < g.nbp ? full : g.nbp;
+  }
+  mode_rot_dma<MODE, TOut, EPI, COL><<<dim3((unsigned)grid), dim3(NTHREADS), 0, stream>>>(g);
   return hipGetLastError();
 }
 

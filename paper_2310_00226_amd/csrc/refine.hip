@@ -455,7 +455,8 @@ hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double*
 
 // ---- autotuning of the launch shapes -------------------------------------------
 // FP32 passes: factor-tile rows 128, 96, 64 or 32; BF16 passes: tile order group
-// 1, 2 or 4 p-strips.  Each pass geometry is timed once (one warm-up launch, the
+// of 1 or 4 p-strips, with one block per tile or one block per CU looping over
+// the tiles (DMA_PERSIST + group).  Each pass geometry is timed once (one warm-up launch, the
 // fastest of three), on the plan's own workspace, and the choice is kept in the
 // plan and in the tuning cache (key: architecture, kernel, output layout, and
 // log2 buckets of rows, contraction length and tensor rows), so plans of similar
@@ -510,7 +511,7 @@ sem_status lp_tune(sem_plan* p, const LpWork& w) {
     return SEM_OK;  // no timing under capture: the rule-based shapes stay
   const Spectral sp{p->alpha, 1.0, 0.0};
   static const int rows_cand[4] = {128, 96, 64, 32};
-  static const int group_cand[3] = {1, 2, 4};
+  static const int group_cand[4] = {1, 4, DMA_PERSIST + 1, DMA_PERSIST + 4};
   for (int s = 0; s < 6; ++s) {
     LpPass ps = prec == SEM_F32 ? f32_pass(p, w, sp, s, nullptr, nullptr, 1, nullptr) : folded_pass(p, w, sp, s);
     if (prec == SEM_F32) ps.in_kind = 1;  // first pass: time the FP32-input variant
@@ -522,7 +523,7 @@ sem_status lp_tune(sem_plan* p, const LpWork& w) {
     int choice = 0;
     if (!tune_lookup(key, &choice)) {
       const int* cand = prec == SEM_F32 ? rows_cand : group_cand;
-      const int nc = prec == SEM_F32 ? 4 : 3;
+      const int nc = 4;
       float best = INFINITY;
       for (int c = 0; c < nc; ++c) {
         if (prec == SEM_F32)
@@ -687,10 +688,11 @@ extern "C" sem_status sem_plan_set_tuning(sem_plan* p, sem_prec prec, const int 
     return set_error(SEM_EINVAL, "sem_plan_set_tuning: only SEM_F32, SEM_BF16 and SEM_BF16X3 have tunable shapes");
   for (int s = 0; s < 6; ++s) {
     const int c = choice[s];
-    const bool ok = prec == SEM_F32 ? (c == 128 || c == 96 || c == 64 || c == 32) : (c == 1 || c == 2 || c == 4);
+    const int g = c > DMA_PERSIST ? c - DMA_PERSIST : c;
+    const bool ok = prec == SEM_F32 ? (c == 128 || c == 96 || c == 64 || c == 32) : (g == 1 || g == 2 || g == 4);
     if (!ok)
       return set_error(SEM_EINVAL, prec == SEM_F32 ? "sem_plan_set_tuning: FP32 tile rows must be 128, 96, 64 or 32"
-                                                   : "sem_plan_set_tuning: BF16 tile groups must be 1, 2 or 4");
+                                                   : "sem_plan_set_tuning: BF16 shapes must be 1, 2, 4 or 17, 18, 20");
   }
   for (int s = 0; s < 6; ++s) p->tune_choice[prec][s] = choice[s];
   p->tuned[prec] = 1;
@@ -701,5 +703,32 @@ extern "C" sem_status sem_tune_stats(int* hits, int* misses, int* entries) {
   if (!hits || !misses || !entries) return set_error(SEM_EINVAL, "sem_tune_stats: null argument");
   tune_counts(hits, misses);
   *entries = tune_size();
+  return SEM_OK;
+}
+
+extern "C" sem_status sem_lowp_pass(sem_plan* p, sem_prec prec, int pass, int reps) {
+  if (!p) return set_error(SEM_EINVAL, "sem_lowp_pass: null plan");
+  if (prec != SEM_F32 && prec != SEM_BF16 && prec != SEM_BF16X3)
+    return set_error(SEM_EINVAL, "sem_lowp_pass: only SEM_F32, SEM_BF16 and SEM_BF16X3 run low-precision passes");
+  if (pass < 0 || pass > 5 || reps < 1) return set_error(SEM_EINVAL, "sem_lowp_pass: pass in 0..5, reps >= 1");
+  LpWork w;
+  sem_status st = lp_prepare(p, prec, &w, true);
+  if (st != SEM_OK) return st;
+  const Spectral sp{p->alpha, 1.0, 0.0};
+  const LpPass ps = prec == SEM_F32 ? f32_pass(p, w, sp, pass, nullptr, nullptr, 1, nullptr) : folded_pass(p, w, sp, pass);
+  LpPass q = ps;
+  if (prec == SEM_F32) {  // FP32 input throughout, the first pass from the residual buffer
+    q.in_kind = 1;
+    if (pass == 0) {
+      q.x = w.r;
+      q.ldx = w.ldr;
+    }
+  } else if (!dma_supported(q)) {
+    return set_error(SEM_EINVAL, "sem_lowp_pass: pass geometry not supported");
+  }
+  for (int r = 0; r < reps; ++r) {
+    const hipError_t e = prec == SEM_F32 ? launch_mode_lp(q, p->stream) : launch_mode_dma(q, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "sem_lowp_pass");
+  }
   return SEM_OK;
 }

@@ -15,7 +15,7 @@ from workloads import normal_noise
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-VALID = {"f32": {128, 96, 64, 32}, "bf16": {1, 2, 4}, "bf16x3": {1, 2, 4}}
+VALID = {"f32": {128, 96, 64, 32}, "bf16": {1, 2, 4, 17, 18, 20}, "bf16x3": {1, 2, 4, 17, 18, 20}}
 BOX = (-1, 1, -1, 1, -1, 1)
 
 
@@ -78,7 +78,7 @@ def test_every_shape_gives_the_same_bits(torch, P, prec, case):
 def test_set_tuning_rejects_invalid(torch, P):
     plan = P.Plan(3, (6, 6, 6), BOX, 1.0, "dirichlet")
     for prec, bad in [("f32", [128, 96, 64, 32, 16, 128]), ("bf16", [1, 2, 3, 1, 1, 1]), ("bf16x3", [0] * 6),
-                      ("f64", [1] * 6)]:
+                      ("bf16x3", [16] * 6), ("bf16", [19] * 6), ("f64", [1] * 6)]:
         with pytest.raises(P.SemError):
             plan.set_tuning(prec, bad)
     with pytest.raises(P.SemError):
@@ -157,3 +157,22 @@ def test_cahn_hilliard_steps_with_tuned_shapes(torch, P, prec):
     assert ch.tuning() == ch_shapes
     f64 = P.CahnHilliard(3, (4, 4, 4), (0, 6.283185307179586) * 3, 0.05, 0.02, 1e-4, prec="f64", refine_sweeps=0)
     assert f64.tuning() is None
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "bf16x3"])
+def test_single_pass_launches(torch, P, prec):
+    """sem_lowp_pass runs every pass on the plan workspace; solves before and
+    after it give identical bits (the workspace is scratch)."""
+    _log(f"[tune] single passes {prec}")
+    plan = P.Plan(3, (14, 11, 17), BOX, 1.0, "periodic")
+    f = torch.from_numpy(normal_noise(plan.shape, seed=21)).to("cuda")
+    u0 = plan.solve_lowp(f, prec=prec).cpu().numpy()
+    for s in range(6):
+        plan.lowp_pass(prec, s, 2)
+    torch.cuda.synchronize()
+    assert np.array_equal(plan.solve_lowp(f, prec=prec).cpu().numpy(), u0)
+    for bad in [(-1, 1), (6, 1), (0, 0)]:
+        with pytest.raises(P.SemError):
+            plan.lowp_pass(prec, *bad)
+    with pytest.raises(P.SemError):
+        plan.lowp_pass("f64", 0, 1)
