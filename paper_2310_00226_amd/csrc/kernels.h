@@ -45,6 +45,14 @@ __device__ inline double spectral_mul(double v, double lam, const EpiArgs& e) {
 // (g zero-padded to a multiple of 128 in both dimensions).
 hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg, const int dims[3], int axis, int epi,
                            const EpiArgs& ea, hipStream_t stream);
+// General block form: Y[p][l][q] = sum_{m < K} A[l][m] X[p][m][q] for l < L, the
+// contracted axis of X of extent ldxa, the output axis of Y of extent ldya (batch
+// strides ldxa Q, ldya Q); g rows >= pad16(K), ldg >= pad128(L).  K = 0 stores zeros.
+hipError_t launch_mode_f64_part(const double* x, double* y, const double* g, int ldg, long P, int K, int L, long Q,
+                                int ldxa, int ldya, int epi, const EpiArgs& ea, hipStream_t stream);
+// Reflection fold (unfold = 0) or unfold (1) of X[p][i][q] along i (fold_f64.hip).
+hipError_t launch_fold_f64(const double* x, double* y, long P, int n, long Q, int nrep, int per, int unfold,
+                           hipStream_t stream);
 
 // ---- low-precision rotating mode products (mode_lp.hip) ----
 enum { LP_F32 = 1, LP_BF16 = 2, LP_BF16X3 = 3 };

@@ -54,9 +54,10 @@ __device__ __forceinline__ long xcd_tile(long nblocks_padded) {
 // ---------------------------------------------------------------------------
 template <int EPI>
 __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __restrict__ x, double* __restrict__ y,
-                                                             const double* __restrict__ g, int ldg, long P, int L,
-                                                             long Q, long tiles_l, long tiles_q, long ntiles,
-                                                             long nblocks_padded, EpiArgs epi) {
+                                                             const double* __restrict__ g, int ldg, long P, int K,
+                                                             int L, int ldxa, int ldya, long Q, long tiles_l,
+                                                             long tiles_q, long ntiles, long nblocks_padded,
+                                                             EpiArgs epi) {
   __shared__ double lds[2 * (TILE_G + TILE_G)];
   const long t = xcd_tile(nblocks_padded);
   if (t >= ntiles) return;
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
   const long p = rest / tiles_q;
   const int l0 = (int)(lt * BM);
   const long q0 = qt * BN;
-  const double* __restrict__ xp = x + (size_t)p * L * Q;
+  const double* __restrict__ xp = x + (size_t)p * ldxa * Q;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -77,12 +78,12 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
   // global -> register staging: element e = 0..7 of this thread covers row
   // kk = tid/64 + 4*(e>>1), col c = tid%64 + 64*(e&1) of a [BK][128] tile.  Loads
   // are branch-free: tensor columns past Q are clamped to a valid address (they
-  // only feed output columns that are never stored); contraction rows past L are
+  // only feed output columns that are never stored); contraction rows past K are
   // clamped and zeroed (the padded factor rows are zero too).
   // The rows of each wave are wave-uniform (row pointers in scalar registers,
   // 32-bit lane offsets).
   double rg[8], rx[8];
-  const int nchunk = (L + BK - 1) / BK;
+  const int nchunk = (K + BK - 1) / BK;
   const int r0 = __builtin_amdgcn_readfirstlane(tid >> 6), c0 = tid & 63;
   const unsigned qa = (unsigned)(q0 + c0 < Q ? q0 + c0 : Q - 1);
   const unsigned qb = (unsigned)(q0 + c0 + 64 < Q ? q0 + c0 + 64 : Q - 1);
@@ -96,12 +97,12 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
       rg[2 * j] = gr[c0];
       rg[2 * j + 1] = gr[c0 + 64];
       const int m = m0 + r0 + 4 * j;
-      const double* __restrict__ xr = xp + (size_t)(m < L ? m : L - 1) * Q;
+      const double* __restrict__ xr = xp + (size_t)(m < K ? m : K - 1) * Q;
       rx[2 * j] = xr[qa];
       rx[2 * j + 1] = xr[qb];
     }
   };
-  // the zeroing of rows past L happens here, after the MFMA block, so that no wait
+  // the zeroing of rows past K happens here, after the MFMA block, so that no wait
   // for the loads in flight is needed before it
   auto store_chunk = [&](int buf, int c) {
     double* sa = lds + buf * (2 * TILE_G);
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int kk = r0 + 4 * j;
-      const bool ok = c * BK + kk < L;
+      const bool ok = c * BK + kk < K;
       sa[kk * LDG + c0] = rg[2 * j];
       sa[kk * LDG + c0 + 64] = rg[2 * j + 1];
       sb[kk * LDG + c0] = ok ? rx[2 * j] : 0.0;
@@ -142,22 +143,25 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
   };
 
   // steady state: loads of chunk c+1 are in flight while chunk c is multiplied
-  load_chunk(0);
-  store_chunk(0, 0);
-  __syncthreads();
-  for (int c = 0; c + 1 < nchunk; ++c) {
-    load_chunk(c + 1);
-    // keep the LDS stores (which wait for the loads) after the whole MFMA block
-    __builtin_amdgcn_sched_barrier(0);
-    compute_chunk(c & 1);
-    __builtin_amdgcn_sched_barrier(0);
-    store_chunk((c + 1) & 1, c + 1);
+  // (K = 0, an empty antisymmetric block, leaves the accumulators at zero)
+  if (nchunk > 0) {
+    load_chunk(0);
+    store_chunk(0, 0);
     __syncthreads();
+    for (int c = 0; c + 1 < nchunk; ++c) {
+      load_chunk(c + 1);
+      // keep the LDS stores (which wait for the loads) after the whole MFMA block
+      __builtin_amdgcn_sched_barrier(0);
+      compute_chunk(c & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      store_chunk((c + 1) & 1, c + 1);
+      __syncthreads();
+    }
+    compute_chunk((nchunk - 1) & 1);
   }
-  compute_chunk((nchunk - 1) & 1);
 
   // f64 16x16 accumulator layout: lane, register r  ->  row 4r + lane/16, col lane%16
-  double* __restrict__ yp = y + (size_t)p * L * Q;
+  double* __restrict__ yp = y + (size_t)p * ldya * Q;
   double cden[4] = {0.0, 0.0, 0.0, 0.0};
   if constexpr (EPI == EPI_DIVIDE || EPI == EPI_SPECTRAL) {
 #pragma unroll
@@ -194,9 +198,9 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
 // ---------------------------------------------------------------------------
 template <int EPI>
 __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __restrict__ x, double* __restrict__ y,
-                                                             const double* __restrict__ g, int ldg, long P, int L,
-                                                             long tiles_l, long ntiles, long nblocks_padded,
-                                                             EpiArgs epi) {
+                                                             const double* __restrict__ g, int ldg, long P, int K,
+                                                             int L, int ldxa, int ldya, long tiles_l, long ntiles,
+                                                             long nblocks_padded, EpiArgs epi) {
   __shared__ double lds[2 * (TILE_T_NT + TILE_G)];
   const long t = xcd_tile(nblocks_padded);
   if (t >= ntiles) return;
@@ -214,20 +218,20 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
   // Factor tile [BK][128] as in the NN shape; tensor tile [128][BK]: element e of
   // this thread is row r = tid/16 + 16 e, contraction column tid%16.  Rows past P
   // are clamped to a valid address (their outputs are never stored); contraction
-  // columns past L are clamped and zeroed.
-  // Uniform tile base, 32-bit lane offsets (128 rows x L < 2^32 elements).
+  // columns past K are clamped and zeroed.
+  // Uniform tile base, 32-bit lane offsets (128 rows x ldxa < 2^32 elements).
   double rg[8], rx[8];
-  const int nchunk = (L + BK - 1) / BK;
+  const int nchunk = (K + BK - 1) / BK;
   const int r0 = __builtin_amdgcn_readfirstlane(tid >> 6), c0 = tid & 63;
   const double* __restrict__ gw = g + (size_t)r0 * ldg + l0;
   const int tr = tid >> 4, tc = tid & 15;
-  const double* __restrict__ tb = x + (size_t)p0 * L;
+  const double* __restrict__ tb = x + (size_t)p0 * ldxa;
   const int rmax = (int)(P - 1 - p0);
   unsigned xoff[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int rr = tr + 16 * e;
-    xoff[e] = (unsigned)(rr < rmax ? rr : rmax) * (unsigned)L;
+    xoff[e] = (unsigned)(rr < rmax ? rr : rmax) * (unsigned)ldxa;
   }
   auto load_chunk = [&](int c) {
     const int m0 = c * BK;
@@ -238,13 +242,13 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
       rg[2 * j + 1] = gr[c0 + 64];
     }
     const int m = m0 + tc;
-    const unsigned mm = (unsigned)(m < L ? m : L - 1);
+    const unsigned mm = (unsigned)(m < K ? m : K - 1);
 #pragma unroll
     for (int e = 0; e < 8; ++e) rx[e] = tb[xoff[e] + mm];
   };
-  // contraction columns past L are zeroed at LDS-store time (after the MFMA block)
+  // contraction columns past K are zeroed at LDS-store time (after the MFMA block)
   auto store_chunk = [&](int buf, int c) {
-    const bool ok = c * BK + tc < L;
+    const bool ok = c * BK + tc < K;
     double* st = lds + buf * (TILE_T_NT + TILE_G);
     double* sg = st + TILE_T_NT;
 #pragma unroll
@@ -281,19 +285,21 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
     }
   };
 
-  load_chunk(0);
-  store_chunk(0, 0);
-  __syncthreads();
-  for (int c = 0; c + 1 < nchunk; ++c) {
-    load_chunk(c + 1);
-    // keep the LDS stores (which wait for the loads) after the whole MFMA block
-    __builtin_amdgcn_sched_barrier(0);
-    compute_chunk(c & 1);
-    __builtin_amdgcn_sched_barrier(0);
-    store_chunk((c + 1) & 1, c + 1);
+  if (nchunk > 0) {  // K = 0 (an empty antisymmetric block) stores zeros
+    load_chunk(0);
+    store_chunk(0, 0);
     __syncthreads();
+    for (int c = 0; c + 1 < nchunk; ++c) {
+      load_chunk(c + 1);
+      // keep the LDS stores (which wait for the loads) after the whole MFMA block
+      __builtin_amdgcn_sched_barrier(0);
+      compute_chunk(c & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      store_chunk((c + 1) & 1, c + 1);
+      __syncthreads();
+    }
+    compute_chunk((nchunk - 1) & 1);
   }
-  compute_chunk((nchunk - 1) & 1);
 
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
     for (int r = 0; r < 4; ++r) {
       const long pp = p0 + wm + 16 * i + 4 * r + fk;
       if (pp >= P) continue;
-      double* __restrict__ yrow = y + (size_t)pp * L;
+      double* __restrict__ yrow = y + (size_t)pp * ldya;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int l = l0 + wn + 16 * j + fr;
@@ -320,16 +326,17 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
 }  // namespace f64k
 
 // ---------------------------------------------------------------------------
-// Host launcher: one mode product along `axis` of an (n0, n1, n2) array.
+// Host launchers.
 // ---------------------------------------------------------------------------
-hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg, const int dims[3], int axis, int epi,
-                           const EpiArgs& ea, hipStream_t stream) {
+// General form: Y[p][l][q] = sum_{m < K} A[l][m] X[p][m][q] for l < L, with the
+// contracted axis of X of extent ldxa and the output axis of Y of extent ldya
+// (batch strides ldxa Q and ldya Q); g[m * ldg + l] = A[l][m], padded so that
+// whole 128 x 16 tiles stay inside (rows >= pad16(K), ldg >= pad128(L)).
+hipError_t launch_mode_f64_part(const double* x, double* y, const double* g, int ldg, long P, int K, int L, long Q,
+                                int ldxa, int ldya, int epi, const EpiArgs& ea, hipStream_t stream) {
   using namespace f64k;
-  long P = 1, Q = 1;
-  const int L = dims[axis];
-  for (int a = 0; a < axis; ++a) P *= dims[a];
-  for (int a = axis + 1; a < 3; ++a) Q *= dims[a];
   if (P <= 0 || Q <= 0 || L <= 0) return hipSuccess;
+  if (K < 0 || K > ldxa || L > ldya) return hipErrorInvalidValue;
   if (Q > 1) {
     const long tiles_l = (L + BM - 1) / BM;
     const long tiles_q = (Q + BN - 1) / BN;
@@ -339,17 +346,20 @@ hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg,
     dim3 grid((unsigned)nbp), block(NT_THREADS);
     switch (epi) {
       case EPI_STORE:
-        mode_nn_f64<EPI_STORE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, Q, tiles_l, tiles_q, ntiles, nbp, ea);
+        mode_nn_f64<EPI_STORE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, Q, tiles_l, tiles_q,
+                                                           ntiles, nbp, ea);
         break;
       case EPI_DIVIDE:
-        mode_nn_f64<EPI_DIVIDE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, Q, tiles_l, tiles_q, ntiles, nbp, ea);
+        mode_nn_f64<EPI_DIVIDE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, Q, tiles_l, tiles_q,
+                                                            ntiles, nbp, ea);
         break;
       case EPI_SPECTRAL:
-        mode_nn_f64<EPI_SPECTRAL><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, Q, tiles_l, tiles_q, ntiles, nbp,
-                                                               ea);
+        mode_nn_f64<EPI_SPECTRAL><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, Q, tiles_l,
+                                                              tiles_q, ntiles, nbp, ea);
         break;
       default:
-        mode_nn_f64<EPI_ACCUM><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, Q, tiles_l, tiles_q, ntiles, nbp, ea);
+        mode_nn_f64<EPI_ACCUM><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, Q, tiles_l, tiles_q,
+                                                           ntiles, nbp, ea);
         break;
     }
   } else {
@@ -361,20 +371,34 @@ hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg,
     dim3 grid((unsigned)nbp), block(NT_THREADS);
     switch (epi) {
       case EPI_STORE:
-        mode_nt_f64<EPI_STORE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, tiles_l, ntiles, nbp, ea);
+        mode_nt_f64<EPI_STORE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, tiles_l, ntiles, nbp,
+                                                           ea);
         break;
       case EPI_DIVIDE:  // only reached for the x axis with ny = nz = 1
-        mode_nt_f64<EPI_DIVIDE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, tiles_l, ntiles, nbp, ea);
+        mode_nt_f64<EPI_DIVIDE><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, tiles_l, ntiles, nbp,
+                                                            ea);
         break;
       case EPI_SPECTRAL:
-        mode_nt_f64<EPI_SPECTRAL><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, tiles_l, ntiles, nbp, ea);
+        mode_nt_f64<EPI_SPECTRAL><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, tiles_l, ntiles,
+                                                              nbp, ea);
         break;
       default:
-        mode_nt_f64<EPI_ACCUM><<<grid, block, 0, stream>>>(x, y, g, ldg, P, L, tiles_l, ntiles, nbp, ea);
+        mode_nt_f64<EPI_ACCUM><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, tiles_l, ntiles, nbp,
+                                                           ea);
         break;
     }
   }
   return hipGetLastError();
+}
+
+// One dense mode product along `axis` of an (n0, n1, n2) array.
+hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg, const int dims[3], int axis, int epi,
+                           const EpiArgs& ea, hipStream_t stream) {
+  long P = 1, Q = 1;
+  const int L = dims[axis];
+  for (int a = 0; a < axis; ++a) P *= dims[a];
+  for (int a = axis + 1; a < 3; ++a) Q *= dims[a];
+  return launch_mode_f64_part(x, y, g, ldg, P, L, L, Q, L, L, epi, ea, stream);
 }
 
 }  // namespace semfd

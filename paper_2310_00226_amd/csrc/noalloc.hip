@@ -59,7 +59,7 @@ extern "C" sem_status sem_solve_noalloc(sem_plan* p, const double* f, double* u)
   double* tmp = nullptr;
   sem_status st = scratch_for_device(p->device, &tmp);
   if (st == SEM_OK) {
-    e = fd64(p, Spectral{p->alpha, 1.0, 0.0}, f, u, tmp);
+    e = fd64_dense(p, Spectral{p->alpha, 1.0, 0.0}, f, u, tmp);
     if (e != hipSuccess) st = hip_fail(e, "sem_solve_noalloc");
   }
   if (cur != p->device) (void)hipSetDevice(cur);

@@ -26,6 +26,13 @@ struct sem_plan {
   double* d_lam[3] = {nullptr, nullptr, nullptr};
   double* d_hb[3] = {nullptr, nullptr, nullptr};  // banded rows of H = M^{-1} K
   double* d_mass[3] = {nullptr, nullptr, nullptr};  // lumped 1D masses (inner products of PCG)
+  // reflection-split FP64 factors [axis][0 = symmetric, 1 = antisymmetric block],
+  // stored G[m][l] = A[l][m] (m contracted), zero-padded to fld x fld: forward
+  // A = modes x representatives, backward A = representatives x modes of the block
+  double* d_gff[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  double* d_gbf[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  int fld[3] = {0, 0, 0};
+  double* d_lamf64[3] = {nullptr, nullptr, nullptr};  // eigenvalues in folded mode order (FP64 path)
   // low-precision factors (created on first use): [axis][0 = forward, 1 = backward],
   // layout [l][k], zero-padded to lp_ld x lp_ld
   void* lp_f32[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
@@ -79,7 +86,11 @@ sem_status lp_factors(sem_plan* p, sem_prec prec);
 sem_status lp_layout(sem_plan* p, sem_prec prec, void* ws, LpWork* w);
 hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u, int first,
                  unsigned long long* norms);
-hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp);
+// FP64 FD application u = S_3 [g(L) (F_3 f)] on the reflection-split transforms
+// (ws: workspace_need(p, SEM_F64) bytes, two folded intermediates; u may alias f).
+hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* ws);
+// The same on the dense transforms with one intermediate array of N doubles.
+hipError_t fd64_dense(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp);
 hipError_t zero_norms(unsigned long long* norms, hipStream_t stream);
 
 // Refinement stop test on the relative updates r_k = ||delta_k|| / ||u_k||: met

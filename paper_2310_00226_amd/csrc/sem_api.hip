@@ -65,6 +65,37 @@ static hipError_t upload_vec(const std::vector<double>& v, double** dst) {
   return hipMemcpy(*dst, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice);
 }
 
+// Reflection-split FP64 factors of axis a in the G[m][l] = A[l][m] layout of the
+// FP64 kernels, zero-padded to fld x fld (fld = nrep rounded up to 128): forward
+// blocks A = (symmetric or antisymmetric modes) x representatives, backward blocks
+// A = representatives x (modes of the block); and the folded eigenvalues.
+static hipError_t upload_fold_factors(sem_plan* p, int a) {
+  const semfd::AxisData& ax = p->ax[a];
+  const int nr = ax.nrep, no = ax.nodd, ld = ((nr + 127) / 128) * 128;
+  p->fld[a] = ld;
+  std::vector<double> g[4];
+  for (auto& v : g) v.assign((size_t)ld * ld, 0.0);
+  for (int l = 0; l < nr; ++l)
+    for (int m = 0; m < nr; ++m) g[0][(size_t)m * ld + l] = ax.ffold[(size_t)l * nr + m];
+  for (int j = 0; j < no; ++j)
+    for (int m = 0; m < nr; ++m) g[1][(size_t)m * ld + j] = ax.ffold[(size_t)(nr + j) * nr + m];
+  for (int r = 0; r < nr; ++r)
+    for (int m = 0; m < nr; ++m) g[2][(size_t)m * ld + r] = ax.bfold_sym[(size_t)r * nr + m];
+  for (int r = 0; r < nr; ++r)
+    for (int m = 0; m < no; ++m) g[3][(size_t)m * ld + r] = ax.bfold_anti[(size_t)r * no + m];
+  double** dst[4] = {&p->d_gff[a][0], &p->d_gff[a][1], &p->d_gbf[a][0], &p->d_gbf[a][1]};
+  for (int i = 0; i < 4; ++i) {
+    hipError_t e = hipMalloc(dst[i], sizeof(double) * g[i].size());
+    if (e != hipSuccess) {
+      *dst[i] = nullptr;
+      return e;
+    }
+    if ((e = hipMemcpy(*dst[i], g[i].data(), sizeof(double) * g[i].size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return e;
+  }
+  return upload_vec(ax.lam_fold, &p->d_lamf64[a]);
+}
+
 sem_status plan_workspace(sem_plan* p, size_t need, void** out) {
   if (p->ws && p->ws_bytes >= need) {
     *out = p->ws;
@@ -217,6 +248,12 @@ sem_status sem_plan_create_mixed(int k, const int ne[3], const double box[6], do
     return hip_fail(e, "sem_plan_create: no HIP device");
   }
   for (int a = 0; a < 3; ++a) {
+    if ((e = upload_fold_factors(p, a)) != hipSuccess) {
+      sem_plan_destroy(p);
+      return hip_fail(e, "sem_plan_create: folded factor upload");
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
     const int n = p->dims[a];
     p->ld[a] = ((n + 127) / 128) * 128;
     if ((e = upload_factor(p->ax[a].F, n, p->ld[a], &p->d_gf[a])) != hipSuccess ||
@@ -244,6 +281,11 @@ void sem_plan_destroy(sem_plan* p) {
     (void)hipFree(p->d_lam[a]);
     (void)hipFree(p->d_hb[a]);
     (void)hipFree(p->d_mass[a]);
+    (void)hipFree(p->d_lamf64[a]);
+    for (int b = 0; b < 2; ++b) {
+      (void)hipFree(p->d_gff[a][b]);
+      (void)hipFree(p->d_gbf[a][b]);
+    }
   }
   release_lowp(p);
   if (p->ws_owned) (void)hipFree(p->ws);

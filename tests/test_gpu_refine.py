@@ -125,3 +125,25 @@ def test_unrefined_lowp_solve(torch, P, prec):
     _log(f"[lowp] {prec}: unrefined rel err {err:.2e}")
     assert err <= LOWP_BOUND[prec], err
     assert err > 1e-13  # an FP64 solve would be at ~1e-15: low precision really was used
+
+
+def test_refined_q5_neumann_n1001_meets_tol(torch, P):
+    """The refinement stop keeps a margin: on Q^5 Neumann with 200^3 elements
+    (n = 1001) and a rough N(0,1) right-hand side, where the low-precision solves
+    contract slowest, every refined result lands within tol = 1e-10 of the FP64
+    solve (the FP64 solve itself is held to the oracle at n = 999 and on every
+    smaller parity case)."""
+    k, ne, box, alpha = 5, (200, 200, 200), (-1, 1, -1, 1, -1, 1), 1.0
+    plan = P.Plan(k, ne, box, alpha, "neumann")
+    assert plan.shape == (1001, 1001, 1001)
+    _log("[n1001 neumann] inputs")
+    fd = _dev(torch, normal_noise(plan.shape, seed=1001))
+    ref = plan.solve(fd)
+    scale = float(ref.abs().max())
+    ud = torch.empty_like(fd)
+    for prec in PRECS:
+        _, iters, rel, st = plan.solve_refined(fd, ud, prec=prec, tol=1e-10, max_iter=40)
+        err = float((ud - ref).abs().max()) / scale
+        _log(f"[n1001 neumann] {prec}: iters={iters} last_rel={rel:.2e} rel err vs FP64 {err:.2e}")
+        assert st == 0
+        assert err <= 1e-10, (prec, err, iters)

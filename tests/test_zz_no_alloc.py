@@ -1,7 +1,9 @@
-"""sem_solve_noalloc (the FP64 solve with the library's fixed scratch array)
-against sem_solve: same kernels, so the results must be equal bit for bit, on
-two calls in a row, the second with a smaller problem; sizes beyond the fixed
-array are rejected; and no device allocation happens during the calls."""
+"""sem_solve_noalloc (the FP64 solve on the dense transforms with the library's
+fixed scratch array) against sem_solve (the reflection-split transforms): the
+same solve up to rounding, held to the FP64 parity bar 1e-12 relative, on two
+calls in a row, the second with a smaller problem; an in-place call repeats the
+first bit for bit; sizes beyond the fixed array are rejected; and no device
+allocation happens during the calls."""
 import sys
 
 import numpy as np
@@ -10,6 +12,11 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 MAX_UNKNOWNS = 8 * 1024 * 1024  # SEM_NOALLOC_MAX_UNKNOWNS
+TOL = 1e-12  # relative max error, the FP64 parity bar
+
+
+def _close(u, ref):
+    return float((u - ref).abs().max()) <= TOL * float(ref.abs().max())
 
 
 def _log(msg):
@@ -51,12 +58,12 @@ def test_noalloc_equals_solve_two_calls(P, torch):
         plan.solve_noalloc(f, u)
         torch.cuda.synchronize()
         assert torch.cuda.memory_allocated() == alloc0  # nothing through torch
-        assert torch.equal(u, ref), float((u - ref).abs().max())
-        # in place (u aliases f), as sem_solve allows
+        assert _close(u, ref), float((u - ref).abs().max())
+        # in place (u aliases f), as sem_solve allows: the same path, the same bits
         g = f.clone()
         plan.solve_noalloc(g, g)
         torch.cuda.synchronize()
-        assert torch.equal(g, ref)
+        assert torch.equal(g, u)
         del before
 
 
@@ -74,4 +81,4 @@ def test_noalloc_rejects_too_large(P, torch):
     ref = plan2.solve(f2)
     u = plan2.solve_noalloc(f2)
     torch.cuda.synchronize()
-    assert torch.equal(u, ref)
+    assert _close(u, ref)
