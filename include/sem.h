@@ -114,15 +114,16 @@ sem_status sem_plan_set_workspace(sem_plan *p, void *dev_ptr, size_t bytes);
  * 1D operators, so the eigenvectors are symmetric or antisymmetric: every
  * product runs as two half-size blocks on the folded vector (v_r + v_R(r),
  * v_r - v_R(r) over the orbit representatives r), half the flops of the dense
- * products, with fold and unfold passes between them.  f and u are device arrays
- * of n_x n_y n_z doubles; u may alias f. */
+ * products; the forward blocks fold while they load, the backward blocks unfold
+ * while they store.  Workspace: N doubles.  f and u are device arrays of
+ * n_x n_y n_z doubles; u may alias f. */
 sem_status sem_solve(sem_plan *p, const double *f, double *u);
 
 /* For callers that cannot allocate device memory (code under HIP stream
- * capture, tight serving loops, allocation-free harnesses): the FP64 solve on the
- * dense transforms (six full mode products, the same result as sem_solve to
- * rounding), with its one intermediate array of N doubles in a fixed device array
- * inside this library instead of the plan workspace.  Allocates nothing (no hipMalloc / hipFree, no library
+ * capture, tight serving loops, allocation-free harnesses): the solve of
+ * sem_solve, same kernels and same result bit for bit, with its intermediate
+ * array of N doubles in a fixed device array inside this library instead of the
+ * plan workspace.  Allocates nothing (no hipMalloc / hipFree, no library
  * allocation); the first call on a device looks up that device's copy of the
  * array, which the device holds until the process ends (SEM_NOALLOC_MAX_UNKNOWNS
  * doubles, 64 MiB).  Every call on one device shares that array: calls that

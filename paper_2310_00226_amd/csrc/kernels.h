@@ -8,7 +8,11 @@
 namespace semfd {
 
 // EPI_SPECTRAL (FP64 kernels only): another multiplier than the divide (EpiArgs::kind)
-enum { EPI_STORE = 0, EPI_DIVIDE = 1, EPI_ACCUM = 2, EPI_SPECTRAL = 3 };
+// EPI_UNFOLD (FP64 kernels only): the output rows (NN) or columns (NT) are orbit
+// representatives r of the output axis (EpiArgs::rn, rper) and the product is the
+// antisymmetric part o: out[r] = e + o, out[R(r)] = e - o with e = out[r] as stored
+// by the symmetric block before (R(r) == r: out[r] only)
+enum { EPI_STORE = 0, EPI_DIVIDE = 1, EPI_ACCUM = 2, EPI_SPECTRAL = 3, EPI_UNFOLD = 4 };
 
 // Arguments of the fused epilogues.
 //   EPI_DIVIDE: out = acc / (alpha + b1 L + b2 L^2),  L = lx[row] + ly[col / nz] + lz[col % nz]
@@ -26,8 +30,16 @@ struct EpiArgs {
   // alpha + b1 L + b2 L^2
   int kind = 0;
   double param = 0.0;
+  // reflection split (FP64 kernels): fold = 1 / 2 reads the contracted axis (of
+  // extent rn, periodic rper, x unfolded) as v+_m = x_m + x_R(m) / v-_m = x_m - x_R(m)
+  // for m < K; EPI_UNFOLD reflects the output axis (extent rn, periodic rper)
+  int fold = 0;
+  int rn = 0, rper = 0;
 };
 constexpr int SPECTRAL_EXP = 1, SPECTRAL_POWER = 2;
+
+// Reflection of node r on an axis of n nodes: n - 1 - r, or (n - r) mod n periodic.
+__host__ __device__ inline int reflect_node(int r, int n, int per) { return per ? (n - r) % n : n - 1 - r; }
 
 // Denominator of the spectral divide, FP64.
 __host__ __device__ inline double spectral_den(double lam, double alpha, double b1, double b2) {
@@ -48,11 +60,9 @@ hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg,
 // General block form: Y[p][l][q] = sum_{m < K} A[l][m] X[p][m][q] for l < L, the
 // contracted axis of X of extent ldxa, the output axis of Y of extent ldya (batch
 // strides ldxa Q, ldya Q); g rows >= pad16(K), ldg >= pad128(L).  K = 0 stores zeros.
+// ea.fold reads X as the v+ / v- of its unfolded axis; EPI_UNFOLD writes e +- o.
 hipError_t launch_mode_f64_part(const double* x, double* y, const double* g, int ldg, long P, int K, int L, long Q,
                                 int ldxa, int ldya, int epi, const EpiArgs& ea, hipStream_t stream);
-// Reflection fold (unfold = 0) or unfold (1) of X[p][i][q] along i (fold_f64.hip).
-hipError_t launch_fold_f64(const double* x, double* y, long P, int n, long Q, int nrep, int per, int unfold,
-                           hipStream_t stream);
 
 // ---- low-precision rotating mode products (mode_lp.hip) ----
 enum { LP_F32 = 1, LP_BF16 = 2, LP_BF16X3 = 3 };

@@ -97,9 +97,17 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
       rg[2 * j] = gr[c0];
       rg[2 * j + 1] = gr[c0 + 64];
       const int m = m0 + r0 + 4 * j;
-      const double* __restrict__ xr = xp + (size_t)(m < K ? m : K - 1) * Q;
-      rx[2 * j] = xr[qa];
-      rx[2 * j + 1] = xr[qb];
+      const int mc = m < K ? m : K - 1;
+      const double* __restrict__ xr = xp + (size_t)mc * Q;
+      if (epi.fold) {  // uniform: v+ or v- of the unfolded axis
+        const double* __restrict__ xm = xp + (size_t)reflect_node(mc, epi.rn, epi.rper) * Q;
+        const double a0 = xr[qa], a1 = xr[qb], b0 = xm[qa], b1 = xm[qb];
+        rx[2 * j] = epi.fold == 1 ? a0 + b0 : a0 - b0;
+        rx[2 * j + 1] = epi.fold == 1 ? a1 + b1 : a1 - b1;
+      } else {
+        rx[2 * j] = xr[qa];
+        rx[2 * j + 1] = xr[qb];
+      }
     }
   };
   // the zeroing of rows past K happens here, after the MFMA block, so that no wait
@@ -180,6 +188,9 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
       if (l >= L) continue;
       double* __restrict__ yrow = yp + (size_t)l * Q;
       const double lxl = (EPI == EPI_DIVIDE || EPI == EPI_SPECTRAL) ? epi.lx[l] : 0.0;
+      // EPI_UNFOLD: row l is representative l; its reflected row takes e - o
+      const int lm = EPI == EPI_UNFOLD ? reflect_node(l, epi.rn, epi.rper) : l;
+      double* __restrict__ ymrow = yp + (size_t)lm * Q;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const long q = q0 + wn + 16 * j + fr;
@@ -188,7 +199,11 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
         if constexpr (EPI == EPI_STORE) yrow[q] = v;
         else if constexpr (EPI == EPI_DIVIDE) yrow[q] = v / spectral_den(lxl + cden[j], epi.alpha, epi.b1, epi.b2);
         else if constexpr (EPI == EPI_SPECTRAL) yrow[q] = spectral_mul(v, lxl + cden[j], epi);
-        else yrow[q] += v;
+        else if constexpr (EPI == EPI_UNFOLD) {
+          const double e = yrow[q];
+          yrow[q] = e + v;
+          if (lm != l) ymrow[q] = e - v;
+        } else yrow[q] += v;
       }
     }
 }
@@ -243,8 +258,17 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
     }
     const int m = m0 + tc;
     const unsigned mm = (unsigned)(m < K ? m : K - 1);
+    if (epi.fold) {  // uniform: v+ or v- of the unfolded axis
+      const unsigned mr = (unsigned)reflect_node((int)mm, epi.rn, epi.rper);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) rx[e] = tb[xoff[e] + mm];
+      for (int e = 0; e < 8; ++e) {
+        const double a = tb[xoff[e] + mm], b = tb[xoff[e] + mr];
+        rx[e] = epi.fold == 1 ? a + b : a - b;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rx[e] = tb[xoff[e] + mm];
+    }
   };
   // contraction columns past K are zeroed at LDS-store time (after the MFMA block)
   auto store_chunk = [&](int buf, int c) {
@@ -318,7 +342,12 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
           yrow[l] = v / spectral_den(epi.lx[l] + epi.ly[0] + epi.lz[0], epi.alpha, epi.b1, epi.b2);
         else if constexpr (EPI == EPI_SPECTRAL)
           yrow[l] = spectral_mul(v, epi.lx[l] + epi.ly[0] + epi.lz[0], epi);
-        else yrow[l] += v;
+        else if constexpr (EPI == EPI_UNFOLD) {  // column l is representative l
+          const int lm = reflect_node(l, epi.rn, epi.rper);
+          const double e = yrow[l];
+          yrow[l] = e + v;
+          if (lm != l) yrow[lm] = e - v;
+        } else yrow[l] += v;
       }
     }
 }
@@ -357,6 +386,10 @@ hipError_t launch_mode_f64_part(const double* x, double* y, const double* g, int
         mode_nn_f64<EPI_SPECTRAL><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, Q, tiles_l,
                                                               tiles_q, ntiles, nbp, ea);
         break;
+      case EPI_UNFOLD:
+        mode_nn_f64<EPI_UNFOLD><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, Q, tiles_l, tiles_q,
+                                                            ntiles, nbp, ea);
+        break;
       default:
         mode_nn_f64<EPI_ACCUM><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, Q, tiles_l, tiles_q,
                                                            ntiles, nbp, ea);
@@ -381,6 +414,10 @@ hipError_t launch_mode_f64_part(const double* x, double* y, const double* g, int
       case EPI_SPECTRAL:
         mode_nt_f64<EPI_SPECTRAL><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, tiles_l, ntiles,
                                                               nbp, ea);
+        break;
+      case EPI_UNFOLD:
+        mode_nt_f64<EPI_UNFOLD><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, tiles_l, ntiles, nbp,
+                                                            ea);
         break;
       default:
         mode_nt_f64<EPI_ACCUM><<<grid, block, 0, stream>>>(x, y, g, ldg, P, K, L, ldxa, ldya, tiles_l, ntiles, nbp,

@@ -2,7 +2,7 @@
 //
 // sem_solve keeps its one intermediate array (N doubles between the mode
 // products) in the plan workspace, which it allocates on first use unless the
-// caller installed one.  sem_solve_noalloc runs the same six passes with that
+// caller installed one.  sem_solve_noalloc runs the same mode products with that
 // array in a fixed device array of this library instead, so that callers that
 // cannot allocate (code under stream capture, tight serving loops, allocation-
 // free harnesses) can solve without any hipMalloc.  Each device that runs it
@@ -59,7 +59,7 @@ extern "C" sem_status sem_solve_noalloc(sem_plan* p, const double* f, double* u)
   double* tmp = nullptr;
   sem_status st = scratch_for_device(p->device, &tmp);
   if (st == SEM_OK) {
-    e = fd64_dense(p, Spectral{p->alpha, 1.0, 0.0}, f, u, tmp);
+    e = fd64(p, Spectral{p->alpha, 1.0, 0.0}, f, u, tmp);
     if (e != hipSuccess) st = hip_fail(e, "sem_solve_noalloc");
   }
   if (cur != p->device) (void)hipSetDevice(cur);

@@ -87,10 +87,8 @@ sem_status lp_layout(sem_plan* p, sem_prec prec, void* ws, LpWork* w);
 hipError_t lp_fd(sem_plan* p, const LpWork& w, const Spectral& sp, const double* f64_src, double* u, int first,
                  unsigned long long* norms);
 // FP64 FD application u = S_3 [g(L) (F_3 f)] on the reflection-split transforms
-// (ws: workspace_need(p, SEM_F64) bytes, two folded intermediates; u may alias f).
-hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* ws);
-// The same on the dense transforms with one intermediate array of N doubles.
-hipError_t fd64_dense(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp);
+// (tmp: N doubles; u may alias f).
+hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp);
 hipError_t zero_norms(unsigned long long* norms, hipStream_t stream);
 
 // Refinement stop test on the relative updates r_k = ||delta_k|| / ||u_k||: met

@@ -103,18 +103,11 @@ __global__ void zero_u64_kernel(unsigned long long* p, int n) {
 
 }  // namespace
 
-// FP64 path: a folded intermediate (one axis at 2 nrep) and one of N doubles.
-static size_t fold64_elems(const sem_plan* p) {
-  const size_t nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
-  const size_t rx = 2 * (size_t)p->ax[0].nrep, ry = 2 * (size_t)p->ax[1].nrep, rz = 2 * (size_t)p->ax[2].nrep;
-  return std::max({nx * ny * rz, nx * ry * nz, rx * ny * nz});
-}
-
 size_t workspace_need(const sem_plan* p, sem_prec prec) {
   const size_t n = p->N;
   switch (prec) {
     case SEM_F64:
-      return ((fold64_elems(p) * sizeof(double) + 255) / 256) * 256 + ((n * sizeof(double) + 255) / 256) * 256;
+      return ((n * sizeof(double) + 255) / 256) * 256;
     case SEM_F32:
     case SEM_BF16:
     case SEM_BF16X3: {
@@ -554,24 +547,32 @@ sem_status lp_tune(sem_plan* p, const LpWork& w) {
 }
 
 // FP64 FD application on the reflection-split transforms (the plan's folded
-// blocks): fold z, z forward (two blocks), fold y, y forward, fold x, x forward +
-// multiplier, x backward to the folded node form, unfold x, y backward, unfold y,
-// z backward, unfold z into u.  Each forward block contracts the nrep
-// representatives of v+ (symmetric modes) or v- (antisymmetric modes); each
-// backward block writes e (from the symmetric modes) or o (antisymmetric) of the
-// node form, and u_r = e_r + o_r, u_R(r) = e_r - o_r.  Modes stay in folded order
-// ([symmetric | antisymmetric]) between the passes, so the multiplier reads the
-// folded eigenvalues.  A: folded intermediate, B: N doubles.
-hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* ws) {
-  double* A = ws;
-  double* B = ws + ((fold64_elems(p) * sizeof(double) + 255) / 256) * 256 / sizeof(double);
+// blocks), two launches per mode product:
+//  - forward (z, y, x): each block reads the unfolded axis as v+ = x_r + x_R(r)
+//    (symmetric modes) or v- = x_r - x_R(r) (antisymmetric modes) for the nrep
+//    representatives r, and writes its modes, in folded order ([symmetric |
+//    antisymmetric]), so the x product's multiplier reads the folded eigenvalues;
+//  - backward (x, y, z): the symmetric block stores e_r at node r, the
+//    antisymmetric block reads it back and stores u_r = e_r + o_r and
+//    u_R(r) = e_r - o_r.
+// Buffers: f -> tmp -> u -> tmp -> u -> tmp -> u (tmp: N doubles; u may alias f,
+// which is read by the first product only).
+hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp) {
   const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
   const int r[3] = {p->ax[0].nrep, p->ax[1].nrep, p->ax[2].nrep};
   const int o[3] = {p->ax[0].nodd, p->ax[1].nodd, p->ax[2].nodd};
-  const int per[3] = {p->bc[0] == SEM_BC_PERIODIC, p->bc[1] == SEM_BC_PERIODIC, p->bc[2] == SEM_BC_PERIODIC};
+  const int n[3] = {nx, ny, nz};
   const long PZ = (long)nx * ny, QY = nz, PY = nx, QX = (long)ny * nz;
+  EpiArgs plus[3], minus[3], unfold[3];
+  for (int a = 0; a < 3; ++a) {
+    const int per = p->bc[a] == SEM_BC_PERIODIC ? 1 : 0;
+    plus[a].fold = 1;
+    minus[a].fold = 2;
+    plus[a].rn = minus[a].rn = unfold[a].rn = n[a];
+    plus[a].rper = minus[a].rper = unfold[a].rper = per;
+  }
   EpiArgs none;
-  EpiArgs mul;
+  EpiArgs mul = plus[0];
   mul.lx = p->d_lamf64[0];
   mul.ly = p->d_lamf64[1];
   mul.lz = p->d_lamf64[2];
@@ -582,71 +583,38 @@ hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, dou
   mul.param = sp.param;
   mul.nz = nz;
   EpiArgs mul_anti = mul;
+  mul_anti.fold = 2;
   mul_anti.lx = p->d_lamf64[0] + r[0];
   const int epi = sp.kind ? EPI_SPECTRAL : EPI_DIVIDE;
   hipStream_t s = p->stream;
   hipError_t e;
 #define SEMFD_TRY(x) \
   if ((e = (x)) != hipSuccess) return e
-  // z: fold, forward blocks (NT shape, rows (x, y))
-  SEMFD_TRY(launch_fold_f64(f, A, PZ, nz, 1, r[2], per[2], 0, s));
-  SEMFD_TRY(launch_mode_f64_part(A, B, p->d_gff[2][0], p->fld[2], PZ, r[2], r[2], 1, 2 * r[2], nz, EPI_STORE, none, s));
-  SEMFD_TRY(launch_mode_f64_part(A + r[2], B + r[2], p->d_gff[2][1], p->fld[2], PZ, r[2], o[2], 1, 2 * r[2], nz,
-                                 EPI_STORE, none, s));
-  // y: fold, forward blocks (batched over x, inner z modes)
-  SEMFD_TRY(launch_fold_f64(B, A, PY, ny, QY, r[1], per[1], 0, s));
-  SEMFD_TRY(
-      launch_mode_f64_part(A, B, p->d_gff[1][0], p->fld[1], PY, r[1], r[1], QY, 2 * r[1], ny, EPI_STORE, none, s));
-  SEMFD_TRY(launch_mode_f64_part(A + (size_t)r[1] * QY, B + (size_t)r[1] * QY, p->d_gff[1][1], p->fld[1], PY, r[1],
-                                 o[1], QY, 2 * r[1], ny, EPI_STORE, none, s));
-  // x: fold, forward blocks with the multiplier (x modes, then (y, z) modes)
-  SEMFD_TRY(launch_fold_f64(B, A, 1, nx, QX, r[0], per[0], 0, s));
-  SEMFD_TRY(launch_mode_f64_part(A, B, p->d_gff[0][0], p->fld[0], 1, r[0], r[0], QX, 2 * r[0], nx, epi, mul, s));
-  SEMFD_TRY(launch_mode_f64_part(A + (size_t)r[0] * QX, B + (size_t)r[0] * QX, p->d_gff[0][1], p->fld[0], 1, r[0],
-                                 o[0], QX, 2 * r[0], nx, epi, mul_anti, s));
-  // x backward to (e | o), unfold
-  SEMFD_TRY(launch_mode_f64_part(B, A, p->d_gbf[0][0], p->fld[0], 1, r[0], r[0], QX, nx, 2 * r[0], EPI_STORE, none, s));
-  SEMFD_TRY(launch_mode_f64_part(B + (size_t)r[0] * QX, A + (size_t)r[0] * QX, p->d_gbf[0][1], p->fld[0], 1, o[0],
-                                 r[0], QX, nx, 2 * r[0], EPI_STORE, none, s));
-  SEMFD_TRY(launch_fold_f64(A, B, 1, nx, QX, r[0], per[0], 1, s));
-  // y backward, unfold
-  SEMFD_TRY(
-      launch_mode_f64_part(B, A, p->d_gbf[1][0], p->fld[1], PY, r[1], r[1], QY, ny, 2 * r[1], EPI_STORE, none, s));
-  SEMFD_TRY(launch_mode_f64_part(B + (size_t)r[1] * QY, A + (size_t)r[1] * QY, p->d_gbf[1][1], p->fld[1], PY, o[1],
-                                 r[1], QY, ny, 2 * r[1], EPI_STORE, none, s));
-  SEMFD_TRY(launch_fold_f64(A, B, PY, ny, QY, r[1], per[1], 1, s));
-  // z backward, unfold into u
-  SEMFD_TRY(launch_mode_f64_part(B, A, p->d_gbf[2][0], p->fld[2], PZ, r[2], r[2], 1, nz, 2 * r[2], EPI_STORE, none, s));
-  SEMFD_TRY(launch_mode_f64_part(B + r[2], A + r[2], p->d_gbf[2][1], p->fld[2], PZ, o[2], r[2], 1, nz, 2 * r[2],
-                                 EPI_STORE, none, s));
-  SEMFD_TRY(launch_fold_f64(A, u, PZ, nz, 1, r[2], per[2], 1, s));
+  // z forward (NT shape, rows (x, y)): f -> tmp (z modes)
+  SEMFD_TRY(launch_mode_f64_part(f, tmp, p->d_gff[2][0], p->fld[2], PZ, r[2], r[2], 1, nz, nz, EPI_STORE, plus[2], s));
+  SEMFD_TRY(launch_mode_f64_part(f, tmp + r[2], p->d_gff[2][1], p->fld[2], PZ, r[2], o[2], 1, nz, nz, EPI_STORE,
+                                 minus[2], s));
+  // y forward (batched over x, inner z modes): tmp -> u
+  SEMFD_TRY(launch_mode_f64_part(tmp, u, p->d_gff[1][0], p->fld[1], PY, r[1], r[1], QY, ny, ny, EPI_STORE, plus[1], s));
+  SEMFD_TRY(launch_mode_f64_part(tmp, u + (size_t)r[1] * QY, p->d_gff[1][1], p->fld[1], PY, r[1], o[1], QY, ny, ny,
+                                 EPI_STORE, minus[1], s));
+  // x forward with the multiplier: u -> tmp
+  SEMFD_TRY(launch_mode_f64_part(u, tmp, p->d_gff[0][0], p->fld[0], 1, r[0], r[0], QX, nx, nx, epi, mul, s));
+  SEMFD_TRY(launch_mode_f64_part(u, tmp + (size_t)r[0] * QX, p->d_gff[0][1], p->fld[0], 1, r[0], o[0], QX, nx, nx,
+                                 epi, mul_anti, s));
+  // x backward: tmp (x modes) -> u (x nodes)
+  SEMFD_TRY(launch_mode_f64_part(tmp, u, p->d_gbf[0][0], p->fld[0], 1, r[0], r[0], QX, nx, nx, EPI_STORE, none, s));
+  SEMFD_TRY(launch_mode_f64_part(tmp + (size_t)r[0] * QX, u, p->d_gbf[0][1], p->fld[0], 1, o[0], r[0], QX, nx, nx,
+                                 EPI_UNFOLD, unfold[0], s));
+  // y backward: u -> tmp
+  SEMFD_TRY(launch_mode_f64_part(u, tmp, p->d_gbf[1][0], p->fld[1], PY, r[1], r[1], QY, ny, ny, EPI_STORE, none, s));
+  SEMFD_TRY(launch_mode_f64_part(u + (size_t)r[1] * QY, tmp, p->d_gbf[1][1], p->fld[1], PY, o[1], r[1], QY, ny, ny,
+                                 EPI_UNFOLD, unfold[1], s));
+  // z backward: tmp -> u
+  SEMFD_TRY(launch_mode_f64_part(tmp, u, p->d_gbf[2][0], p->fld[2], PZ, r[2], r[2], 1, nz, nz, EPI_STORE, none, s));
+  SEMFD_TRY(launch_mode_f64_part(tmp + r[2], u, p->d_gbf[2][1], p->fld[2], PZ, o[2], r[2], 1, nz, nz, EPI_UNFOLD,
+                                 unfold[2], s));
 #undef SEMFD_TRY
-  return hipSuccess;
-}
-
-// FP64 FD application u = S_3 [ (F_3 f) / (alpha + b1 L + b2 L^2) ] on the dense
-// transforms; tmp holds N doubles (the entry point that allocates nothing).
-hipError_t fd64_dense(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp) {
-  EpiArgs none;
-  EpiArgs div;
-  div.lx = p->d_lam[0];
-  div.ly = p->d_lam[1];
-  div.lz = p->d_lam[2];
-  div.alpha = sp.alpha;
-  div.b1 = sp.b1;
-  div.b2 = sp.b2;
-  div.kind = sp.kind;
-  div.param = sp.param;
-  div.nz = p->dims[2];
-  hipError_t e;
-  if ((e = launch_mode_f64(f, tmp, p->d_gf[2], p->ld[2], p->dims, 2, EPI_STORE, none, p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(tmp, u, p->d_gf[1], p->ld[1], p->dims, 1, EPI_STORE, none, p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(u, tmp, p->d_gf[0], p->ld[0], p->dims, 0, sp.kind ? EPI_SPECTRAL : EPI_DIVIDE, div,
-                           p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(tmp, u, p->d_gb[2], p->ld[2], p->dims, 2, EPI_STORE, none, p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(u, tmp, p->d_gb[1], p->ld[1], p->dims, 1, EPI_STORE, none, p->stream)) != hipSuccess ||
-      (e = launch_mode_f64(tmp, u, p->d_gb[0], p->ld[0], p->dims, 0, EPI_STORE, none, p->stream)) != hipSuccess)
-    return e;
   return hipSuccess;
 }
 
