@@ -31,10 +31,11 @@ struct EpiArgs {
   int kind = 0;
   double param = 0.0;
   // reflection split (FP64 kernels): fold = 1 / 2 reads the contracted axis (of
-  // extent rn, periodic rper, x unfolded) as v+_m = x_m + x_R(m) / v-_m = x_m - x_R(m)
-  // for m < K; EPI_UNFOLD reflects the output axis (extent rn, periodic rper)
+  // extent rn, periodic rper, x unfolded) as v+_r = x_r + x_R(r) / v-_r = x_r - x_R(r)
+  // with r = m + roff for m < K; EPI_UNFOLD reflects the output axis (extent rn,
+  // periodic rper) with output row / column l at representative r = l + roff
   int fold = 0;
-  int rn = 0, rper = 0;
+  int rn = 0, rper = 0, roff = 0;
 };
 constexpr int SPECTRAL_EXP = 1, SPECTRAL_POWER = 2;
 
@@ -63,6 +64,11 @@ hipError_t launch_mode_f64(const double* x, double* y, const double* g, int ldg,
 // ea.fold reads X as the v+ / v- of its unfolded axis; EPI_UNFOLD writes e +- o.
 hipError_t launch_mode_f64_part(const double* x, double* y, const double* g, int ldg, long P, int K, int L, long Q,
                                 int ldxa, int ldya, int epi, const EpiArgs& ea, hipStream_t stream);
+// Compact reflection fold of X[p][i][q] along i (n nodes): Y[p][r] = X[p][r] + X[p][R(r)]
+// for the nrep representatives, then Y[p][nrep + j] = X[p][r] - X[p][R(r)] for the
+// n - nrep representatives r = j + off that are not their own reflection
+// (off = 1 periodic, 0 otherwise): Y has n rows like X.
+hipError_t launch_fold_f64(const double* x, double* y, long P, int n, long Q, int nrep, int per, hipStream_t stream);
 
 // ---- low-precision rotating mode products (mode_lp.hip) ----
 enum { LP_F32 = 1, LP_BF16 = 2, LP_BF16X3 = 3 };

@@ -98,9 +98,11 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
       rg[2 * j + 1] = gr[c0 + 64];
       const int m = m0 + r0 + 4 * j;
       const int mc = m < K ? m : K - 1;
-      const double* __restrict__ xr = xp + (size_t)mc * Q;
-      if (epi.fold) {  // uniform: v+ or v- of the unfolded axis
-        const double* __restrict__ xm = xp + (size_t)reflect_node(mc, epi.rn, epi.rper) * Q;
+      const double* __restrict__ xr = xp + (size_t)mc * Q;  // (K >= 1 when loading)
+      if (epi.fold) {  // uniform: v+ or v- of the unfolded axis at representative mc + roff
+        const int rr = mc + epi.roff;
+        xr = xp + (size_t)rr * Q;
+        const double* __restrict__ xm = xp + (size_t)reflect_node(rr, epi.rn, epi.rper) * Q;
         const double a0 = xr[qa], a1 = xr[qb], b0 = xm[qa], b1 = xm[qb];
         rx[2 * j] = epi.fold == 1 ? a0 + b0 : a0 - b0;
         rx[2 * j + 1] = epi.fold == 1 ? a1 + b1 : a1 - b1;
@@ -186,11 +188,13 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
     for (int r = 0; r < 4; ++r) {
       const int l = l0 + wm + 16 * i + 4 * r + fk;
       if (l >= L) continue;
-      double* __restrict__ yrow = yp + (size_t)l * Q;
-      const double lxl = (EPI == EPI_DIVIDE || EPI == EPI_SPECTRAL) ? epi.lx[l] : 0.0;
-      // EPI_UNFOLD: row l is representative l; its reflected row takes e - o
-      const int lm = EPI == EPI_UNFOLD ? reflect_node(l, epi.rn, epi.rper) : l;
+      // EPI_UNFOLD: row l holds o of representative lr = l + roff, whose reflected
+      // row takes e - o
+      const int lr = EPI == EPI_UNFOLD ? l + epi.roff : l;
+      const int lm = EPI == EPI_UNFOLD ? reflect_node(lr, epi.rn, epi.rper) : l;
+      double* __restrict__ yrow = yp + (size_t)lr * Q;
       double* __restrict__ ymrow = yp + (size_t)lm * Q;
+      const double lxl = (EPI == EPI_DIVIDE || EPI == EPI_SPECTRAL) ? epi.lx[l] : 0.0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const long q = q0 + wn + 16 * j + fr;
@@ -202,7 +206,7 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nn_f64(const double* __res
         else if constexpr (EPI == EPI_UNFOLD) {
           const double e = yrow[q];
           yrow[q] = e + v;
-          if (lm != l) ymrow[q] = e - v;
+          if (lm != lr) ymrow[q] = e - v;
         } else yrow[q] += v;
       }
     }
@@ -258,11 +262,12 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
     }
     const int m = m0 + tc;
     const unsigned mm = (unsigned)(m < K ? m : K - 1);
-    if (epi.fold) {  // uniform: v+ or v- of the unfolded axis
-      const unsigned mr = (unsigned)reflect_node((int)mm, epi.rn, epi.rper);
+    if (epi.fold) {  // uniform: v+ or v- of the unfolded axis at representative mm + roff
+      const unsigned ma = mm + (unsigned)epi.roff;
+      const unsigned mr = (unsigned)reflect_node((int)ma, epi.rn, epi.rper);
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const double a = tb[xoff[e] + mm], b = tb[xoff[e] + mr];
+        const double a = tb[xoff[e] + ma], b = tb[xoff[e] + mr];
         rx[e] = epi.fold == 1 ? a + b : a - b;
       }
     } else {
@@ -342,14 +347,75 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
           yrow[l] = v / spectral_den(epi.lx[l] + epi.ly[0] + epi.lz[0], epi.alpha, epi.b1, epi.b2);
         else if constexpr (EPI == EPI_SPECTRAL)
           yrow[l] = spectral_mul(v, epi.lx[l] + epi.ly[0] + epi.lz[0], epi);
-        else if constexpr (EPI == EPI_UNFOLD) {  // column l is representative l
-          const int lm = reflect_node(l, epi.rn, epi.rper);
-          const double e = yrow[l];
-          yrow[l] = e + v;
-          if (lm != l) yrow[lm] = e - v;
+        else if constexpr (EPI == EPI_UNFOLD) {  // column l holds o of representative l + roff
+          const int lr = l + epi.roff, lm = reflect_node(lr, epi.rn, epi.rper);
+          const double e = yrow[lr];
+          yrow[lr] = e + v;
+          if (lm != lr) yrow[lm] = e - v;
         } else yrow[l] += v;
       }
     }
+}
+
+// Compact reflection fold (see launch_fold_f64): blocks stride over rows, (p, s)
+// when Q > 1 (threads over q), p when Q == 1 (threads over s); output row s < nrep
+// is v+ of representative s, row nrep + j is v- of representative j + off.
+constexpr int FT = 256, FU = 4;
+__global__ __launch_bounds__(FT) void fold_f64_kernel(const double* __restrict__ x, double* __restrict__ y, long P,
+                                                      int n, long Q, int nrep, int per) {
+  const int off = per ? 1 : 0;
+  auto src = [&](int s, int& a, int& b, bool& minus) {  // output row s <- rows a +- b
+    minus = s >= nrep;
+    a = minus ? s - nrep + off : s;
+    b = reflect_node(a, n, per);
+  };
+  if (Q > 1) {
+    const long rows = P * n;
+    for (long row = blockIdx.x; row < rows; row += gridDim.x) {
+      const long p = row / n;
+      const int s = (int)(row - p * n);
+      int a, b;
+      bool minus;
+      src(s, a, b, minus);
+      const double* __restrict__ xa = x + (size_t)(p * n + a) * Q;
+      const double* __restrict__ xb = x + (size_t)(p * n + b) * Q;
+      double* __restrict__ ys = y + (size_t)row * Q;
+      for (long q0 = threadIdx.x; q0 < Q; q0 += FT * FU) {
+        double va[FU], vb[FU];
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+          const long q = q0 + (long)FT * u < Q ? q0 + (long)FT * u : Q - 1;
+          va[u] = xa[q];
+          vb[u] = xb[q];
+        }
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+          const long q = q0 + (long)FT * u;
+          if (q < Q) ys[q] = minus ? va[u] - vb[u] : va[u] + vb[u];
+        }
+      }
+    }
+  } else {
+    for (long p = blockIdx.x; p < P; p += gridDim.x) {
+      const double* __restrict__ xp = x + (size_t)p * n;
+      double* __restrict__ yp = y + (size_t)p * n;
+      for (int s0 = threadIdx.x; s0 < n; s0 += FT * FU) {
+        double v[FU];
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+          const int s = s0 + FT * u < n ? s0 + FT * u : n - 1;
+          int a, b;
+          bool minus;
+          src(s, a, b, minus);
+          const double xa = xp[a], xb = xp[b];
+          v[u] = minus ? xa - xb : xa + xb;
+        }
+#pragma unroll
+        for (int u = 0; u < FU; ++u)
+          if (s0 + FT * u < n) yp[s0 + FT * u] = v[u];
+      }
+    }
+  }
 }
 
 }  // namespace f64k
@@ -425,6 +491,16 @@ hipError_t launch_mode_f64_part(const double* x, double* y, const double* g, int
         break;
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_f64(const double* x, double* y, long P, int n, long Q, int nrep, int per, hipStream_t stream) {
+  using namespace f64k;
+  if (P <= 0 || Q <= 0 || n <= 0) return hipSuccess;
+  if (nrep < 1 || nrep > n || 2 * nrep < n || x == y) return hipErrorInvalidValue;
+  const long rows = Q > 1 ? P * n : P;
+  const long grid = rows < 16384 ? rows : 16384;
+  fold_f64_kernel<<<dim3((unsigned)grid), dim3(FT), 0, stream>>>(x, y, P, n, Q, nrep, per);
   return hipGetLastError();
 }
 

@@ -547,32 +547,45 @@ sem_status lp_tune(sem_plan* p, const LpWork& w) {
 }
 
 // FP64 FD application on the reflection-split transforms (the plan's folded
-// blocks), two launches per mode product:
-//  - forward (z, y, x): each block reads the unfolded axis as v+ = x_r + x_R(r)
-//    (symmetric modes) or v- = x_r - x_R(r) (antisymmetric modes) for the nrep
-//    representatives r, and writes its modes, in folded order ([symmetric |
+// blocks), two launches per mode product.  The antisymmetric blocks use only the
+// nodd representatives that are not their own reflection (r = j + off, off = 1
+// on periodic axes, whose node 0 is fixed; the fixed node of an odd
+// non-periodic axis is the last representative), whose v- is not identically 0:
+//  - z forward: the blocks read the unfolded z rows as v+ = x_r + x_R(r) or
+//    v- = x_r - x_R(r) in their loads;
+//  - y and x forward: a compact fold pass ([v+ of the nrep representatives |
+//    v- of the nodd others], n rows) feeds plain block products;
+//  - the forward blocks write the modes in folded order ([symmetric |
 //    antisymmetric]), so the x product's multiplier reads the folded eigenvalues;
 //  - backward (x, y, z): the symmetric block stores e_r at node r, the
 //    antisymmetric block reads it back and stores u_r = e_r + o_r and
-//    u_R(r) = e_r - o_r.
-// Buffers: f -> tmp -> u -> tmp -> u -> tmp -> u (tmp: N doubles; u may alias f,
-// which is read by the first product only).
+//    u_R(r) = e_r - o_r (at a fixed node e_r stays).
+// Buffers: f -> tmp -> u -> tmp -> u -> tmp -> u -> tmp -> u (tmp: N doubles; u
+// may alias f, which the first product alone reads).
 hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, double* tmp) {
   const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
   const int r[3] = {p->ax[0].nrep, p->ax[1].nrep, p->ax[2].nrep};
   const int o[3] = {p->ax[0].nodd, p->ax[1].nodd, p->ax[2].nodd};
   const int n[3] = {nx, ny, nz};
-  const long PZ = (long)nx * ny, QY = nz, PY = nx, QX = (long)ny * nz;
-  EpiArgs plus[3], minus[3], unfold[3];
+  int per[3], off[3];
   for (int a = 0; a < 3; ++a) {
-    const int per = p->bc[a] == SEM_BC_PERIODIC ? 1 : 0;
-    plus[a].fold = 1;
-    minus[a].fold = 2;
-    plus[a].rn = minus[a].rn = unfold[a].rn = n[a];
-    plus[a].rper = minus[a].rper = unfold[a].rper = per;
+    per[a] = p->bc[a] == SEM_BC_PERIODIC ? 1 : 0;
+    off[a] = per[a];
   }
+  const long PZ = (long)nx * ny, QY = nz, PY = nx, QX = (long)ny * nz;
   EpiArgs none;
-  EpiArgs mul = plus[0];
+  EpiArgs plus_z, minus_z, unfold[3];
+  plus_z.fold = 1;
+  minus_z.fold = 2;
+  plus_z.rn = minus_z.rn = nz;
+  plus_z.rper = minus_z.rper = per[2];
+  minus_z.roff = off[2];
+  for (int a = 0; a < 3; ++a) {
+    unfold[a].rn = n[a];
+    unfold[a].rper = per[a];
+    unfold[a].roff = off[a];
+  }
+  EpiArgs mul;
   mul.lx = p->d_lamf64[0];
   mul.ly = p->d_lamf64[1];
   mul.lz = p->d_lamf64[2];
@@ -583,37 +596,44 @@ hipError_t fd64(sem_plan* p, const Spectral& sp, const double* f, double* u, dou
   mul.param = sp.param;
   mul.nz = nz;
   EpiArgs mul_anti = mul;
-  mul_anti.fold = 2;
   mul_anti.lx = p->d_lamf64[0] + r[0];
   const int epi = sp.kind ? EPI_SPECTRAL : EPI_DIVIDE;
+  // antisymmetric blocks: forward factors start at row off (representative
+  // off), backward factors at column off
+  const double* gfa[3];
+  const double* gba[3];
+  for (int a = 0; a < 3; ++a) {
+    gfa[a] = p->d_gff[a][1] + (size_t)off[a] * p->fld[a];
+    gba[a] = p->d_gbf[a][1] + off[a];
+  }
   hipStream_t s = p->stream;
   hipError_t e;
 #define SEMFD_TRY(x) \
   if ((e = (x)) != hipSuccess) return e
-  // z forward (NT shape, rows (x, y)): f -> tmp (z modes)
-  SEMFD_TRY(launch_mode_f64_part(f, tmp, p->d_gff[2][0], p->fld[2], PZ, r[2], r[2], 1, nz, nz, EPI_STORE, plus[2], s));
-  SEMFD_TRY(launch_mode_f64_part(f, tmp + r[2], p->d_gff[2][1], p->fld[2], PZ, r[2], o[2], 1, nz, nz, EPI_STORE,
-                                 minus[2], s));
-  // y forward (batched over x, inner z modes): tmp -> u
-  SEMFD_TRY(launch_mode_f64_part(tmp, u, p->d_gff[1][0], p->fld[1], PY, r[1], r[1], QY, ny, ny, EPI_STORE, plus[1], s));
-  SEMFD_TRY(launch_mode_f64_part(tmp, u + (size_t)r[1] * QY, p->d_gff[1][1], p->fld[1], PY, r[1], o[1], QY, ny, ny,
-                                 EPI_STORE, minus[1], s));
-  // x forward with the multiplier: u -> tmp
+  // z forward (NT shape, rows (x, y)), folding in the loads: f -> tmp (z modes)
+  SEMFD_TRY(launch_mode_f64_part(f, tmp, p->d_gff[2][0], p->fld[2], PZ, r[2], r[2], 1, nz, nz, EPI_STORE, plus_z, s));
+  SEMFD_TRY(launch_mode_f64_part(f, tmp + r[2], gfa[2], p->fld[2], PZ, o[2], o[2], 1, nz, nz, EPI_STORE, minus_z, s));
+  // y: fold tmp -> u, forward (batched over x, inner z modes) u -> tmp
+  SEMFD_TRY(launch_fold_f64(tmp, u, PY, ny, QY, r[1], per[1], s));
+  SEMFD_TRY(launch_mode_f64_part(u, tmp, p->d_gff[1][0], p->fld[1], PY, r[1], r[1], QY, ny, ny, EPI_STORE, none, s));
+  SEMFD_TRY(launch_mode_f64_part(u + (size_t)r[1] * QY, tmp + (size_t)r[1] * QY, gfa[1], p->fld[1], PY, o[1], o[1], QY,
+                                 ny, ny, EPI_STORE, none, s));
+  // x: fold tmp -> u, forward with the multiplier u -> tmp
+  SEMFD_TRY(launch_fold_f64(tmp, u, 1, nx, QX, r[0], per[0], s));
   SEMFD_TRY(launch_mode_f64_part(u, tmp, p->d_gff[0][0], p->fld[0], 1, r[0], r[0], QX, nx, nx, epi, mul, s));
-  SEMFD_TRY(launch_mode_f64_part(u, tmp + (size_t)r[0] * QX, p->d_gff[0][1], p->fld[0], 1, r[0], o[0], QX, nx, nx,
-                                 epi, mul_anti, s));
+  SEMFD_TRY(launch_mode_f64_part(u + (size_t)r[0] * QX, tmp + (size_t)r[0] * QX, gfa[0], p->fld[0], 1, o[0], o[0], QX,
+                                 nx, nx, epi, mul_anti, s));
   // x backward: tmp (x modes) -> u (x nodes)
   SEMFD_TRY(launch_mode_f64_part(tmp, u, p->d_gbf[0][0], p->fld[0], 1, r[0], r[0], QX, nx, nx, EPI_STORE, none, s));
-  SEMFD_TRY(launch_mode_f64_part(tmp + (size_t)r[0] * QX, u, p->d_gbf[0][1], p->fld[0], 1, o[0], r[0], QX, nx, nx,
-                                 EPI_UNFOLD, unfold[0], s));
+  SEMFD_TRY(launch_mode_f64_part(tmp + (size_t)r[0] * QX, u, gba[0], p->fld[0], 1, o[0], o[0], QX, nx, nx, EPI_UNFOLD,
+                                 unfold[0], s));
   // y backward: u -> tmp
   SEMFD_TRY(launch_mode_f64_part(u, tmp, p->d_gbf[1][0], p->fld[1], PY, r[1], r[1], QY, ny, ny, EPI_STORE, none, s));
-  SEMFD_TRY(launch_mode_f64_part(u + (size_t)r[1] * QY, tmp, p->d_gbf[1][1], p->fld[1], PY, o[1], r[1], QY, ny, ny,
-                                 EPI_UNFOLD, unfold[1], s));
+  SEMFD_TRY(launch_mode_f64_part(u + (size_t)r[1] * QY, tmp, gba[1], p->fld[1], PY, o[1], o[1], QY, ny, ny, EPI_UNFOLD,
+                                 unfold[1], s));
   // z backward: tmp -> u
   SEMFD_TRY(launch_mode_f64_part(tmp, u, p->d_gbf[2][0], p->fld[2], PZ, r[2], r[2], 1, nz, nz, EPI_STORE, none, s));
-  SEMFD_TRY(launch_mode_f64_part(tmp + r[2], u, p->d_gbf[2][1], p->fld[2], PZ, o[2], r[2], 1, nz, nz, EPI_UNFOLD,
-                                 unfold[2], s));
+  SEMFD_TRY(launch_mode_f64_part(tmp + r[2], u, gba[2], p->fld[2], PZ, o[2], o[2], 1, nz, nz, EPI_UNFOLD, unfold[2], s));
 #undef SEMFD_TRY
   return hipSuccess;
 }

@@ -66,15 +66,18 @@ static hipError_t upload_vec(const std::vector<double>& v, double** dst) {
 }
 
 // Reflection-split FP64 factors of axis a in the G[m][l] = A[l][m] layout of the
-// FP64 kernels, zero-padded to fld x fld (fld = nrep rounded up to 128): forward
-// blocks A = (symmetric or antisymmetric modes) x representatives, backward blocks
-// A = representatives x (modes of the block); and the folded eigenvalues.
+// FP64 kernels, fld columns (nrep rounded up to 128) and fld + 128 zero-padded
+// rows, so that a block read at a row or column offset of one (the antisymmetric
+// blocks skip the representatives that are their own reflection) keeps whole
+// tiles inside: forward blocks A = (symmetric or antisymmetric modes) x
+// representatives, backward blocks A = representatives x (modes of the block);
+// and the folded eigenvalues.
 static hipError_t upload_fold_factors(sem_plan* p, int a) {
   const semfd::AxisData& ax = p->ax[a];
   const int nr = ax.nrep, no = ax.nodd, ld = ((nr + 127) / 128) * 128;
   p->fld[a] = ld;
   std::vector<double> g[4];
-  for (auto& v : g) v.assign((size_t)ld * ld, 0.0);
+  for (auto& v : g) v.assign((size_t)(ld + 128) * ld, 0.0);
   for (int l = 0; l < nr; ++l)
     for (int m = 0; m < nr; ++m) g[0][(size_t)m * ld + l] = ax.ffold[(size_t)l * nr + m];
   for (int j = 0; j < no; ++j)
