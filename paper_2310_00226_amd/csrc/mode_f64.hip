@@ -357,29 +357,24 @@ __global__ __launch_bounds__(NT_THREADS, 2) void mode_nt_f64(const double* __res
     }
 }
 
-// Compact reflection fold (see launch_fold_f64): blocks stride over rows, (p, s)
-// when Q > 1 (threads over q), p when Q == 1 (threads over s); output row s < nrep
-// is v+ of representative s, row nrep + j is v- of representative j + off.
+// Compact reflection fold (see launch_fold_f64): blocks stride over the
+// representatives, (p, r) when Q > 1 (threads over q), p when Q == 1 (threads over
+// r); each reads x_r and x_R(r) once and writes v+ to row r and, unless r is its
+// own reflection, v- to row nrep + r - off.
 constexpr int FT = 256, FU = 4;
 __global__ __launch_bounds__(FT) void fold_f64_kernel(const double* __restrict__ x, double* __restrict__ y, long P,
                                                       int n, long Q, int nrep, int per) {
   const int off = per ? 1 : 0;
-  auto src = [&](int s, int& a, int& b, bool& minus) {  // output row s <- rows a +- b
-    minus = s >= nrep;
-    a = minus ? s - nrep + off : s;
-    b = reflect_node(a, n, per);
-  };
   if (Q > 1) {
-    const long rows = P * n;
+    const long rows = P * nrep;
     for (long row = blockIdx.x; row < rows; row += gridDim.x) {
-      const long p = row / n;
-      const int s = (int)(row - p * n);
-      int a, b;
-      bool minus;
-      src(s, a, b, minus);
-      const double* __restrict__ xa = x + (size_t)(p * n + a) * Q;
-      const double* __restrict__ xb = x + (size_t)(p * n + b) * Q;
-      double* __restrict__ ys = y + (size_t)row * Q;
+      const long p = row / nrep;
+      const int r = (int)(row - p * nrep), m = reflect_node(r, n, per);
+      const double* __restrict__ xa = x + (size_t)(p * n + r) * Q;
+      const double* __restrict__ xb = x + (size_t)(p * n + m) * Q;
+      double* __restrict__ yp = y + (size_t)(p * n + r) * Q;
+      double* __restrict__ ym = y + (size_t)(p * n + nrep + r - off) * Q;
+      const bool minus = m != r;  // uniform over the block
       for (long q0 = threadIdx.x; q0 < Q; q0 += FT * FU) {
         double va[FU], vb[FU];
 #pragma unroll
@@ -391,7 +386,10 @@ __global__ __launch_bounds__(FT) void fold_f64_kernel(const double* __restrict__
 #pragma unroll
         for (int u = 0; u < FU; ++u) {
           const long q = q0 + (long)FT * u;
-          if (q < Q) ys[q] = minus ? va[u] - vb[u] : va[u] + vb[u];
+          if (q < Q) {
+            yp[q] = va[u] + vb[u];
+            if (minus) ym[q] = va[u] - vb[u];
+          }
         }
       }
     }
@@ -399,20 +397,21 @@ __global__ __launch_bounds__(FT) void fold_f64_kernel(const double* __restrict__
     for (long p = blockIdx.x; p < P; p += gridDim.x) {
       const double* __restrict__ xp = x + (size_t)p * n;
       double* __restrict__ yp = y + (size_t)p * n;
-      for (int s0 = threadIdx.x; s0 < n; s0 += FT * FU) {
-        double v[FU];
+      for (int r0 = threadIdx.x; r0 < nrep; r0 += FT * FU) {
+        double va[FU], vb[FU];
 #pragma unroll
         for (int u = 0; u < FU; ++u) {
-          const int s = s0 + FT * u < n ? s0 + FT * u : n - 1;
-          int a, b;
-          bool minus;
-          src(s, a, b, minus);
-          const double xa = xp[a], xb = xp[b];
-          v[u] = minus ? xa - xb : xa + xb;
+          const int r = r0 + FT * u < nrep ? r0 + FT * u : nrep - 1;
+          va[u] = xp[r];
+          vb[u] = xp[reflect_node(r, n, per)];
         }
 #pragma unroll
-        for (int u = 0; u < FU; ++u)
-          if (s0 + FT * u < n) yp[s0 + FT * u] = v[u];
+        for (int u = 0; u < FU; ++u) {
+          const int r = r0 + FT * u;
+          if (r >= nrep) continue;
+          yp[r] = va[u] + vb[u];
+          if (reflect_node(r, n, per) != r) yp[nrep + r - off] = va[u] - vb[u];
+        }
       }
     }
   }
@@ -498,7 +497,7 @@ hipError_t launch_fold_f64(const double* x, double* y, long P, int n, long Q, in
   using namespace f64k;
   if (P <= 0 || Q <= 0 || n <= 0) return hipSuccess;
   if (nrep < 1 || nrep > n || 2 * nrep < n || x == y) return hipErrorInvalidValue;
-  const long rows = Q > 1 ? P * n : P;
+  const long rows = Q > 1 ? P * nrep : P;
   const long grid = rows < 16384 ? rows : 16384;
   fold_f64_kernel<<<dim3((unsigned)grid), dim3(FT), 0, stream>>>(x, y, P, n, Q, nrep, per);
   return hipGetLastError();
