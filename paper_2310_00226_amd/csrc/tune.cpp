@@ -14,6 +14,8 @@
 #include <sstream>
 #include <string>
 
+#include <unistd.h>
+
 namespace semfd {
 namespace {
 
@@ -63,7 +65,9 @@ void load_locked() {
 void save_locked() {
   const char* path = cache_path();
   if (!path) return;
-  const std::string tmp = std::string(path) + ".tmp";
+  // a temporary file of this process, renamed over the cache in one step, so a
+  // reader (or another process saving at the same time) never sees a partial file
+  const std::string tmp = std::string(path) + ".tmp." + std::to_string((long)getpid());
   {
     std::ofstream out(tmp, std::ios::trunc);
     if (!out) return;
