@@ -110,6 +110,64 @@ __global__ __launch_bounds__(DOT_THREADS) void pcg_update(double* __restrict__ u
   if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXDOT] = t;
 }
 
+// The same update for a reflection-split BF16 preconditioner, which also writes
+// the new r folded along z and rounded to BF16 (hi, and lo = r - hi when split),
+// the input of the preconditioner's first pass: v+ = r_z + r_R(z) at column z,
+// v- = r_z - r_R(z) at fpad + z for the nrep representatives z (the sums in FP64,
+// then FP32, then BF16, as the conversion kernel of the FD application does),
+// zeros in the rest of the row of pitch 2 fpad.  A thread takes a representative
+// and its reflection (once for a fixed node).
+template <int NS>
+__global__ __launch_bounds__(DOT_THREADS) void pcg_update_fold(double* __restrict__ u, double* __restrict__ r,
+                                                               const double* __restrict__ p,
+                                                               const double* __restrict__ q, double a,
+                                                               const double* __restrict__ mx,
+                                                               const double* __restrict__ my,
+                                                               const double* __restrict__ mz, int nx, int ny, int nz,
+                                                               double* __restrict__ partial,
+                                                               unsigned short* __restrict__ o, long plane_o, int nrep,
+                                                               int fpad, int per) {
+  __shared__ double sh[DOT_THREADS / 64];
+  double s = 0.0;
+  const long rows = (long)nx * ny;
+  for (long row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int i = (int)(row / ny), j = (int)(row - (long)i * ny);
+    const double mr = mx[i] * my[j];
+    const size_t base = (size_t)row * nz;
+    unsigned short* __restrict__ orow = o + (size_t)row * 2 * fpad;
+    for (int zr = threadIdx.x; zr < fpad; zr += DOT_THREADS) {
+      double vp = 0.0, vm = 0.0;
+      if (zr < nrep) {
+        const int zm = per ? (nz - zr) % nz : nz - 1 - zr;
+        const size_t g0 = base + zr, g1 = base + zm;
+        u[g0] += a * p[g0];
+        const double r0 = r[g0] - a * q[g0];
+        r[g0] = r0;
+        s += mr * mz[zr] * r0 * r0;
+        double r1 = r0;
+        if (zm != zr) {
+          u[g1] += a * p[g1];
+          r1 = r[g1] - a * q[g1];
+          r[g1] = r1;
+          s += mr * mz[zm] * r1 * r1;
+        }
+        vp = r0 + r1;
+        vm = r0 - r1;
+      }
+      const float fp = (float)vp, fm = (float)vm;
+      const __bf16 hp = (__bf16)fp, hm = (__bf16)fm;
+      orow[zr] = __builtin_bit_cast(unsigned short, hp);
+      orow[fpad + zr] = __builtin_bit_cast(unsigned short, hm);
+      if (NS == 2) {
+        orow[plane_o + zr] = __builtin_bit_cast(unsigned short, (__bf16)(fp - (float)hp));
+        orow[plane_o + fpad + zr] = __builtin_bit_cast(unsigned short, (__bf16)(fm - (float)hm));
+      }
+    }
+  }
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.x * MAXDOT] = t;
+}
+
 // Fixed-order sum of the block partials: out[d] = sum_b partial[b][d].
 __global__ __launch_bounds__(DOT_THREADS) void mdot_final(const double* __restrict__ partial, int nblocks, int ndot,
                                                           double* __restrict__ out) {
@@ -264,6 +322,16 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
     sem_status st = lp_prepare(p, prec, &lw);
     if (st != SEM_OK) return st;
   }
+  // BF16 modes: after the first application (from r = f), the update writes the
+  // folded BF16 r itself and the application starts at its first pass
+  FoldAxis fz;
+  bool fold_update = false;
+  if (prec == SEM_BF16 || prec == SEM_BF16X3) {
+    FoldAxis fa[3];
+    lp_fold_axes(p, fa);
+    fz = fa[2];
+    fold_update = lp_fold_pitch_z(p) == 2 * fz.pad;
+  }
   auto precondition = [&]() -> hipError_t {
     return prec == SEM_F64 ? fd64(p, sp, w.r, w.z, tmp64) : lp_fd(p, lw, sp, w.r, w.z, 1, nullptr);
   };
@@ -323,8 +391,21 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
     if (!(pq > 0.0) || !(rz > 0.0))
       return set_error(SEM_ENOCONV, "sem_pcg_solve: operator or preconditioner not positive definite");
     const double a = rz / pq;
-    pcg_update<<<nb, DOT_THREADS, 0, p->stream>>>(u, w.r, w.p, w.q, a, p->d_mass[0], p->d_mass[1], p->d_mass[2],
-                                                   p->dims[0], p->dims[1], p->dims[2], w.partial);
+    if (fold_update) {
+      // the update also writes the preconditioner's folded BF16 input
+      if (prec == SEM_BF16X3)
+        pcg_update_fold<2><<<nb, DOT_THREADS, 0, p->stream>>>(
+            u, w.r, w.p, w.q, a, p->d_mass[0], p->d_mass[1], p->d_mass[2], p->dims[0], p->dims[1], p->dims[2],
+            w.partial, (unsigned short*)lw.t1, lw.tplane, fz.nrep, fz.pad, fz.per);
+      else
+        pcg_update_fold<1><<<nb, DOT_THREADS, 0, p->stream>>>(
+            u, w.r, w.p, w.q, a, p->d_mass[0], p->d_mass[1], p->d_mass[2], p->dims[0], p->dims[1], p->dims[2],
+            w.partial, (unsigned short*)lw.t1, lw.tplane, fz.nrep, fz.pad, fz.per);
+      lw.input_in_t1 = true;
+    } else {
+      pcg_update<<<nb, DOT_THREADS, 0, p->stream>>>(u, w.r, w.p, w.q, a, p->d_mass[0], p->d_mass[1], p->d_mass[2],
+                                                     p->dims[0], p->dims[1], p->dims[2], w.partial);
+    }
     mdot_final<<<1, DOT_THREADS, 0, p->stream>>>(w.partial, nb, 1, w.out);
     if ((e = hipGetLastError()) != hipSuccess ||
         (e = hipMemcpyAsync(h, w.out, sizeof(double), hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||

@@ -79,7 +79,16 @@ struct LpWork {
   unsigned long long* norms = nullptr;  // 2 x FP64 bit patterns
   int rkind = 1, ldr = 0;   // ResidualArgs.r_kind and row pitch of r
   long rplane = 0, tplane = 0;
+  // BF16 modes: t1 already holds the folded input of the first pass (written by
+  // the caller's own kernel), so the application skips its conversion
+  bool input_in_t1 = false;
 };
+struct FoldAxis;
+// Geometry of the reflection split along axis a (representatives, their count
+// rounded up to 32, periodic flag) and the row pitch of the z-folded BF16 input
+// of the first pass.
+void lp_fold_axes(const sem_plan* p, FoldAxis fa[3]);
+int lp_fold_pitch_z(const sem_plan* p);
 sem_status lp_prepare(sem_plan* p, sem_prec prec, LpWork* w, bool tune = true);
 sem_status lp_tune(sem_plan* p, const LpWork& w);
 sem_status lp_factors(sem_plan* p, sem_prec prec);

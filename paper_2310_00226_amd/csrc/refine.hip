@@ -278,6 +278,9 @@ static void fold_axes(const sem_plan* p, FoldAxis fa[3]) {
   }
 }
 
+void lp_fold_axes(const sem_plan* p, FoldAxis fa[3]) { fold_axes(p, fa); }
+int lp_fold_pitch_z(const sem_plan* p) { return fold_pitch(p, 2); }
+
 // Pass s (0..5) of the reflection-split sequence: t1 -> t0 -> t1 -> t0 -> t1 -> t0 -> t1.
 static LpPass folded_pass(sem_plan* p, const LpWork& w, const Spectral& sp, int s) {
   const int nx = p->dims[0], ny = p->dims[1], nz = p->dims[2];
@@ -357,7 +360,9 @@ static hipError_t lp_fd_folded(sem_plan* p, const LpWork& w, const Spectral& sp,
   fold_axes(p, fa);
   hipError_t e;
   // folded right-hand side into t1
-  if (f64_src)
+  if (w.input_in_t1)
+    e = hipSuccess;
+  else if (f64_src)
     e = launch_to_lowp(f64_src, w.t1, w.tplane, split, p->dims, fold_pitch(p, 2), &fa[2], p->stream);
   else
     e = launch_fold_lowp(w.r, w.rplane, w.ldr, w.t1, w.tplane, fold_pitch(p, 2), split, p->dims, fa[2], p->stream);
