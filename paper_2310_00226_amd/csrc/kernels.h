@@ -179,10 +179,22 @@ hipError_t launch_to_lowp(const double* f, void* out, long plane_o, int split, c
 // BF16 (split) rows of pitch ldi -> the same rows folded along z, pitch ldo.
 hipError_t launch_fold_lowp(const void* in, long plane_i, int ldi, void* out, long plane_o, int ldo, int split,
                             const int dims[3], const FoldAxis& fold, hipStream_t stream);
+// Weighted inner products an unfold with first = 1 forms as it writes u: per-block
+// partial sums of <r, u>_M and <u, q>_M (mass weight mx_i my_j mz_l of node (i, j, l))
+// into partial[2 b] and partial[2 b + 1], b < blocks (the grid of such a launch).
+struct UnfoldDot {
+  const double* r = nullptr;
+  const double* q = nullptr;
+  const double *mx = nullptr, *my = nullptr, *mz = nullptr;
+  double* partial = nullptr;
+  int blocks = 0;
+};
 // u (+)= the correction d (FP32, every axis in folded node form: e rows then o
-// rows, pitch ldd for z''), see unfold_accum_kernel.
+// rows, pitch ldd for z''), see unfold_accum_kernel; dot (first = 1 only): also
+// the partial sums of UnfoldDot.
 hipError_t launch_unfold_accum(const float* d, int ldd, double* u, const int dims[3], const FoldAxis fold[3],
-                               int first, unsigned long long* norms, hipStream_t stream);
+                               int first, unsigned long long* norms, hipStream_t stream,
+                               const UnfoldDot* dot = nullptr);
 
 // Generalised nodal residual  r = cf f - cd d - ch (H_x + H_y + H_z) v  with banded
 // H rows hb[a][g * (2k+1) + d] = H_a(g, g - k + d), FP64 arithmetic.

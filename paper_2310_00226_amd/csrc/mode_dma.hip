@@ -656,13 +656,15 @@ struct UnfoldAxis {
 };
 __device__ __forceinline__ int refl_node(int r, const UnfoldAxis& a) { return a.per ? (a.n - r) % a.n : a.n - 1 - r; }
 
+template <bool DOT>
 __global__ __launch_bounds__(256) void unfold_accum_kernel(const float* __restrict__ d, int ldd, double* __restrict__ u,
                                                            UnfoldAxis ax, UnfoldAxis ay, UnfoldAxis az, int first,
-                                                           unsigned long long* __restrict__ norms) {
+                                                           unsigned long long* __restrict__ norms, UnfoldDot dot) {
   // blocks stride over the orbit rows (x_r, y_r), threads over z_r; one atomic
   // pair per block for the norms
   __shared__ double red[2][4];
   double dmax = 0.0, umax = 0.0;
+  double s0 = 0.0, s1 = 0.0;  // DOT: <r, u>_M and <u, q>_M of this thread's nodes
   const long rows = (long)ax.nrep * ay.nrep;
   const int ny2 = 2 * ay.nrep;
   for (long row = blockIdx.x; row < rows; row += gridDim.x) {
@@ -700,12 +702,35 @@ __global__ __launch_bounds__(256) void unfold_accum_kernel(const float* __restri
             const size_t gi = ((size_t)xs[sx] * ay.n + ys[sy]) * az.n + zs[sz];
             const double un = (first ? 0.0 : u[gi]) + dv;
             u[gi] = un;
+            if constexpr (DOT) {
+              const double m = dot.mx[xs[sx]] * dot.my[ys[sy]] * dot.mz[zs[sz]];
+              s0 += m * dot.r[gi] * un;
+              s1 += m * un * dot.q[gi];
+            }
             // a NaN / Inf turns the norm into +Inf (fmax alone would drop NaN)
             dmax = fabs(dv) <= DBL_MAX ? fmax(dmax, fabs(dv)) : INFINITY;
             umax = fabs(un) <= DBL_MAX ? fmax(umax, fabs(un)) : INFINITY;
           }
         }
       }
+    }
+  }
+  if constexpr (DOT) {  // fixed-order block sums (waves, then the 4 wave sums)
+#pragma unroll
+    for (int s2 = 32; s2 >= 1; s2 >>= 1) {
+      s0 += __shfl_xor(s0, s2);
+      s1 += __shfl_xor(s1, s2);
+    }
+    __shared__ double dsum[2][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+      dsum[0][wave] = s0;
+      dsum[1][wave] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      dot.partial[2 * (size_t)blockIdx.x] = dsum[0][0] + dsum[0][1] + dsum[0][2] + dsum[0][3];
+      dot.partial[2 * (size_t)blockIdx.x + 1] = dsum[1][0] + dsum[1][1] + dsum[1][2] + dsum[1][3];
     }
   }
   if (norms) {
@@ -872,14 +897,23 @@ hipError_t launch_fold_lowp(const void* in, long plane_i, int ldi, void* out, lo
 }
 
 hipError_t launch_unfold_accum(const float* d, int ldd, double* u, const int dims[3], const FoldAxis fold[3],
-                               int first, unsigned long long* norms, hipStream_t stream) {
+                               int first, unsigned long long* norms, hipStream_t stream, const UnfoldDot* dot) {
   if (ldd < 2 * fold[2].nrep) return hipErrorInvalidValue;
   const dmak::UnfoldAxis ax{dims[0], fold[0].nrep, fold[0].per}, ay{dims[1], fold[1].nrep, fold[1].per},
       az{dims[2], fold[2].nrep, fold[2].per};
   const long rows = (long)fold[0].nrep * fold[1].nrep;
+  if (dot) {
+    if (!first || !dot->r || !dot->q || !dot->mx || !dot->my || !dot->mz || !dot->partial || dot->blocks < 1 ||
+        dot->blocks != std::min<long>(rows, dot->blocks))
+      return hipErrorInvalidValue;
+    dmak::unfold_accum_kernel<true><<<dim3((unsigned)dot->blocks), dim3(256), 0, stream>>>(d, ldd, u, ax, ay, az, first,
+                                                                                       norms, *dot);
+    return hipGetLastError();
+  }
   const unsigned grid = (unsigned)std::min<long>(rows, 8192);
   if (grid == 0) return hipSuccess;
-  dmak::unfold_accum_kernel<<<dim3(grid), dim3(256), 0, stream>>>(d, ldd, u, ax, ay, az, first, norms);
+  dmak::unfold_accum_kernel<false><<<dim3(grid), dim3(256), 0, stream>>>(d, ldd, u, ax, ay, az, first, norms,
+                                                                         UnfoldDot());
   return hipGetLastError();
 }
 

@@ -324,13 +324,22 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
   }
   // BF16 modes: after the first application (from r = f), the update writes the
   // folded BF16 r itself and the application starts at its first pass
+  // and the unfold into z forms <r, z>_M and <z, q>_M as it writes z
   FoldAxis fz;
   bool fold_update = false;
+  UnfoldDot ud;
   if (prec == SEM_BF16 || prec == SEM_BF16X3) {
     FoldAxis fa[3];
     lp_fold_axes(p, fa);
     fz = fa[2];
     fold_update = lp_fold_pitch_z(p) == 2 * fz.pad;
+    ud.r = w.r;
+    ud.q = w.q;
+    ud.mx = p->d_mass[0];
+    ud.my = p->d_mass[1];
+    ud.mz = p->d_mass[2];
+    ud.partial = w.partial;
+    ud.blocks = (int)std::min<long>((long)fa[0].nrep * fa[1].nrep, DOT_BLOCKS);
   }
   auto precondition = [&]() -> hipError_t {
     return prec == SEM_F64 ? fd64(p, sp, w.r, w.z, tmp64) : lp_fd(p, lw, sp, w.r, w.z, 1, nullptr);
@@ -402,6 +411,7 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
             u, w.r, w.p, w.q, a, p->d_mass[0], p->d_mass[1], p->d_mass[2], p->dims[0], p->dims[1], p->dims[2],
             w.partial, (unsigned short*)lw.t1, lw.tplane, fz.nrep, fz.pad, fz.per);
       lw.input_in_t1 = true;
+      lw.unfold_dot = &ud;
     } else {
       pcg_update<<<nb, DOT_THREADS, 0, p->stream>>>(u, w.r, w.p, w.q, a, p->d_mass[0], p->d_mass[1], p->d_mass[2],
                                                      p->dims[0], p->dims[1], p->dims[2], w.partial);
@@ -424,7 +434,15 @@ sem_status sem_pcg_solve(sem_plan* p, const double* v, double shift, sem_prec pr
       b = h[0] / rz;
       rz = h[0];
     } else {
-      if ((e = mdot(p, w, 2, w.r, w.z, w.z, w.q, h)) != hipSuccess) return hip_fail(e, "sem_pcg_solve: dot");
+      if (lw.unfold_dot) {  // partials from the preconditioner's unfold
+        mdot_final<<<1, DOT_THREADS, 0, p->stream>>>(w.partial, ud.blocks, 2, w.out);
+        if ((e = hipGetLastError()) != hipSuccess ||
+            (e = hipMemcpyAsync(h, w.out, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(p->stream)) != hipSuccess)
+          return hip_fail(e, "sem_pcg_solve: dot");
+      } else if ((e = mdot(p, w, 2, w.r, w.z, w.z, w.q, h)) != hipSuccess) {
+        return hip_fail(e, "sem_pcg_solve: dot");
+      }
       b = -a * h[1] / rz;
       rz = h[0];
     }

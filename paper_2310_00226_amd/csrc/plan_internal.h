@@ -70,6 +70,8 @@ struct Spectral {
   int kind = 0;
   double param = 0.0;
 };
+struct FoldAxis;
+struct UnfoldDot;
 // Buffers of the low-precision solves inside the plan workspace.
 struct LpWork {
   sem_prec prec = SEM_F32;
@@ -82,8 +84,9 @@ struct LpWork {
   // BF16 modes: t1 already holds the folded input of the first pass (written by
   // the caller's own kernel), so the application skips its conversion
   bool input_in_t1 = false;
+  // BF16 modes, first = 1: the unfold also forms these inner products
+  const UnfoldDot* unfold_dot = nullptr;
 };
-struct FoldAxis;
 // Geometry of the reflection split along axis a (representatives, their count
 // rounded up to 32, periodic flag) and the row pitch of the z-folded BF16 input
 // of the first pass.

@@ -372,7 +372,7 @@ static hipError_t lp_fd_folded(sem_plan* p, const LpWork& w, const Spectral& sp,
     if (!dma_supported(ps)) return hipErrorInvalidValue;
     if ((e = launch_mode_dma(ps, p->stream)) != hipSuccess) return e;
   }
-  return launch_unfold_accum((const float*)w.t1, dpitch(p), u, p->dims, fa, first, norms, p->stream);
+  return launch_unfold_accum((const float*)w.t1, dpitch(p), u, p->dims, fa, first, norms, p->stream, w.unfold_dot);
 }
 
 // Pass s (0..5) of the FP32 sequence  src -> t0 -> t1 -> t0 -> t1 -> t0 -> u.
