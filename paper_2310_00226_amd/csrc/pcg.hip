@@ -12,7 +12,9 @@
 // per-node weight alpha + V, which for k <= 8 also sums <p, q> per block); u += a p
 // and r -= a q fused with <r, r>;
 // z = P^{-1} r (an FP64 FD solve, or a low-precision one); <r, z> (and <z, q>);
-// p = z + b p.  The weighted inner products are two-stage block reductions
+// p = z + b p.  With a BF16 preconditioner (reflection-split passes) the update
+// also writes the new r folded along z in BF16, the input of the preconditioner's
+// first pass, and the preconditioner's unfold into z forms <r, z> and <z, q>.  The weighted inner products are two-stage block reductions
 // (fixed block count, partial sums added in a fixed order: deterministic); the
 // mass weight of node (i, j, l) is Mx_i My_j Mz_l from the three 1D masses.
 //
