@@ -656,13 +656,15 @@ struct UnfoldAxis {
 };
 __device__ __forceinline__ int refl_node(int r, const UnfoldAxis& a) { return a.per ? (a.n - r) % a.n : a.n - 1 - r; }
 
+constexpr int UNFOLD_THREADS = 512;  // one pass over nrep_z <= 512 representatives per row
 template <bool DOT>
-__global__ __launch_bounds__(256) void unfold_accum_kernel(const float* __restrict__ d, int ldd, double* __restrict__ u,
+__global__ __launch_bounds__(UNFOLD_THREADS) void unfold_accum_kernel(const float* __restrict__ d, int ldd, double* __restrict__ u,
                                                            UnfoldAxis ax, UnfoldAxis ay, UnfoldAxis az, int first,
                                                            unsigned long long* __restrict__ norms, UnfoldDot dot) {
   // blocks stride over the orbit rows (x_r, y_r), threads over z_r; one atomic
   // pair per block for the norms
-  __shared__ double red[2][4];
+  constexpr int NW = UNFOLD_THREADS / 64;
+  __shared__ double red[2][NW];
   double dmax = 0.0, umax = 0.0;
   double s0 = 0.0, s1 = 0.0;  // DOT: <r, u>_M and <u, q>_M of this thread's nodes
   const long rows = (long)ax.nrep * ay.nrep;
@@ -670,7 +672,7 @@ __global__ __launch_bounds__(256) void unfold_accum_kernel(const float* __restri
   for (long row = blockIdx.x; row < rows; row += gridDim.x) {
     const int xr = (int)(row / ay.nrep), yr = (int)(row - (long)xr * ay.nrep);
     const int xs[2] = {xr, refl_node(xr, ax)}, ys[2] = {yr, refl_node(yr, ay)};
-    for (int zr = threadIdx.x; zr < az.nrep; zr += 256) {
+    for (int zr = threadIdx.x; zr < az.nrep; zr += UNFOLD_THREADS) {
       float v[2][2][2];
 #pragma unroll
       for (int ex = 0; ex < 2; ++ex)
@@ -721,7 +723,7 @@ __global__ __launch_bounds__(256) void unfold_accum_kernel(const float* __restri
       s0 += __shfl_xor(s0, s2);
       s1 += __shfl_xor(s1, s2);
     }
-    __shared__ double dsum[2][4];
+    __shared__ double dsum[2][NW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
       dsum[0][wave] = s0;
@@ -729,8 +731,13 @@ __global__ __launch_bounds__(256) void unfold_accum_kernel(const float* __restri
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      dot.partial[2 * (size_t)blockIdx.x] = dsum[0][0] + dsum[0][1] + dsum[0][2] + dsum[0][3];
-      dot.partial[2 * (size_t)blockIdx.x + 1] = dsum[1][0] + dsum[1][1] + dsum[1][2] + dsum[1][3];
+      double t0 = 0.0, t1 = 0.0;
+      for (int w2 = 0; w2 < NW; ++w2) {
+        t0 += dsum[0][w2];
+        t1 += dsum[1][w2];
+      }
+      dot.partial[2 * (size_t)blockIdx.x] = t0;
+      dot.partial[2 * (size_t)blockIdx.x + 1] = t1;
     }
   }
   if (norms) {
@@ -746,7 +753,7 @@ __global__ __launch_bounds__(256) void unfold_accum_kernel(const float* __restri
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      for (int w = 1; w < 4; ++w) {
+      for (int w = 1; w < NW; ++w) {
         dmax = fmax(dmax, red[0][w]);
         umax = fmax(umax, red[1][w]);
       }
@@ -906,13 +913,13 @@ hipError_t launch_unfold_accum(const float* d, int ldd, double* u, const int dim
     if (!first || !dot->r || !dot->q || !dot->mx || !dot->my || !dot->mz || !dot->partial || dot->blocks < 1 ||
         dot->blocks != std::min<long>(rows, dot->blocks))
       return hipErrorInvalidValue;
-    dmak::unfold_accum_kernel<true><<<dim3((unsigned)dot->blocks), dim3(256), 0, stream>>>(d, ldd, u, ax, ay, az, first,
+    dmak::unfold_accum_kernel<true><<<dim3((unsigned)dot->blocks), dim3(dmak::UNFOLD_THREADS), 0, stream>>>(d, ldd, u, ax, ay, az, first,
                                                                                        norms, *dot);
     return hipGetLastError();
   }
   const unsigned grid = (unsigned)std::min<long>(rows, 8192);
   if (grid == 0) return hipSuccess;
-  dmak::unfold_accum_kernel<false><<<dim3(grid), dim3(256), 0, stream>>>(d, ldd, u, ax, ay, az, first, norms,
+  dmak::unfold_accum_kernel<false><<<dim3(grid), dim3(dmak::UNFOLD_THREADS), 0, stream>>>(d, ldd, u, ax, ay, az, first, norms,
                                                                          UnfoldDot());
   return hipGetLastError();
 }
