@@ -257,7 +257,7 @@ PROFILED_TRAFFIC = {
     "f64": {"fetch_bytes": 20.70e9, "write_bytes": 8.17e9, "algorithmic_bytes": 15.97e9,
             "mfma_flops_counted": 2.112e12, "mfma_busy": 0.836, "source": "profiles/mode_f64_n999.md"},
     # one split-BF16 FD application (conversion, six passes, unfold)
-    "bf16x3": {"fetch_bytes": 43.4e9, "write_bytes": 36.8e9, "source": "profiles/split_bf16_refined_n999.md"},
+    "bf16x3": {"fetch_bytes": 43.5e9, "write_bytes": 36.7e9, "source": "profiles/split_bf16_refined_n999.md"},
 }
 
 # The kernel whose launch the headline roofline times, per low-precision variant.
@@ -270,8 +270,8 @@ KERNEL_NAME = {
 # above; MFMA ops = SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512; busy = SQ_VALU_MFMA_BUSY_CYCLES
 # / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs)).  Variants without such runs: null.
 PROFILED_KERNEL = {
-    "bf16x3": {"fetch_bytes": 5.18e9, "write_bytes": 4.09e9, "algorithmic_bytes": 7.98e9,
-               "mfma_flops_counted": 4.291e12, "mfma_busy": 0.549, "clock_ghz": 1.88,
+    "bf16x3": {"fetch_bytes": 5.22e9, "write_bytes": 4.09e9, "algorithmic_bytes": 7.98e9,
+               "mfma_flops_counted": 4.291e12, "mfma_busy": 0.557, "clock_ghz": 1.92,
                "source": "profiles/split_bf16_refined_n999.md"},
 }
 
