@@ -656,14 +656,15 @@ struct UnfoldAxis {
 };
 __device__ __forceinline__ int refl_node(int r, const UnfoldAxis& a) { return a.per ? (a.n - r) % a.n : a.n - 1 - r; }
 
-constexpr int UNFOLD_THREADS = 512;  // one pass over nrep_z <= 512 representatives per row
-template <bool DOT>
-__global__ __launch_bounds__(UNFOLD_THREADS) void unfold_accum_kernel(const float* __restrict__ d, int ldd, double* __restrict__ u,
+// NT threads per block (128, 256 or 512): the launch takes the smallest that
+// covers a row's nrep_z representatives in one pass (or 512)
+template <int NT, bool DOT>
+__global__ __launch_bounds__(NT) void unfold_accum_kernel(const float* __restrict__ d, int ldd, double* __restrict__ u,
                                                            UnfoldAxis ax, UnfoldAxis ay, UnfoldAxis az, int first,
                                                            unsigned long long* __restrict__ norms, UnfoldDot dot) {
   // blocks stride over the orbit rows (x_r, y_r), threads over z_r; one atomic
   // pair per block for the norms
-  constexpr int NW = UNFOLD_THREADS / 64;
+  constexpr int NW = NT / 64;
   __shared__ double red[2][NW];
   double dmax = 0.0, umax = 0.0;
   double s0 = 0.0, s1 = 0.0;  // DOT: <r, u>_M and <u, q>_M of this thread's nodes
@@ -672,7 +673,7 @@ __global__ __launch_bounds__(UNFOLD_THREADS) void unfold_accum_kernel(const floa
   for (long row = blockIdx.x; row < rows; row += gridDim.x) {
     const int xr = (int)(row / ay.nrep), yr = (int)(row - (long)xr * ay.nrep);
     const int xs[2] = {xr, refl_node(xr, ax)}, ys[2] = {yr, refl_node(yr, ay)};
-    for (int zr = threadIdx.x; zr < az.nrep; zr += UNFOLD_THREADS) {
+    for (int zr = threadIdx.x; zr < az.nrep; zr += NT) {
       float v[2][2][2];
 #pragma unroll
       for (int ex = 0; ex < 2; ++ex)
@@ -717,7 +718,7 @@ __global__ __launch_bounds__(UNFOLD_THREADS) void unfold_accum_kernel(const floa
       }
     }
   }
-  if constexpr (DOT) {  // fixed-order block sums (waves, then the 4 wave sums)
+  if constexpr (DOT) {  // fixed-order block sums (waves, then the NW wave sums)
 #pragma unroll
     for (int s2 = 32; s2 >= 1; s2 >>= 1) {
       s0 += __shfl_xor(s0, s2);
@@ -903,25 +904,34 @@ hipError_t launch_fold_lowp(const void* in, long plane_i, int ldi, void* out, lo
   return hipGetLastError();
 }
 
+template <int NT>
+static hipError_t unfold_launch(const float* d, int ldd, double* u, const dmak::UnfoldAxis& ax,
+                                const dmak::UnfoldAxis& ay, const dmak::UnfoldAxis& az, int first,
+                                unsigned long long* norms, hipStream_t stream, const UnfoldDot* dot, long rows) {
+  if (dot) {
+    dmak::unfold_accum_kernel<NT, true><<<dim3((unsigned)dot->blocks), dim3(NT), 0, stream>>>(d, ldd, u, ax, ay, az,
+                                                                                           first, norms, *dot);
+    return hipGetLastError();
+  }
+  const unsigned grid = (unsigned)std::min<long>(rows, 8192);
+  if (grid == 0) return hipSuccess;
+  dmak::unfold_accum_kernel<NT, false><<<dim3(grid), dim3(NT), 0, stream>>>(d, ldd, u, ax, ay, az, first, norms,
+                                                                            UnfoldDot());
+  return hipGetLastError();
+}
+
 hipError_t launch_unfold_accum(const float* d, int ldd, double* u, const int dims[3], const FoldAxis fold[3],
                                int first, unsigned long long* norms, hipStream_t stream, const UnfoldDot* dot) {
   if (ldd < 2 * fold[2].nrep) return hipErrorInvalidValue;
   const dmak::UnfoldAxis ax{dims[0], fold[0].nrep, fold[0].per}, ay{dims[1], fold[1].nrep, fold[1].per},
       az{dims[2], fold[2].nrep, fold[2].per};
   const long rows = (long)fold[0].nrep * fold[1].nrep;
-  if (dot) {
-    if (!first || !dot->r || !dot->q || !dot->mx || !dot->my || !dot->mz || !dot->partial || dot->blocks < 1 ||
-        dot->blocks != std::min<long>(rows, dot->blocks))
-      return hipErrorInvalidValue;
-    dmak::unfold_accum_kernel<true><<<dim3((unsigned)dot->blocks), dim3(dmak::UNFOLD_THREADS), 0, stream>>>(d, ldd, u, ax, ay, az, first,
-                                                                                       norms, *dot);
-    return hipGetLastError();
-  }
-  const unsigned grid = (unsigned)std::min<long>(rows, 8192);
-  if (grid == 0) return hipSuccess;
-  dmak::unfold_accum_kernel<false><<<dim3(grid), dim3(dmak::UNFOLD_THREADS), 0, stream>>>(d, ldd, u, ax, ay, az, first, norms,
-                                                                         UnfoldDot());
-  return hipGetLastError();
+  if (dot && (!first || !dot->r || !dot->q || !dot->mx || !dot->my || !dot->mz || !dot->partial || dot->blocks < 1 ||
+              dot->blocks != std::min<long>(rows, dot->blocks)))
+    return hipErrorInvalidValue;
+  if (az.nrep > 256) return unfold_launch<512>(d, ldd, u, ax, ay, az, first, norms, stream, dot, rows);
+  if (az.nrep > 128) return unfold_launch<256>(d, ldd, u, ax, ay, az, first, norms, stream, dot, rows);
+  return unfold_launch<128>(d, ldd, u, ax, ay, az, first, norms, stream, dot, rows);
 }
 
 }  // namespace semfd
