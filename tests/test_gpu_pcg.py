@@ -43,14 +43,17 @@ def _dev(torch, a):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("case", ["neumann-q5", "dirichlet-q3"])
+@pytest.mark.parametrize("case", ["neumann-q5", "dirichlet-q3", "dirichlet-q4-long-z"])
 def test_pcg_matches_oracle(torch, P, prec, case):
     if case == "neumann-q5":  # the paper's problem: its V (beta = 10) and exact solution
         k, ne, bc, box, alpha, beta = 5, (6, 7, 5), "neumann", SCHRODINGER_BOX, 1.0, 10.0
         prob = O.Problem(k, ne, box, alpha, bc)
         v, _, f = schrodinger_data(*(o.x for o in prob.axes), alpha, beta)
     else:  # a general positive potential and right-hand side, several tiles and ragged tails
-        k, ne, bc, box, alpha, beta = 3, (30, 22, 27), "dirichlet", (-1.0, 2.0, 0.0, 1.5, -0.5, 0.5), 0.5, 40.0
+        if case == "dirichlet-q3":
+            k, ne, bc, box, alpha, beta = 3, (30, 22, 27), "dirichlet", (-1.0, 2.0, 0.0, 1.5, -0.5, 0.5), 0.5, 40.0
+        else:  # n = (15, 19, 359): 180 representatives per z row (the 256-thread unfold with its inner products)
+            k, ne, bc, box, alpha, beta = 4, (4, 5, 90), "dirichlet", (0.0, 1.0, 0.0, 1.2, 0.0, 20.0), 1.0, 5.0
         prob = O.Problem(k, ne, box, alpha, bc)
         rng = np.random.default_rng(41)
         v = rng.uniform(0.0, beta, size=prob.shape)

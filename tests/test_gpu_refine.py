@@ -53,6 +53,9 @@ CASES = [
     (2, (2, 2, 1), (-1, 1, -1, 1, -1, 1), 1.0, "dirichlet", "noise"),
     (1, (200, 3, 1), (0, 1, 0, 1, 0, 1), 1.0, "neumann", "noise"),
     (6, (3, 20, 17), (0, 1, 0, 5, -1, 1), 3.0, "neumann", "noise"),
+    # long z rows: 161 and 351 representatives per row (the 256- and 512-thread unfolds)
+    (2, (5, 4, 160), (0, 1, 0, 1, 0, 8), 1.0, "neumann", "noise"),
+    (1, (3, 2, 700), (0, 1, 0, 1, 0, 20), 1.0, "dirichlet", "noise"),
 ]
 
 
